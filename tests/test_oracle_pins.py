@@ -1,0 +1,395 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a closed
+form, a brute-force computation written differently, a library routine the
+operation reduces to, an invariant, or a planted structure with a known
+answer. The tests are chosen so that a plausible slip (a dropped term, a
+wrong sign or index, a transposed axis, a wrong source level) fails one.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import oracle as O
+from gen import phantoms as P
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+
+
+def rnd(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+# ------------------------------------------------------------------ P1 taps
+@pytest.mark.parametrize("sigma", [0.95, 1.2263, 1.6, 1.9466, 3.09])
+def test_taps_sum_symmetry_and_shape(sigma):
+    w = O.gauss_taps(sigma, 3.0)
+    r = (len(w) - 1) // 2
+    assert r == math.ceil(3.0 * sigma)
+    assert abs(w.sum() - 1.0) <= 1e-15
+    assert np.array_equal(w, w[::-1])
+    # ratio to the centre tap is the Gaussian density ratio
+    t = np.arange(-r, r + 1)
+    np.testing.assert_allclose(w / w[r], np.exp(-t * t / (2 * sigma * sigma)), rtol=1e-14)
+    # variance of a +/-3 sigma truncated normal is 0.9733 sigma^2
+    var = float((w * t * t).sum())
+    assert 0.96 * sigma ** 2 < var < 1.0 * sigma ** 2
+
+
+def test_zero_sigma_is_identity():
+    assert np.array_equal(O.gauss_taps(0.0), np.array([1.0]))
+    v = rnd((5, 6, 7), 1)
+    assert np.array_equal(O.blur(v, 0.0), v)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_blur_axis_equals_scipy_correlate_nearest(axis):
+    v = rnd((9, 11, 13), 2)
+    w = O.gauss_taps(1.5)
+    ref = ndi.correlate1d(v, w, axis=2 - axis, mode="nearest")
+    np.testing.assert_allclose(O.blur_axis(v, w, axis), ref, rtol=0, atol=1e-13)
+
+
+def test_impulse_response_is_outer_product():
+    n = 31
+    v = np.zeros((n, n, n))
+    v[15, 15, 15] = 1.0
+    sigma = 2.0
+    w = O.gauss_taps(sigma)
+    r = (len(w) - 1) // 2
+    out = O.blur(v, sigma)
+    ref = np.zeros_like(v)
+    ref[15 - r:15 + r + 1, 15 - r:15 + r + 1, 15 - r:15 + r + 1] = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-17)
+
+
+def test_constant_volume_unchanged_everywhere():
+    p = O.Params(n_octaves=3, min_dim=8)
+    v = np.full((40, 36, 44), 0.37)
+    octs = O.pyramid(v, p)
+    assert len(octs) == 3
+    for oc in octs:
+        for g in oc.G:
+            np.testing.assert_allclose(g, 0.37, rtol=0, atol=1e-15)
+        for d in oc.D:
+            assert np.abs(d).max() <= 1e-15
+    assert len(O.detect([oc.D for oc in octs], p)) == 0
+
+
+# ------------------------------------------------------------------ P2 brute force
+def test_separable_equals_bruteforce_3d_convolution():
+    v = rnd((16, 16, 16), 3)
+    sigma = 1.2263
+    w = O.gauss_taps(sigma)
+    r = (len(w) - 1) // 2
+    n = 16
+    idx = np.arange(n)
+    ref = np.zeros_like(v)
+    for k in range(-r, r + 1):
+        zk = np.clip(idx + k, 0, n - 1)
+        for j in range(-r, r + 1):
+            yj = np.clip(idx + j, 0, n - 1)
+            for i in range(-r, r + 1):
+                xi = np.clip(idx + i, 0, n - 1)
+                ref += w[i + r] * w[j + r] * w[k + r] * v[np.ix_(zk, yj, xi)]
+    np.testing.assert_allclose(O.blur(v, sigma), ref, rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------------ P3 sub-sampling
+def test_subsample_ramp_constant_and_odd_dims():
+    nz, ny, nx = 9, 8, 11
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ramp = 3.0 * x - 2.0 * y + 0.5 * z + 1.0
+    out = O.subsample(ramp)
+    assert out.shape == (4, 4, 5)
+    Z, Y, X = np.meshgrid(np.arange(4), np.arange(4), np.arange(5), indexing="ij")
+    np.testing.assert_array_equal(out, 3.0 * (2 * X + 0.5) - 2.0 * (2 * Y + 0.5) + 0.5 * (2 * Z + 0.5) + 1.0)
+    np.testing.assert_array_equal(O.subsample(np.full((5, 5, 5), 2.5)), np.full((2, 2, 2), 2.5))
+    v = rnd((8, 6, 10), 4)
+    ref = v.reshape(4, 2, 3, 2, 5, 2).mean(axis=(1, 3, 5))
+    np.testing.assert_allclose(O.subsample(v), ref, rtol=0, atol=1e-15)
+    assert GOLD["subsample_inputs_per_output"]["value"] == 8
+
+
+# ------------------------------------------------------------------ P4 sum of signs
+def _brute_extremum(dm, d0, dp, x, y, z):
+    v = d0[z, y, x]
+    nb = np.concatenate([dm[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2].ravel(),
+                         np.delete(d0[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2].ravel(), 13),
+                         dp[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2].ravel()])
+    assert len(nb) == GOLD["neighbours_per_extremum_test"]["value"]
+    return bool(np.all(v > nb)), bool(np.all(v < nb)), int(np.sign(v - nb).sum())
+
+
+def test_sum_of_signs_matches_bruteforce_with_ties():
+    rng = np.random.default_rng(5)
+    for trial in range(6):
+        # quantised values make ties common
+        dm, d0, dp = (np.round(rng.standard_normal((6, 7, 8)) * (2 if trial % 2 else 50)) for _ in range(3))
+        # plant one strict maximum and one tied maximum
+        d0[2, 3, 3] = 1000.0
+        d0[3, 3, 5] = 1000.0
+        dm[3, 3, 5] = 1000.0  # tie with the neighbour below: not strict
+        rows = O.detect_triple(dm, d0, dp, 0.0, 80)
+        got = {(int(r[0]), int(r[1]), int(r[2])): int(r[3]) for r in rows}
+        want = {}
+        for z in range(1, 5):
+            for y in range(1, 6):
+                for x in range(1, 7):
+                    mx, mn, f = _brute_extremum(dm, d0, dp, x, y, z)
+                    assert O.sum_of_signs(dm, d0, dp, x, y, z) == f
+                    assert (f == GOLD["peak_sum_of_signs"]["value"]) == mx
+                    assert (f == GOLD["valley_sum_of_signs"]["value"]) == mn
+                    if (mx or mn) and abs(d0[z, y, x]) > 0.0:
+                        want[(x, y, z)] = 1 if mx else -1
+        assert got == want
+        assert got.get((3, 3, 2)) == 1
+        assert (5, 3, 3) not in got
+
+
+def test_relaxed_votes_and_threshold():
+    rng = np.random.default_rng(6)
+    dm, d0, dp = (rng.standard_normal((7, 7, 7)) for _ in range(3))
+    for votes in (60, 78):
+        rows = O.detect_triple(dm, d0, dp, 0.5, votes)
+        got = {(int(r[0]), int(r[1]), int(r[2])) for r in rows}
+        want = set()
+        for z in range(1, 6):
+            for y in range(1, 6):
+                for x in range(1, 6):
+                    _, _, f = _brute_extremum(dm, d0, dp, x, y, z)
+                    if abs(d0[z, y, x]) > 0.5 and abs(f) >= votes:
+                        want.add((x, y, z))
+        assert got == want
+
+
+# ------------------------------------------------------------------ schedule
+def test_level_schedule_closed_form():
+    p = O.Params()
+    base, inc = O.level_increments(p)
+    assert base == pytest.approx(1.6)
+    assert len(inc) == p.scales + 2
+    tot = base ** 2
+    for i, s in enumerate(inc, start=1):
+        tot += s * s
+        assert math.sqrt(tot) == pytest.approx(1.6 * 2 ** (i / 3), rel=1e-14)
+    # tap radii of the hot path: 5 for the base blur, then 4, 5, 6, 8, 10
+    assert [math.ceil(3 * s) for s in [base] + inc] == [5, 4, 5, 6, 8, 10]
+    assert [O.siftrank_radius(p, s) for s in (1, 2, 3)] == [5, 6, 7]
+
+
+def test_octave_dims():
+    p = O.Params()
+    assert O.octave_dims((145, 174, 145), p) == [(145, 174, 145), (72, 87, 72), (36, 43, 36), (18, 21, 18)]
+    assert O.octave_dims((64, 64, 64), O.Params(n_octaves=2)) == [(64, 64, 64), (32, 32, 32)]
+    assert len(O.octave_dims((512, 512, 384), p)) == 5
+    assert O.octave_dims((15, 40, 40), p) == []
+
+
+# ------------------------------------------------------------------ P5 planted blobs
+def _blob(n, c, s, a=1.0):
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    return a * np.exp(-((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2) / (2 * s * s))
+
+
+@pytest.mark.parametrize("sb,o,s", [(2.8, 0, 1), (3.5, 0, 2), (4.4, 0, 3), (5.5, 1, 1), (7.0, 1, 2), (8.8, 1, 3)])
+@pytest.mark.parametrize("amp", [1.0, -0.5])
+def test_planted_blob_recovered_at_centre_and_scale(sb, o, s, amp):
+    # the continuous DoG maximiser of a Gaussian blob is sigma* = 0.7267 sigma_b
+    # for kappa = 2^(1/3); sigma_b in the interior of a scale bin picks that bin.
+    p = O.Params(n_octaves=2, min_dim=8)
+    n = 96 if o == 1 else 64
+    c = (n // 2) * 1.0 + (0.5 if o == 1 else 0.0)   # a voxel centre of octave o
+    v = _blob(n, c, sb, amp)
+    octs = O.pyramid(v, p)
+    k = O.detect([oc.D for oc in octs], p)
+    hit = k[(np.abs(k["xf"] - c) < 1) & (np.abs(k["yf"] - c) < 1) & (np.abs(k["zf"] - c) < 1)]
+    assert len(hit) == 1
+    h = hit[0]
+    assert (int(h["octave"]), int(h["scale"])) == (o, s)
+    assert int(h["polarity"]) == (1 if amp > 0 else -1)
+    assert abs(float(h["dog"])) == pytest.approx(0.127 * abs(amp), rel=0.03)
+    assert float(h["sigma"]) / sb == pytest.approx(0.7267, rel=0.2)
+
+
+def test_blob_below_smallest_detectable_scale_not_found():
+    p = O.Params(n_octaves=2, min_dim=8)
+    octs = O.pyramid(_blob(64, 32.0, 2.0), p)
+    k = O.detect([oc.D for oc in octs], p)
+    assert not np.any((k["x"] == 32) & (k["y"] == 32) & (k["z"] == 32) & (k["octave"] == 0))
+
+
+# ------------------------------------------------------------------ descriptors, closed forms
+def _ramp(n, axis, a=1.0):
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    return a * (x, y, z)[axis].astype(np.float64)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("a", [0.7, -1.3])
+def test_siftrank_histogram_of_a_ramp(axis, a):
+    R = 5
+    G = _ramp(24, axis, a)
+    hist, rk = O.siftrank(G, np.array([[12, 12, 12]]), R)
+    bo = (1 << axis) if a > 0 else 0
+    want = np.zeros(64)
+    for bs in range(8):
+        want[8 * bs + bo] = abs(a) * (R + 0.5) ** 3
+    np.testing.assert_allclose(hist[0], want, rtol=1e-13, atol=1e-12)
+    assert sorted(rk[0].tolist()) == list(range(64))
+
+
+def test_siftrank_spatial_bins_of_abs_profile():
+    # G = |x - 12|: gradient -1 on the left (bin 0), +1 on the right (bin 1),
+    # 0 on the centre plane; left samples land in spatial bx = 0, right in bx = 1
+    n, R = 24, 4
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    G = np.abs(x - 12.0)
+    hist, _ = O.siftrank(G, np.array([[12, 12, 12]]), R)
+    want = np.zeros(64)
+    half = (R + 0.5) ** 2 * R  # R planes per side, (R+0.5)^2 weight per plane per (by, bz) half
+    for by in range(2):
+        for bz in range(2):
+            want[8 * (0 + 2 * by + 4 * bz) + 0] = half
+            want[8 * (1 + 2 * by + 4 * bz) + 1] = half
+    np.testing.assert_allclose(hist[0], want, rtol=1e-13, atol=1e-12)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_brief_on_a_ramp_is_offset_difference(axis):
+    # a Gaussian blur leaves a linear function unchanged away from the edges,
+    # so d_i = B(p1) - B(p2) = a (o1 - o2) along the ramp axis
+    G = _ramp(40, axis, 0.5)
+    draws = P.pair_draws(1, 256)
+    p = O.Params()
+    off = O.pair_offsets(draws, p, 1)
+    assert np.abs(off).max() <= 12
+    wb = O.gauss_taps(0.95)
+    d, bits, rk = O.brief_rrief(G, np.array([[20, 20, 20]]), off, wb)
+    want = 0.5 * (off[:, 0, axis] - off[:, 1, axis]).astype(np.float64)
+    np.testing.assert_allclose(d[0], want, rtol=0, atol=1e-12)
+    for i in range(256):
+        assert bool((int(bits[0, i // 64]) >> (i % 64)) & 1) == (want[i] > 0)
+    assert sorted(rk[0].tolist()) == list(range(256))
+
+
+def test_brief_special_cases():
+    G = rnd((20, 20, 20), 7)
+    off = np.zeros((64, 2, 3), dtype=np.int32)
+    off[:, 0] = np.random.default_rng(8).integers(-4, 5, (64, 3))
+    off[:, 1] = off[:, 0]
+    d, bits, rk = O.brief_rrief(G, np.array([[10, 10, 10]]), off, O.gauss_taps(0.95))
+    assert np.all(d == 0.0) and np.all(bits == 0)
+    assert rk[0].tolist() == list(range(64))     # ties broken by index
+    # sigma_b = 0: B(p) is the sample itself
+    off2 = np.array([[[1, 0, 0], [0, -2, 3]]], dtype=np.int32)
+    d2, _, _ = O.brief_rrief(G, np.array([[10, 10, 10]]), off2, np.array([1.0]))
+    assert d2[0, 0] == G[10, 10, 11] - G[13, 8, 10]
+    # sample points clamp at the volume edge
+    d3, _, _ = O.brief_rrief(G, np.array([[0, 19, 1]]), np.array([[[-5, 4, 0], [0, 0, -9]]], dtype=np.int32),
+                             np.array([1.0]))
+    assert d3[0, 0] == G[1, 19, 0] - G[0, 19, 0]
+
+
+def test_pair_offsets_follow_method_3():
+    # p1 ~ N(0, sigma), p2 ~ N(p1, sigma): var(p1) = sigma^2, var(p2) = 2 sigma^2,
+    # corr(p1, p2) = 1/sqrt(2); a method-2 slip (independent p2) gives corr 0
+    p = O.Params(brief_n=60000)
+    draws = P.pair_draws(99, 60000)
+    off = O.pair_offsets(draws, p, 3).astype(np.float64)
+    sig = O.scale_sigma(p, 3)
+    assert sig == pytest.approx(3.2)
+    a, b = off[:, 0].ravel(), off[:, 1].ravel()
+    assert np.var(a) / sig ** 2 == pytest.approx(1.0 + 1.0 / (12 * sig ** 2), rel=0.03)
+    assert np.var(b) / sig ** 2 == pytest.approx(2.0 + 1.0 / (12 * sig ** 2), rel=0.03)
+    assert np.corrcoef(a, b)[0, 1] == pytest.approx(1 / math.sqrt(2), abs=0.01)
+    assert abs(a.mean()) < 0.05 and abs(b.mean()) < 0.05
+    assert np.all(off == np.floor(off))
+
+
+def test_rank_is_stable_permutation():
+    v = np.array([3.0, 1.0, 3.0, -2.0, 1.0])
+    assert O.rank(v).tolist() == [3, 1, 4, 0, 2]
+    assert GOLD["siftrank_length"]["value"] == 2 * 2 * 2 * GOLD["siftrank_orientation_bins"]["value"]
+    assert 64 <= 2 ** GOLD["siftrank_bits_per_element"]["value"]
+
+
+# ------------------------------------------------------------------ P6-P10 invariants
+@pytest.fixture(scope="module")
+def small_case():
+    p = O.Params(n_octaves=2, min_dim=8)
+    v = P.noise_blob_volume((48, 40, 44), 11, n_blobs=14, margin=8).astype(np.float64)
+    draws = P.pair_draws(5, 256)
+    octs, k, desc = O.extract(v, p, draws)
+    assert len(k) > 10
+    return p, v, draws, octs, k, desc
+
+
+def _key(k):
+    return [(int(r["octave"]), int(r["scale"]), int(r["z"]), int(r["y"]), int(r["x"])) for r in k]
+
+
+def test_canonical_order_and_ranks_are_permutations(small_case):
+    p, v, draws, octs, k, desc = small_case
+    keys = _key(k)
+    assert keys == sorted(keys)
+    assert np.all(np.sort(desc["siftrank"], axis=1) == np.arange(64))
+    assert np.all(np.sort(desc["rrief"].astype(int), axis=1) == np.arange(256))
+
+
+def test_offset_invariance(small_case):
+    p, v, draws, octs, k, desc = small_case
+    _, k2, d2 = O.extract(v + 0.25, p, draws)
+    assert _key(k2) == _key(k)
+    assert np.array_equal(d2["siftrank"], desc["siftrank"])
+    np.testing.assert_allclose(d2["diff"], desc["diff"], rtol=0, atol=1e-12)
+
+
+def test_scaling_invariance(small_case):
+    p, v, draws, octs, k, desc = small_case
+    p2 = O.Params(**{**p.__dict__, "dog_threshold": 2 * p.dog_threshold})
+    _, k2, d2 = O.extract(2.0 * v, p2, draws)
+    assert _key(k2) == _key(k)
+    for f in ("siftrank", "brief", "rrief"):
+        assert np.array_equal(d2[f], desc[f])
+
+
+def test_negation_swaps_peaks_and_valleys(small_case):
+    p, v, draws, octs, k, desc = small_case
+    _, k2, d2 = O.extract(-v, p, draws)
+    assert _key(k2) == _key(k)
+    assert np.array_equal(k2["polarity"], -k["polarity"])
+    assert np.array_equal(d2["diff"], -desc["diff"])
+    nz = desc["diff"] != 0
+    for kk in range(len(k)):
+        for i in range(256):
+            b1 = (int(desc["brief"][kk, i // 64]) >> (i % 64)) & 1
+            b2 = (int(d2["brief"][kk, i // 64]) >> (i % 64)) & 1
+            if nz[kk, i]:
+                assert b1 != b2
+    dd = desc["diff"]
+    untied = np.array([len(np.unique(row)) == len(row) for row in dd])
+    assert np.array_equal(d2["rrief"][untied].astype(int), 255 - desc["rrief"][untied].astype(int))
+    # SIFT-Rank: orientation bin bo -> 7 - bo for every non-zero gradient component
+    perm = np.array([8 * (e // 8) + 7 - (e % 8) for e in range(64)])
+    np.testing.assert_allclose(d2["hist"], desc["hist"][:, perm], rtol=1e-12, atol=1e-14)
+
+
+def test_x_mirror(small_case):
+    p, v, draws, octs, k, desc = small_case
+    assert v.shape[2] % 4 == 0
+    _, k2, d2 = O.extract(v[:, :, ::-1].copy(), p, draws)
+    m = {}
+    for i, r in enumerate(k2):
+        nx_o = v.shape[2] >> int(r["octave"])
+        m[(int(r["octave"]), int(r["scale"]), int(r["z"]), int(r["y"]), nx_o - 1 - int(r["x"]))] = i
+    keys = _key(k)
+    assert set(m) == set(keys)
+    # spatial bx flips and orientation bit 0 flips
+    perm = np.array([8 * ((e // 8) ^ 1) + ((e % 8) ^ 1) for e in range(64)])
+    for i, key in enumerate(keys):
+        np.testing.assert_allclose(d2["hist"][m[key]], desc["hist"][i][perm], rtol=1e-11, atol=1e-13)
