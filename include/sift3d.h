@@ -1,0 +1,206 @@
+/*
+ * sift3d.h -- C ABI of the MI355X (gfx950) 3D SIFT-Rank hot path.
+ *
+ * Method: Carluer et al., "GPU optimization of the 3D Scale-invariant
+ * Feature Transform Algorithm and a Novel BRIEF-inspired 3D Fast
+ * Descriptor" (arXiv 2112.10258). The problem statement (Section 3.1):
+ * a scalar volume I_x goes to keypoints (sigma_i, x_i) found as 4D extrema
+ * of a difference-of-Gaussian scale space, each described by a vector f_i.
+ *
+ * Conventions
+ *   - Volumes are float32, layout [z][y][x] with x fastest, dims (nx,ny,nz).
+ *   - All device pointers (prefix d_) are HIP device memory owned by the
+ *     caller. The library owns only its host handles and one small device
+ *     table per context (pair offsets), freed by sift3d_destroy.
+ *   - `stream` is a hipStream_t (NULL = the null stream). Every call that
+ *     takes a stream only enqueues work on it and returns without waiting;
+ *     no call synchronises the device, so a whole sift3d_extract can be
+ *     captured into a HIP graph. Inputs must stay alive until the stream
+ *     work completes.
+ *   - Functions return SIFT3D_OK (0) or a negative SIFT3D_E_* code; they
+ *     never abort. On SIFT3D_E_HIP, sift3d_last_hip_error() gives the
+ *     hipError_t of the failing call on this thread.
+ *   - Octave o has dims floor(dims_{o-1} / 2). Each octave holds S+3
+ *     Gaussian levels G_0..G_{S+2} and S+2 DoG levels D_0..D_{S+1}.
+ */
+#ifndef SIFT3D_H
+#define SIFT3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SIFT3D_OK = 0,
+    SIFT3D_E_ARG = -1,        /* null pointer, bad parameter or size       */
+    SIFT3D_E_TOO_SMALL = -2,  /* volume gives no octave (min dim < min_dim) */
+    SIFT3D_E_WORKSPACE = -3,  /* workspace smaller than the plan needs      */
+    SIFT3D_E_HIP = -5,        /* a HIP runtime call failed                  */
+    SIFT3D_E_UNSUPPORTED = -6 /* parameter outside what the kernels support */
+};
+
+/* Method parameters. sift3d_default_params() fills the defaults in []. */
+typedef struct sift3d_params {
+    int n_octaves;          /* [0] 0 = keep octave o while min(dims_o) >= min_dim;
+                               >0 = at most this many octaves                    */
+    int min_dim;            /* [16] smallest dimension an octave may have (>= 4) */
+    int scales;             /* [3] S, detection scales per octave, 1..5          */
+    double sigma0;          /* [1.6] blur of G_0 in its octave's voxels          */
+    double sigma_in;        /* [0.0] blur already present in the input           */
+    double trunc;           /* [3.0] tap radius r = ceil(trunc * sigma), r <= 16 */
+    float dog_threshold;    /* [0.01] keypoints need |D| > dog_threshold         */
+    int votes;              /* [80] sum-of-signs acceptance |f| >= votes, 1..80  */
+    int brief_n;            /* [256] BRIEF/RRIEF pairs, multiple of 64, <= 256   */
+    double brief_blur;      /* [0.95] patch pre-blur sigma_b (0 = none), <= 2.0  */
+    double siftrank_factor; /* [2.0] SIFT-Rank half-width R = ceil(f * sigma_s), R <= 7 */
+} sift3d_params;
+
+/*
+ * One keypoint (40 bytes). (x, y, z) are voxel coordinates in octave
+ * `octave`, `scale` is the DoG level s (1..S) it is an extremum of,
+ * polarity is +1 for a peak and -1 for a valley, `dog` is D_s at the
+ * voxel. (xf, yf, zf) is the position in input voxels,
+ * 2^o * x + (2^o - 1) / 2, and sigma = sigma0 * 2^(s/S) * 2^o.
+ */
+typedef struct sift3d_keypoint {
+    int32_t x, y, z;
+    int16_t octave, scale;
+    int8_t polarity;
+    int8_t pad[3];
+    float dog, xf, yf, zf, sigma;
+} sift3d_keypoint;
+
+typedef struct sift3d_ctx sift3d_ctx;
+typedef struct sift3d_plan sift3d_plan;
+
+/* Fill *p with the defaults listed above. */
+int sift3d_default_params(sift3d_params *p);
+
+/*
+ * Create a context on the current HIP device.
+ * pair_draws: host array [n_draws][2][3] of standard-normal draws (z1, z2)
+ * for the BRIEF/RRIEF point pairs (Section 3.2.3, method 3: p1 ~ N(0, sigma),
+ * p2 ~ N(p1, sigma)); pair i uses u1 = z1, u2 = z1 + z2 and, at scale s,
+ * the integer offsets floor(sigma_s * u + 0.5) with sigma_s = sigma0 2^(s/S).
+ * n_draws >= brief_n. May be NULL only if brief_n == 0. The draws are
+ * copied; the offset tables are uploaded synchronously to device memory
+ * that the context owns.
+ */
+int sift3d_create(const sift3d_params *p, const double *pair_draws, int n_draws, sift3d_ctx **out);
+int sift3d_destroy(sift3d_ctx *ctx);
+
+/*
+ * Integer pair offsets of scale s (1..S) that a context built from the same
+ * parameters and draws uses: out is [brief_n][2][3] (x,y,z). Pure host
+ * function (no device needed).
+ */
+int sift3d_pair_offsets(const sift3d_params *p, const double *pair_draws, int n_draws, int scale,
+                        int32_t *out);
+
+/*
+ * Plan extraction for one volume shape. Host only, allocates nothing on
+ * the device. kp_capacity >= 0 is the size of the caller's keypoint and
+ * descriptor buffers. The plan keeps a pointer to ctx, which must outlive it.
+ */
+int sift3d_plan_create(sift3d_ctx *ctx, int nx, int ny, int nz, int kp_capacity, sift3d_plan **out);
+int sift3d_plan_destroy(sift3d_plan *plan);
+
+/* Workspace size in bytes and number of octaves of a plan. */
+int sift3d_plan_info(const sift3d_plan *plan, size_t *workspace_bytes, int *n_octaves);
+
+/* Dims (nx, ny, nz) of octave o. */
+int sift3d_plan_octave_dims(const sift3d_plan *plan, int octave, int dims[3]);
+
+/*
+ * Device pointer of one pyramid level inside a workspace: kind 0 = G_idx
+ * (idx 0..S+2), kind 1 = D_idx (idx 0..S+1). A view, no copy; the level is
+ * a [nz][ny][nx] float32 array of octave `octave`'s dims.
+ */
+int sift3d_level(const sift3d_plan *plan, void *d_ws, int octave, int kind, int idx, float **d_ptr);
+
+/*
+ * Gaussian scale space, DoG and sub-sampling (Section 3.2.2, Gaussian
+ * Convolution, Sub-sampling, Difference-of-Gaussian):
+ *   octave 0: G_0 = I blurred by sqrt(sigma0^2 - sigma_in^2);
+ *   octave o > 0: G_0 = mean of each 2x2x2 block of G_S of octave o-1;
+ *   G_i = G_{i-1} blurred by sigma0 sqrt(kappa^(2i) - kappa^(2i-2)),
+ *         kappa = 2^(1/S), i = 1..S+2 (separable x, y, z passes, taps a
+ *         normalised sampled Gaussian, clamp-to-edge);
+ *   D_i = G_i - G_{i+1}, i = 0..S+1.
+ * d_vol: [nz][ny][nx] float32, read only. d_ws: workspace of at least the
+ * planned size (256-byte aligned); all levels are written into it.
+ */
+int sift3d_build_pyramid(const sift3d_plan *plan, const float *d_vol, void *d_ws, size_t ws_bytes,
+                         void *stream);
+
+/*
+ * The pyramid is built by sift3d_pyramid_pass_count() fused passes, run in
+ * index order; sift3d_build_pyramid() runs them all. Pass i reads one level
+ * once and writes G_level of `octave`, D_{level-1} (level > 0) and, for
+ * level S of a non-final octave, G_0 of the next octave. Exposed so that a
+ * caller can time or re-run single passes; the workspace must hold the
+ * passes' inputs (pass 0 reads d_vol).
+ *   info[0] = octave, info[1] = level, info[2] = tap radius, info[3] = 1 if
+ *   the pass also writes the next octave's G_0;
+ *   *bytes = algorithmic HBM bytes of the pass: 4 per voxel read, 4 per
+ *   voxel written for G and D, 4 per sub-sampled voxel.
+ */
+int sift3d_pyramid_pass_count(const sift3d_plan *plan, int *n_passes);
+int sift3d_pyramid_pass_info(const sift3d_plan *plan, int pass, int info[4], size_t *bytes);
+int sift3d_pyramid_pass(const sift3d_plan *plan, int pass, const float *d_vol, void *d_ws, size_t ws_bytes,
+                        void *stream);
+
+/*
+ * 4D extremum detection (Section 3.2.2, 4D Peak Detection): for every
+ * octave, scale s = 1..S and interior voxel v (1 <= x <= nx-2, same for y,
+ * z) keep v if |D_s(v)| > dog_threshold and the sum over its 80 neighbours
+ * in D_{s-1}, D_s, D_{s+1} of sign(D_s(v) - neighbour) is >= votes (peak)
+ * or <= -votes (valley). Keypoints are written to d_kp in (octave, scale,
+ * z, y, x) order, at most kp_capacity of them; *d_count (device int)
+ * receives the total number found, which may exceed kp_capacity (then the
+ * list is the first kp_capacity in that order). Uses the workspace's
+ * scratch area; the pyramid must have been built in d_ws.
+ */
+int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_keypoint *d_kp,
+                  int kp_capacity, int *d_count, void *stream);
+
+/*
+ * Descriptors of keypoints 0 .. min(*d_count, kp_capacity) - 1, each on
+ * G_s of its octave. Any of the three outputs may be NULL to skip it.
+ *   d_siftrank [cap][64] uint8: upright SIFT-Rank (Section 2, 2x2x2
+ *     spatial x 8 orientation bins, normalised by ranking): over the
+ *     window d in [-R, R]^3, R = ceil(siftrank_factor * sigma_s), the
+ *     central-difference gradient g at clamp(v + d) adds |g| to orientation
+ *     bin [gx>0] + 2[gy>0] + 4[gz>0] of spatial bin (bx + 2 by + 4 bz),
+ *     where per axis d < 0 -> 0, d > 0 -> 1 and d = 0 splits half/half;
+ *     element e = 8 * spatial + orientation holds the rank of its sum
+ *     among the 64 (ties broken by index).
+ *   d_brief [cap][brief_n/64] uint64: bit i (least significant first) is
+ *     [B(p1_i) - B(p2_i) > 0] with p = clamp(v + offset) and B the
+ *     sigma_b Gaussian pre-blur of G_s evaluated at p (Section 3.2.3).
+ *   d_rrief [cap][brief_n] uint8: rank of d_i = B(p1_i) - B(p2_i) among
+ *     the brief_n differences (Section 3.2.3, RRIEF; ties by index).
+ */
+int sift3d_describe(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes,
+                    const sift3d_keypoint *d_kp, const int *d_count, int kp_capacity,
+                    uint8_t *d_siftrank, uint64_t *d_brief, uint8_t *d_rrief, void *stream);
+
+/* build_pyramid + detect + describe on one stream. */
+int sift3d_extract(const sift3d_plan *plan, const float *d_vol, void *d_ws, size_t ws_bytes,
+                   sift3d_keypoint *d_kp, int kp_capacity, int *d_count, uint8_t *d_siftrank,
+                   uint64_t *d_brief, uint8_t *d_rrief, void *stream);
+
+/* Static description of an error code. */
+const char *sift3d_error_string(int code);
+
+/* hipError_t of the last failing HIP call made by the library on this thread. */
+int sift3d_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIFT3D_H */

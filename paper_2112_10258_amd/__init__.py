@@ -1,0 +1,20 @@
+"""MI355X (gfx950) 3D SIFT-Rank hot path: HIP kernels behind a C ABI.
+
+The compute lives in libsift3d.so (built from csrc/ by ``build.py``); the
+Python side only marshals torch tensors and streams into the C ABI
+declared in include/sift3d.h.
+"""
+from .sift3d import (  # noqa: F401
+    KEYPOINT_BYTES,
+    KEYPOINT_DTYPE,
+    Buffers,
+    Context,
+    Params,
+    Plan,
+    Sift3dError,
+    default_params,
+    pair_offsets,
+    exported_symbols,
+    fetch_results,
+    run_extract,
+)

@@ -1,0 +1,292 @@
+"""ctypes binding of libsift3d.so: argument marshalling only.
+
+Every step of the hot path runs in the HIP kernels of libsift3d.so; this
+module converts torch tensors (device memory) and streams into the raw
+pointers the C ABI takes. There is no fallback: if the library is missing
+or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsift3d.so")
+
+KEYPOINT_DTYPE = np.dtype([
+    ("x", "<i4"), ("y", "<i4"), ("z", "<i4"),
+    ("octave", "<i2"), ("scale", "<i2"), ("polarity", "i1"), ("pad", "i1", (3,)),
+    ("dog", "<f4"), ("xf", "<f4"), ("yf", "<f4"), ("zf", "<f4"), ("sigma", "<f4"),
+])
+KEYPOINT_BYTES = 40
+assert KEYPOINT_DTYPE.itemsize == KEYPOINT_BYTES
+
+OK, E_ARG, E_TOO_SMALL, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -5, -6
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n_octaves", ctypes.c_int),
+        ("min_dim", ctypes.c_int),
+        ("scales", ctypes.c_int),
+        ("sigma0", ctypes.c_double),
+        ("sigma_in", ctypes.c_double),
+        ("trunc", ctypes.c_double),
+        ("dog_threshold", ctypes.c_float),
+        ("votes", ctypes.c_int),
+        ("brief_n", ctypes.c_int),
+        ("brief_blur", ctypes.c_double),
+        ("siftrank_factor", ctypes.c_double),
+    ]
+
+
+class Sift3dError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        lib = _load()
+        msg = lib.sift3d_error_string(code).decode()
+        if code == E_HIP:
+            msg += f" (hipError {lib.sift3d_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{code}]")
+        self.code = code
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsift3d.so not built ({LIB_PATH}); run python -m paper_2112_10258_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    i, sz = ctypes.c_int, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "sift3d_default_params": (i, [P(Params)]),
+        "sift3d_create": (i, [P(Params), P(ctypes.c_double), i, P(_vp)]),
+        "sift3d_destroy": (i, [_vp]),
+        "sift3d_pair_offsets": (i, [P(Params), P(ctypes.c_double), i, i, P(ctypes.c_int32)]),
+        "sift3d_plan_create": (i, [_vp, i, i, i, i, P(_vp)]),
+        "sift3d_plan_destroy": (i, [_vp]),
+        "sift3d_plan_info": (i, [_vp, P(sz), P(i)]),
+        "sift3d_plan_octave_dims": (i, [_vp, i, P(i)]),
+        "sift3d_level": (i, [_vp, _vp, i, i, i, P(_vp)]),
+        "sift3d_build_pyramid": (i, [_vp, _vp, _vp, sz, _vp]),
+        "sift3d_detect": (i, [_vp, _vp, sz, _vp, i, _vp, _vp]),
+        "sift3d_describe": (i, [_vp, _vp, sz, _vp, _vp, i, _vp, _vp, _vp, _vp]),
+        "sift3d_extract": (i, [_vp, _vp, _vp, sz, _vp, i, _vp, _vp, _vp, _vp, _vp]),
+        "sift3d_pyramid_pass_count": (i, [_vp, P(i)]),
+        "sift3d_pyramid_pass_info": (i, [_vp, i, P(i), P(sz)]),
+        "sift3d_pyramid_pass": (i, [_vp, i, _vp, _vp, sz, _vp]),
+        "sift3d_error_string": (ctypes.c_char_p, [i]),
+        "sift3d_last_hip_error": (i, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names the binding resolves in libsift3d.so (all C ABI entry points)."""
+    lib = _load()
+    return [n for n in dir(lib) if n.startswith("sift3d_")]
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise Sift3dError(code, what)
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    _check(_load().sift3d_default_params(ctypes.byref(p)), "sift3d_default_params")
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def pair_offsets(params: Params, pair_draws: np.ndarray, scale: int) -> np.ndarray:
+    """Integer (x,y,z) pair offsets [brief_n][2][3] of one scale (host only)."""
+    draws = np.ascontiguousarray(pair_draws, dtype=np.float64).reshape(-1, 2, 3)
+    out = np.zeros((params.brief_n, 2, 3), dtype=np.int32)
+    _check(_load().sift3d_pair_offsets(ctypes.byref(params), draws.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       len(draws), scale, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+           "sift3d_pair_offsets")
+    return out
+
+
+class Context:
+    """Method parameters plus the pair draws; owns a small device table."""
+
+    def __init__(self, params: Params | None = None, pair_draws: np.ndarray | None = None, **overrides):
+        lib = _load()
+        self.params = params if params is not None else default_params(**overrides)
+        draws = None
+        n = 0
+        if pair_draws is not None:
+            draws = np.ascontiguousarray(pair_draws, dtype=np.float64).reshape(-1, 2, 3)
+            n = len(draws)
+        self._draws = draws
+        h = _vp()
+        dp = draws.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if draws is not None else None
+        _check(lib.sift3d_create(ctypes.byref(self.params), dp, n, ctypes.byref(h)), "sift3d_create")
+        self.handle = h
+
+    def pair_offsets(self, scale: int) -> np.ndarray:
+        return pair_offsets(self.params, self._draws, scale)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _load().sift3d_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Extraction plan for one (nx, ny, nz) shape and keypoint capacity."""
+
+    def __init__(self, ctx: Context, shape_xyz, kp_capacity: int):
+        lib = _load()
+        self.ctx = ctx
+        self.shape_xyz = tuple(int(v) for v in shape_xyz)
+        self.capacity = int(kp_capacity)
+        h = _vp()
+        nx, ny, nz = self.shape_xyz
+        _check(lib.sift3d_plan_create(ctx.handle, nx, ny, nz, self.capacity, ctypes.byref(h)), "sift3d_plan_create")
+        self.handle = h
+        ws = ctypes.c_size_t()
+        no = ctypes.c_int()
+        _check(lib.sift3d_plan_info(h, ctypes.byref(ws), ctypes.byref(no)), "sift3d_plan_info")
+        self.workspace_bytes = ws.value
+        self.n_octaves = no.value
+
+    def octave_dims(self, o: int):
+        d = (ctypes.c_int * 3)()
+        _check(_load().sift3d_plan_octave_dims(self.handle, o, d), "sift3d_plan_octave_dims")
+        return tuple(d)
+
+    def level(self, ws, octave: int, kind: int, idx: int):
+        """torch view [nz, ny, nx] float32 of a level inside the workspace tensor."""
+        import torch
+        p = _vp()
+        _check(_load().sift3d_level(self.handle, _vp(ws.data_ptr()), octave, kind, idx, ctypes.byref(p)),
+               "sift3d_level")
+        nx, ny, nz = self.octave_dims(octave)
+        off = p.value - ws.data_ptr()
+        n = nx * ny * nz
+        return ws[off:off + 4 * n].view(torch.float32).view(nz, ny, nx)
+
+    def alloc_workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+    def build_pyramid(self, vol, ws, stream=None):
+        _check(_load().sift3d_build_pyramid(self.handle, _vp(vol.data_ptr()), _vp(ws.data_ptr()), ws.numel(),
+                                            _vp(_stream(stream))), "sift3d_build_pyramid")
+
+    def pyramid_passes(self):
+        """[(octave, level, radius, writes_sub, algorithmic_bytes)] in launch order."""
+        lib = _load()
+        n = ctypes.c_int()
+        _check(lib.sift3d_pyramid_pass_count(self.handle, ctypes.byref(n)), "sift3d_pyramid_pass_count")
+        out = []
+        for i in range(n.value):
+            info = (ctypes.c_int * 4)()
+            b = ctypes.c_size_t()
+            _check(lib.sift3d_pyramid_pass_info(self.handle, i, info, ctypes.byref(b)), "sift3d_pyramid_pass_info")
+            out.append((info[0], info[1], info[2], info[3], b.value))
+        return out
+
+    def pyramid_pass(self, i, vol, ws, stream=None):
+        _check(_load().sift3d_pyramid_pass(self.handle, i, _vp(_ptr(vol)), _vp(ws.data_ptr()), ws.numel(),
+                                           _vp(_stream(stream))), "sift3d_pyramid_pass")
+
+    def detect(self, ws, kp, count, stream=None):
+        _check(_load().sift3d_detect(self.handle, _vp(ws.data_ptr()), ws.numel(), _vp(_ptr(kp)), self.capacity,
+                                     _vp(count.data_ptr()), _vp(_stream(stream))), "sift3d_detect")
+
+    def describe(self, ws, kp, count, siftrank=None, brief=None, rrief=None, stream=None):
+        _check(_load().sift3d_describe(self.handle, _vp(ws.data_ptr()), ws.numel(), _vp(_ptr(kp)),
+                                       _vp(count.data_ptr()), self.capacity, _vp(_ptr(siftrank)),
+                                       _vp(_ptr(brief)), _vp(_ptr(rrief)), _vp(_stream(stream))),
+               "sift3d_describe")
+
+    def extract(self, vol, ws, kp, count, siftrank=None, brief=None, rrief=None, stream=None):
+        _check(_load().sift3d_extract(self.handle, _vp(vol.data_ptr()), _vp(ws.data_ptr()), ws.numel(),
+                                      _vp(_ptr(kp)), self.capacity, _vp(count.data_ptr()), _vp(_ptr(siftrank)),
+                                      _vp(_ptr(brief)), _vp(_ptr(rrief)), _vp(_stream(stream))),
+               "sift3d_extract")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _load().sift3d_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Buffers:
+    """Device buffers (torch) for one plan: workspace, keypoints, count, descriptors."""
+
+    def __init__(self, plan: Plan, device="cuda"):
+        import torch
+        cap = plan.capacity
+        n = plan.ctx.params.brief_n
+        self.ws = plan.alloc_workspace(device)
+        self.kp = torch.zeros(max(cap, 1) * KEYPOINT_BYTES, dtype=torch.uint8, device=device)
+        self.count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.siftrank = torch.zeros(max(cap, 1), 64, dtype=torch.uint8, device=device)
+        self.brief = torch.zeros(max(cap, 1), max(n // 64, 1), dtype=torch.int64, device=device)
+        self.rrief = torch.zeros(max(cap, 1), max(n, 1), dtype=torch.uint8, device=device)
+
+
+def run_extract(plan: Plan, vol, buf: Buffers, stream=None):
+    plan.extract(vol, buf.ws, buf.kp, buf.count, buf.siftrank, buf.brief, buf.rrief, stream=stream)
+
+
+def fetch_results(plan: Plan, buf: Buffers):
+    """Copy keypoints and descriptors to host numpy (synchronises)."""
+    count = int(buf.count.item())
+    k = min(count, plan.capacity)
+    kp = buf.kp[: k * KEYPOINT_BYTES].cpu().numpy().view(KEYPOINT_DTYPE)
+    n = plan.ctx.params.brief_n
+    return {
+        "count": count,
+        "keypoints": kp,
+        "siftrank": buf.siftrank[:k].cpu().numpy(),
+        "brief": buf.brief[:k].cpu().numpy().view(np.uint64)[:, : n // 64],
+        "rrief": buf.rrief[:k].cpu().numpy()[:, :n],
+    }
