@@ -92,6 +92,43 @@ void pair_offsets(const sift3d_params &p, const double *draws, int s, int32_t *o
         }
 }
 
+int xy_blocks(const OctaveGeom &g)
+{
+    return ((g.nx + kXYTX - 1) / kXYTX) * ((g.ny + kXYTY - 1) / kXYTY) * g.nz;
+}
+
+int z_blocks(const OctaveGeom &g)
+{
+    return ((g.nx + 31) / 32) * ((g.ny + 7) / 8) * ((g.nz + kZPlanes - 1) / kZPlanes);
+}
+
+// Geometry of job j of an xy launch; block0 continues after job j-1.
+void set_xy_job(XYArgs &a, int j, const OctaveGeom &g)
+{
+    XYJob &jb = a.job[j];
+    jb.nx = g.nx;
+    jb.ny = g.ny;
+    jb.nz = g.nz;
+    jb.tiles_x = (g.nx + kXYTX - 1) / kXYTX;
+    jb.tiles_y = (g.ny + kXYTY - 1) / kXYTY;
+    jb.block0 = j == 0 ? 0 : a.job[j - 1].block0 + a.job[j - 1].tiles_x * a.job[j - 1].tiles_y * a.job[j - 1].nz;
+}
+
+void set_z_job(ZArgs &a, int j, const OctaveGeom &g, const OctaveGeom *sub)
+{
+    ZJob &jb = a.job[j];
+    jb.nx = g.nx;
+    jb.ny = g.ny;
+    jb.nz = g.nz;
+    jb.mx = sub ? sub->nx : 0;
+    jb.my = sub ? sub->ny : 0;
+    jb.mz = sub ? sub->nz : 0;
+    jb.gx = (g.nx + 31) / 32;
+    jb.gy = (g.ny + 7) / 8;
+    jb.gz = (g.nz + kZPlanes - 1) / kZPlanes;
+    jb.block0 = j == 0 ? 0 : a.job[j - 1].block0 + a.job[j - 1].gx * a.job[j - 1].gy * a.job[j - 1].gz;
+}
+
 }  // namespace
 
 extern "C" {
@@ -184,7 +221,7 @@ int sift3d_plan_create(sift3d_ctx *ctx, int nx, int ny, int nz, int kp_capacity,
     pl->nz = nz;
     pl->cap = kp_capacity;
     pl->S = p.scales;
-    const int S = p.scales, nlev = 2 * S + 5;
+    const int S = p.scales, nlev = levels_per_octave(S);
     // octave geometry: halve (floor) while the smallest dim stays >= min_dim
     int cx = nx, cy = ny, cz = nz;
     size_t off = 0;
@@ -221,6 +258,9 @@ int sift3d_plan_create(sift3d_ctx *ctx, int nx, int ny, int nz, int kp_capacity,
     off += align256((size_t)pl->det_blocks * sizeof(int));
     pl->block_off_off = off;
     off += align256((size_t)pl->det_blocks * sizeof(int));
+    pl->masks_off = off;
+    for (const auto &g : pl->oct)
+        off += align256((size_t)S * (g.nz - 2) * (g.ny - 2) * ((g.nx + 63) / 64) * sizeof(unsigned long long));
     pl->ws_bytes = off;
 
     // blur schedule: G_0 of octave 0 from the input, then G_1..G_{S+2} per
@@ -244,23 +284,42 @@ int sift3d_plan_create(sift3d_ctx *ctx, int nx, int ny, int nz, int kp_capacity,
             L.dst_idx = i;
             L.dog_idx = i - 1;
             L.sub_octave = (i == S && o + 1 < pl->n_oct) ? o + 1 : -1;
-            BlurArgs &a = L.a;
-            a.nx = g.nx;
-            a.ny = g.ny;
-            a.nz = g.nz;
-            if (L.sub_octave >= 0) {
-                a.mx = pl->oct[o + 1].nx;
-                a.my = pl->oct[o + 1].ny;
-                a.mz = pl->oct[o + 1].nz;
+            L.fused = (long long)g.n >= kFusedMinVoxels;
+            if (L.fused) {
+                BlurArgs &a = L.a;
+                a.nx = g.nx;
+                a.ny = g.ny;
+                a.nz = g.nz;
+                if (L.sub_octave >= 0) {
+                    a.mx = pl->oct[o + 1].nx;
+                    a.my = pl->oct[o + 1].ny;
+                    a.mz = pl->oct[o + 1].nz;
+                }
+                a.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
+                a.tiles_y = (g.ny + kBlurTY - 1) / kBlurTY;
+                a.L = choose_slab(g.nz, a.tiles_x * a.tiles_y, L.r);
+                a.slabs = (g.nz + a.L - 1) / a.L;
+                a.n_blocks = a.tiles_x * a.tiles_y * a.slabs;
+                for (int t = 0; t < kMaxTaps; ++t) a.w[t] = t < (int)w.size() ? (float)w[t] : 0.0f;
+            } else {
+                const OctaveGeom *sub = L.sub_octave >= 0 ? &pl->oct[o + 1] : nullptr;
+                set_xy_job(L.xy, 0, g);
+                L.xy.n_jobs = 1;
+                L.xy.n_blocks = L.xy.job[0].block0 + xy_blocks(g);
+                set_z_job(L.z, 0, g, sub);
+                L.z.n_jobs = 1;
+                L.z.n_blocks = z_blocks(g);
+                for (int t = 0; t < kMaxTaps; ++t) L.xy.w[t] = L.z.w[t] = t < (int)w.size() ? (float)w[t] : 0.0f;
             }
-            a.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
-            a.tiles_y = (g.ny + kBlurTY - 1) / kBlurTY;
-            a.L = choose_slab(g.nz, a.tiles_x * a.tiles_y, L.r);
-            a.slabs = (g.nz + a.L - 1) / a.L;
-            a.n_blocks = a.tiles_x * a.tiles_y * a.slabs;
-            for (int t = 0; t < kMaxTaps; ++t) a.w[t] = t < (int)w.size() ? (float)w[t] : 0.0f;
             pl->blur.push_back(L);
         }
+    }
+    // BRIEF pre-blur: B_s = G_s blurred by sigma_b (none when sigma_b == 0)
+    {
+        const std::vector<double> wb = gaussian(p.brief_blur, p.trunc);
+        pl->brief_rb = p.brief_blur > 0.0 ? (int)(wb.size() - 1) / 2 : -1;
+        pl->wb.assign(kMaxTaps, 0.0f);
+        for (size_t t = 0; t < wb.size(); ++t) pl->wb[t] = (float)wb[t];
     }
     *out = pl;
     return SIFT3D_OK;
@@ -290,11 +349,16 @@ int sift3d_plan_octave_dims(const sift3d_plan *plan, int octave, int dims[3])
     return SIFT3D_OK;
 }
 
-static float *level_ptr(const sift3d_plan *pl, void *ws, int o, int kind, int idx)
+static float *raw_level(const sift3d_plan *pl, const void *ws, int o, int lev)
 {
     const OctaveGeom &g = pl->oct[o];
-    const int lev = kind == 0 ? idx : pl->S + 3 + idx;
-    return reinterpret_cast<float *>(static_cast<char *>(ws) + g.base + (size_t)lev * g.level_bytes);
+    return reinterpret_cast<float *>(const_cast<char *>(static_cast<const char *>(ws)) + g.base +
+                                     (size_t)lev * g.level_bytes);
+}
+
+static float *level_ptr(const sift3d_plan *pl, const void *ws, int o, int kind, int idx)
+{
+    return raw_level(pl, ws, o, kind == 0 ? lev_G(idx) : lev_D(pl->S, idx));
 }
 
 int sift3d_level(const sift3d_plan *plan, void *d_ws, int octave, int kind, int idx, float **d_ptr)
@@ -316,13 +380,72 @@ static int check_ws(const sift3d_plan *plan, const void *ws, size_t bytes)
 
 static int run_pass(const sift3d_plan *plan, const BlurLaunch &L, const float *d_vol, void *d_ws, hipStream_t st)
 {
-    BlurArgs a = L.a;
-    a.src = L.src_kind < 0 ? d_vol : level_ptr(plan, d_ws, L.octave, 0, L.src_idx);
-    a.dst = level_ptr(plan, d_ws, L.octave, 0, L.dst_idx);
-    a.dog = L.dog ? level_ptr(plan, d_ws, L.octave, 1, L.dog_idx) : nullptr;
-    a.sub = L.sub_octave >= 0 ? level_ptr(plan, d_ws, L.sub_octave, 0, 0) : nullptr;
-    const hipError_t e = launch_blur(a, L.r, L.dog, st);
+    const float *src = L.src_kind < 0 ? d_vol : level_ptr(plan, d_ws, L.octave, 0, L.src_idx);
+    float *dst = level_ptr(plan, d_ws, L.octave, 0, L.dst_idx);
+    float *dog = L.dog ? level_ptr(plan, d_ws, L.octave, 1, L.dog_idx) : nullptr;
+    float *sub = L.sub_octave >= 0 ? level_ptr(plan, d_ws, L.sub_octave, 0, 0) : nullptr;
+    hipError_t e;
+    if (L.fused) {
+        BlurArgs a = L.a;
+        a.src = src;
+        a.dst = dst;
+        a.dog = dog;
+        a.sub = sub;
+        e = launch_blur(a, L.r, L.dog, st);
+    } else {
+        float *t = raw_level(plan, d_ws, L.octave, lev_T(plan->S));
+        XYArgs xy = L.xy;
+        xy.job[0].src = src;
+        xy.job[0].dst = t;
+        e = launch_blur_xy(xy, L.r, st);
+        if (e == hipSuccess) {
+            ZArgs z = L.z;
+            z.job[0].t = t;
+            z.job[0].center = src;
+            z.job[0].dst = dst;
+            z.job[0].dog = dog;
+            z.job[0].sub = sub;
+            e = launch_blur_z(z, L.r, L.dog, st);
+        }
+    }
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
+}
+
+// B_s = G_s blurred by the BRIEF pre-blur, for every octave and s = 1..S,
+// as job lists of at most kMaxJobs (octave, s) levels per launch pair.
+static int run_preblur(const sift3d_plan *plan, const void *d_ws, hipStream_t st)
+{
+    if (plan->brief_rb < 0) return SIFT3D_OK;
+    const int S = plan->S;
+    std::vector<std::pair<int, int>> jobs;
+    for (int o = 0; o < plan->n_oct; ++o)
+        for (int s = 1; s <= S; ++s) jobs.emplace_back(o, s);
+    for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxJobs) {
+        XYArgs xy{};
+        ZArgs z{};
+        const int nj = (int)std::min<size_t>(kMaxJobs, jobs.size() - j0);
+        for (int j = 0; j < nj; ++j) {
+            const int o = jobs[j0 + j].first, s = jobs[j0 + j].second;
+            const OctaveGeom &g = plan->oct[o];
+            set_xy_job(xy, j, g);
+            xy.job[j].src = raw_level(plan, d_ws, o, lev_G(s));
+            xy.job[j].dst = raw_level(plan, d_ws, o, lev_Tb(S, s));
+            set_z_job(z, j, g, nullptr);
+            z.job[j].t = xy.job[j].dst;
+            z.job[j].center = nullptr;
+            z.job[j].dst = raw_level(plan, d_ws, o, lev_B(S, s));
+            z.job[j].dog = nullptr;
+            z.job[j].sub = nullptr;
+        }
+        xy.n_jobs = z.n_jobs = nj;
+        xy.n_blocks = xy.job[nj - 1].block0 + xy_blocks(plan->oct[jobs[j0 + nj - 1].first]);
+        z.n_blocks = z.job[nj - 1].block0 + z_blocks(plan->oct[jobs[j0 + nj - 1].first]);
+        for (int t = 0; t < kMaxTaps; ++t) xy.w[t] = z.w[t] = plan->wb[t];
+        hipError_t e = launch_blur_xy(xy, plan->brief_rb, st);
+        if (e == hipSuccess) e = launch_blur_z(z, plan->brief_rb, false, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return SIFT3D_OK;
 }
 
 int sift3d_build_pyramid(const sift3d_plan *plan, const float *d_vol, void *d_ws, size_t ws_bytes, void *stream)
@@ -395,7 +518,21 @@ int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_k
             d.row_base += (long long)plan->S * (plan->oct[q].nz - 2) * (plan->oct[q].ny - 2);
         d.rows = (long long)plan->S * (g.nz - 2) * (g.ny - 2);
         for (int s = 0; s <= plan->S; ++s) d.sigma[s] = (float)(scale_sigma(p, s) * std::ldexp(1.0, o));
+        d.words = (g.nx + 63) / 64;
+        d.tiles_x = d.words;
+        d.tiles_y = (g.ny - 2 + kDTY - 1) / kDTY;   // interior rows 1..ny-2
+        d.tiles_z = (g.nz - 2 + kDTZ - 1) / kDTZ;   // interior planes 1..nz-2
+        d.block0 = a.tile_blocks;
+        a.tile_blocks += d.tiles_x * d.tiles_y * d.tiles_z;
     }
+    {
+        size_t moff = plan->masks_off;
+        for (int o = 0; o < plan->n_oct; ++o) {
+            a.oc[o].masks = reinterpret_cast<unsigned long long *>(static_cast<char *>(d_ws) + moff);
+            moff += align256((size_t)a.oc[o].rows * a.oc[o].words * sizeof(unsigned long long));
+        }
+    }
+    a.row_blocks = (int)((plan->total_rows + kRowBlock - 1) / kRowBlock);
     a.n_oct = plan->n_oct;
     a.S = plan->S;
     a.total_rows = plan->total_rows;
@@ -425,7 +562,8 @@ int sift3d_describe(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes, 
     DescribeArgs a{};
     for (int o = 0; o < plan->n_oct; ++o) {
         const OctaveGeom &g = plan->oct[o];
-        a.oc[o].G = level_ptr(plan, const_cast<void *>(d_ws), o, 0, 0);
+        a.oc[o].G = level_ptr(plan, d_ws, o, 0, 0);
+        a.oc[o].B = plan->brief_rb >= 0 ? raw_level(plan, d_ws, o, lev_B(plan->S, 1)) : level_ptr(plan, d_ws, o, 0, 1);
         a.oc[o].lstride = (long long)(g.level_bytes / sizeof(float));
         a.oc[o].nx = g.nx;
         a.oc[o].ny = g.ny;
@@ -441,10 +579,11 @@ int sift3d_describe(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes, 
     a.brief = d_brief;
     a.rrief = d_rrief;
     a.brief_n = p.brief_n;
-    const std::vector<double> wb = gaussian(p.brief_blur, p.trunc);
-    a.brief_rb = (int)(wb.size() - 1) / 2;
-    for (size_t t = 0; t < wb.size(); ++t) a.wb[t] = wb[t];
     a.pairs = plan->ctx->d_offsets;
+    if (d_brief != nullptr || d_rrief != nullptr) {
+        rc = run_preblur(plan, d_ws, static_cast<hipStream_t>(stream));
+        if (rc != SIFT3D_OK) return rc;
+    }
     const int grid = std::min(kp_capacity, 4096);
     const hipError_t e = launch_describe(a, grid, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);

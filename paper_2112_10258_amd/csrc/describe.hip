@@ -15,6 +15,49 @@ constexpr int kDescThreads = 256;
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// One (dx, dy) column of the SIFT-Rank window: all loads of the column are
+// issued first (4 per sample for the x/y differences, the column itself for
+// z), then |g| is accumulated per (z half, orientation octant) in double.
+template <int R>
+__device__ __forceinline__ void sift_column(const float *G, int nx, int ny, int nz, int cx, int cy, int cz,
+                                            double (&acc)[16])
+{
+    constexpr int W = 2 * R + 1;
+    const int qx = clampi(cx, 0, nx - 1), qy = clampi(cy, 0, ny - 1);
+    const int xm = clampi(qx - 1, 0, nx - 1), xp = clampi(qx + 1, 0, nx - 1);
+    const int ym = clampi(qy - 1, 0, ny - 1), yp = clampi(qy + 1, 0, ny - 1);
+    const size_t nxy = (size_t)nx * ny;
+    float fxp[W], fxm[W], fyp[W], fym[W], fzp[W], fzm[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        const int qz = clampi(cz + i - R, 0, nz - 1);
+        const int zm = clampi(qz - 1, 0, nz - 1), zp = clampi(qz + 1, 0, nz - 1);
+        const size_t rc = (size_t)qz * nxy + (size_t)qy * nx;
+        fxp[i] = G[rc + xp];
+        fxm[i] = G[rc + xm];
+        fyp[i] = G[(size_t)qz * nxy + (size_t)yp * nx + qx];
+        fym[i] = G[(size_t)qz * nxy + (size_t)ym * nx + qx];
+        fzp[i] = G[(size_t)zp * nxy + (size_t)qy * nx + qx];
+        fzm[i] = G[(size_t)zm * nxy + (size_t)qy * nx + qx];
+    }
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        const int dz = i - R;
+        const double gx = 0.5 * ((double)fxp[i] - (double)fxm[i]);
+        const double gy = 0.5 * ((double)fyp[i] - (double)fym[i]);
+        const double gz = 0.5 * ((double)fzp[i] - (double)fzm[i]);
+        const double m = sqrt(gx * gx + gy * gy + gz * gz);
+        const int bo = (gx > 0.0) + 2 * (gy > 0.0) + 4 * (gz > 0.0);
+        const double w0 = dz < 0 ? m : (dz == 0 ? 0.5 * m : 0.0);
+        const double w1 = dz > 0 ? m : (dz == 0 ? 0.5 * m : 0.0);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            acc[b] += bo == b ? w0 : 0.0;
+            acc[8 + b] += bo == b ? w1 : 0.0;
+        }
+    }
+}
+
 // SIFT-Rank. Each lane owns one (dx, dy) column of the (2R+1)^3 window and
 // walks dz, accumulating |g| per (z half, orientation octant); the centre
 // plane dz = 0 adds half to each z half. The 64 bins are then summed over
@@ -42,27 +85,14 @@ __global__ void __launch_bounds__(kDescThreads) siftrank_kernel(const DescribeAr
         for (int b = 0; b < 16; ++b) acc[b] = 0.0;
         if (tid < W * W) {
             const int dx = tid % W - R, dy = tid / W - R;
-            const int qx = clampi(kp.x + dx, 0, nx - 1), qy = clampi(kp.y + dy, 0, ny - 1);
-            const int xm = clampi(qx - 1, 0, nx - 1), xp = clampi(qx + 1, 0, nx - 1);
-            const int ym = clampi(qy - 1, 0, ny - 1), yp = clampi(qy + 1, 0, ny - 1);
-            for (int dz = -R; dz <= R; ++dz) {
-                const int qz = clampi(kp.z + dz, 0, nz - 1);
-                const int zm = clampi(qz - 1, 0, nz - 1), zp = clampi(qz + 1, 0, nz - 1);
-                const size_t rc = ((size_t)qz * ny + qy) * nx;
-                const double gx = 0.5 * ((double)G[rc + xp] - (double)G[rc + xm]);
-                const double gy = 0.5 * ((double)G[((size_t)qz * ny + yp) * nx + qx] -
-                                         (double)G[((size_t)qz * ny + ym) * nx + qx]);
-                const double gz = 0.5 * ((double)G[((size_t)zp * ny + qy) * nx + qx] -
-                                         (double)G[((size_t)zm * ny + qy) * nx + qx]);
-                const double m = sqrt(gx * gx + gy * gy + gz * gz);
-                const int bo = (gx > 0.0) + 2 * (gy > 0.0) + 4 * (gz > 0.0);
-                const double w0 = dz < 0 ? m : (dz == 0 ? 0.5 * m : 0.0);
-                const double w1 = dz > 0 ? m : (dz == 0 ? 0.5 * m : 0.0);
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    acc[b] += bo == b ? w0 : 0.0;
-                    acc[8 + b] += bo == b ? w1 : 0.0;
-                }
+            switch (R) {
+            case 1: sift_column<1>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+            case 2: sift_column<2>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+            case 3: sift_column<3>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+            case 4: sift_column<4>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+            case 5: sift_column<5>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+            case 6: sift_column<6>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+            default: sift_column<7>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
             }
         }
 #pragma unroll
@@ -84,9 +114,10 @@ __global__ void __launch_bounds__(kDescThreads) siftrank_kernel(const DescribeAr
         if (tid < 64) {
             const double h = hist[tid];
             int r = 0;
+#pragma unroll 8
             for (int e = 0; e < 64; ++e) {
                 const double o = hist[e];
-                r += (o < h) || (o == h && e < tid);
+                r += (int)(o < h) | ((int)(o == h) & (int)(e < tid));
             }
             a.siftrank[(size_t)k * 64 + tid] = (uint8_t)r;
         }
@@ -94,63 +125,65 @@ __global__ void __launch_bounds__(kDescThreads) siftrank_kernel(const DescribeAr
     }
 }
 
-// BRIEF / RRIEF. For each of the 2n sample points p = clamp(v + offset),
-// B(p) = sum over the (2rb+1)^3 stencil of wb_a wb_b wb_c G[clamp(p + (a,b,c))]
-// is evaluated by one wavefront: lane (a, b) sums its z column, the wave
-// then reduces with a fixed xor-butterfly and lane 0's total is kept.
+// BRIEF / RRIEF. B_s is G_s already blurred by the sigma_b pre-blur (a
+// whole-level separable pass with the same clamp-to-edge rule, so B_s at a
+// voxel equals the pre-blur stencil evaluated there). One wavefront per
+// keypoint: lane l owns pairs l, l+64, ...; d_i = B_s(p1) - B_s(p2) is the
+// exact double difference of the two samples; bit words come from ballots
+// and each rank from a comparison against all n differences in LDS.
 __global__ void __launch_bounds__(kDescThreads) brief_kernel(const DescribeArgs a)
 {
-    __shared__ double Bv[2 * kMaxPairs];
-    __shared__ double dd[kMaxPairs];
+    constexpr int WAVES = kDescThreads / 64;
+    __shared__ double dd[WAVES][kMaxPairs];
     const int count = min(*a.d_count, a.cap);
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-    const int n = a.brief_n, rb = a.brief_rb, W = 2 * rb + 1, W2 = W * W;
-    const int nw = n / 64;
-    for (int k = blockIdx.x; k < count; k += gridDim.x) {
-        const sift3d_keypoint kp = a.kp[k];
-        if (kp.octave < 0 || kp.octave >= a.n_oct || kp.scale < 1 || kp.scale > a.S) {
-            if (wave < nw && a.brief != nullptr && lane == 0) a.brief[(size_t)k * nw + wave] = 0;
-            if (tid < n && a.rrief != nullptr) a.rrief[(size_t)k * n + tid] = 0;
-            continue;
+    const int n = a.brief_n, nw = n / 64;
+    for (int k0 = blockIdx.x * WAVES; k0 < count; k0 += gridDim.x * WAVES) {
+        const int k = k0 + wave;
+        const bool live = k < count;
+        sift3d_keypoint kp{};
+        if (live) kp = a.kp[k];
+        const bool valid = live && kp.octave >= 0 && kp.octave < a.n_oct && kp.scale >= 1 && kp.scale <= a.S;
+        double d[kMaxPairs / 64] = {0.0, 0.0, 0.0, 0.0};
+        if (valid) {
+            const DescOctave &oc = a.oc[kp.octave];
+            const float *B = oc.B + oc.lstride * (kp.scale - 1);
+            const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
+            const int32_t *off = a.pairs + (size_t)(kp.scale - 1) * n * 6;
+            for (int q = 0; q < nw; ++q) {
+                const int32_t *o = off + (size_t)(lane + 64 * q) * 6;
+                const int x1 = clampi(kp.x + o[0], 0, nx - 1), y1 = clampi(kp.y + o[1], 0, ny - 1);
+                const int z1 = clampi(kp.z + o[2], 0, nz - 1);
+                const int x2 = clampi(kp.x + o[3], 0, nx - 1), y2 = clampi(kp.y + o[4], 0, ny - 1);
+                const int z2 = clampi(kp.z + o[5], 0, nz - 1);
+                const float b1 = B[((size_t)z1 * ny + y1) * nx + x1];
+                const float b2 = B[((size_t)z2 * ny + y2) * nx + x2];
+                d[q] = (double)b1 - (double)b2;
+                dd[wave][lane + 64 * q] = d[q];
+            }
         }
-        const DescOctave &oc = a.oc[kp.octave];
-        const float *G = oc.G + oc.lstride * kp.scale;
-        const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
-        const int32_t *off = a.pairs + (size_t)(kp.scale - 1) * n * 6;
-        for (int q = wave; q < 2 * n; q += kDescThreads / 64) {
-            const int px = clampi(kp.x + off[3 * q + 0], 0, nx - 1);
-            const int py = clampi(kp.y + off[3 * q + 1], 0, ny - 1);
-            const int pz = clampi(kp.z + off[3 * q + 2], 0, nz - 1);
-            double part = 0.0;
-            for (int ab = lane; ab < W2; ab += 64) {
-                const int ai = ab % W, bi = ab / W;
-                const int xx = clampi(px + ai - rb, 0, nx - 1), yy = clampi(py + bi - rb, 0, ny - 1);
-                const float *col = G + (size_t)yy * nx + xx;
-                double acc = 0.0;
-                for (int c = 0; c < W; ++c) {
-                    const int zz = clampi(pz + c - rb, 0, nz - 1);
-                    acc += a.wb[c] * (double)col[(size_t)zz * nx * ny];
+        __syncthreads();
+        if (live) {
+            int r[kMaxPairs / 64] = {0, 0, 0, 0};
+            if (valid && a.rrief != nullptr) {
+                // rank of d_i among the n: #{j : d_j < d_i or (d_j == d_i and j < i)}
+                for (int j0 = 0; j0 < n; j0 += 8) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int jj = j0 + u;
+                        const double o = dd[wave][jj];
+#pragma unroll
+                        for (int q = 0; q < kMaxPairs / 64; ++q)  // branch-free; q >= nw is unused
+                            r[q] += (int)(o < d[q]) | ((int)(o == d[q]) & (int)(jj < lane + 64 * q));
+                    }
                 }
-                part += (a.wb[ai] * a.wb[bi]) * acc;
             }
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o);
-            if (lane == 0) Bv[q] = part;
-        }
-        __syncthreads();
-        if (tid < n) dd[tid] = Bv[2 * tid] - Bv[2 * tid + 1];
-        __syncthreads();
-        if (wave < nw) {
-            const double d = dd[tid];
-            const unsigned long long m = __ballot(d > 0.0);
-            if (a.brief != nullptr && lane == 0) a.brief[(size_t)k * nw + wave] = m;
-            if (a.rrief != nullptr) {
-                int r = 0;
-                for (int j = 0; j < n; ++j) {
-                    const double o = dd[j];
-                    r += (o < d) || (o == d && j < tid);
-                }
-                a.rrief[(size_t)k * n + tid] = (uint8_t)r;
+            for (int q = 0; q < kMaxPairs / 64; ++q) {
+                if (q >= nw) break;
+                const unsigned long long m = __ballot(valid && d[q] > 0.0);
+                if (a.brief != nullptr && lane == 0) a.brief[(size_t)k * nw + q] = m;
+                if (a.rrief != nullptr) a.rrief[(size_t)k * n + lane + 64 * q] = (uint8_t)r[q];
             }
         }
         __syncthreads();
@@ -168,7 +201,8 @@ hipError_t launch_describe(const DescribeArgs &a, int grid, hipStream_t st)
         if (e != hipSuccess) return e;
     }
     if ((a.brief != nullptr || a.rrief != nullptr) && a.brief_n > 0) {
-        hipLaunchKernelGGL(brief_kernel, dim3(grid), dim3(kDescThreads), 0, st, a);
+        const int g = (grid + kDescThreads / 64 - 1) / (kDescThreads / 64);
+        hipLaunchKernelGGL(brief_kernel, dim3(g), dim3(kDescThreads), 0, st, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -1,0 +1,220 @@
+// Two-launch separable Gaussian level for volumes that stay resident in the
+// last-level cache (Section 3.2.2, Gaussian Convolution / Difference-of-
+// Gaussian / Sub-sampling):
+//   xy launch: per (plane, 64x16 tile), stage the (16+2R) x (64+2R) halo
+//              tile in LDS, blur along x into a second LDS tile, then along
+//              y, write the xy-blurred plane T;
+//   z launch:  per (32x8 columns, 8 output planes), slide a register window
+//              of 8+2R samples of T down each column, blur along z, and
+//              write G, optionally D = centre - G and the 2x2x2 mean of G.
+// Neither launch has a serial plane chain, so every block finishes in a
+// few microseconds; the price is the T round trip through the cache.
+//
+// Both launches take a list of jobs (one per volume/level) that share the
+// tap radius, so several levels or volumes are processed by one launch.
+#include "sift3d_internal.h"
+
+namespace s3d {
+namespace {
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+template <int R, typename F>
+__device__ __forceinline__ float sym_stencil(const float (&w)[2 * R + 1], F at)
+{
+    if constexpr (R == 0) {
+        return w[0] * at(0);
+    } else {
+        float s = w[0] * (at(0) + at(2 * R));
+#pragma unroll
+        for (int k = 1; k < R; ++k) s = __builtin_fmaf(w[k], at(k) + at(2 * R - k), s);
+        return __builtin_fmaf(w[R], at(R), s);
+    }
+}
+
+template <typename Args>
+__device__ __forceinline__ int find_job(const Args &a, int bid)
+{
+    int j = 0;
+    while (j + 1 < a.n_jobs && bid >= a.job[j + 1].block0) ++j;
+    return j;
+}
+
+template <int R>
+__global__ void __launch_bounds__(kXYThreads) blur_xy_kernel(const XYArgs a)
+{
+    constexpr int TX = kXYTX, TY = kXYTY, NT = kXYThreads, M = 2 * R + 1;
+    constexpr int NYo = TX * TY / NT;               // y outputs per thread
+    constexpr int AWL = TX + 2 * R;
+    constexpr int AW = (AWL + 3) & ~3;
+    constexpr int AH = TY + 2 * R;
+    constexpr int AE = AH * AWL;
+    constexpr int XQ = TX / 4;
+    constexpr int XIN = 4 + ((2 * R + 3) & ~3);
+    __shared__ __align__(16) float A[AH * AW];
+    __shared__ __align__(16) float B[AH * TX];
+
+    const int j = find_job(a, blockIdx.x);
+    const XYJob &jb = a.job[j];
+    const int local = blockIdx.x - jb.block0;
+    const int ntile = jb.tiles_x * jb.tiles_y;
+    const int z = local / ntile;
+    const int t2 = local - z * ntile;
+    const int tyi = t2 / jb.tiles_x, txi = t2 - tyi * jb.tiles_x;
+    const int x0 = txi * TX, y0 = tyi * TY;
+    const int nx = jb.nx, ny = jb.ny;
+    const size_t plane = (size_t)z * nx * ny;
+    const float *src = jb.src + plane;
+    const int tid = threadIdx.x;
+
+    float w[M];
+#pragma unroll
+    for (int t = 0; t < M; ++t) w[t] = a.w[t];
+
+    for (int idx = tid; idx < AE; idx += NT) {
+        const int r = idx / AWL, c = idx - r * AWL;
+        A[r * AW + c] = src[clampi(y0 - R + r, 0, ny - 1) * nx + clampi(x0 - R + c, 0, nx - 1)];
+    }
+    __syncthreads();
+    for (int item = tid; item < AH * XQ; item += NT) {
+        const int r = item / XQ, xb = (item - r * XQ) * 4;
+        float in[XIN];
+        const float4 *s4 = reinterpret_cast<const float4 *>(&A[r * AW + xb]);
+#pragma unroll
+        for (int q = 0; q < XIN / 4; ++q) {
+            const float4 v = s4[q];
+            in[4 * q + 0] = v.x;
+            in[4 * q + 1] = v.y;
+            in[4 * q + 2] = v.z;
+            in[4 * q + 3] = v.w;
+        }
+        float o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = sym_stencil<R>(w, [&](int t) { return in[q + t]; });
+        *reinterpret_cast<float4 *>(&B[r * TX + xb]) = make_float4(o[0], o[1], o[2], o[3]);
+    }
+    __syncthreads();
+    const int tx = tid % TX, tyb = (tid / TX) * NYo;
+    float col[NYo + 2 * R];
+#pragma unroll
+    for (int q = 0; q < NYo + 2 * R; ++q) col[q] = B[(tyb + q) * TX + tx];
+    const int gx = x0 + tx;
+#pragma unroll
+    for (int k = 0; k < NYo; ++k) {
+        const float v = sym_stencil<R>(w, [&](int t) { return col[k + t]; });
+        const int gy = y0 + tyb + k;
+        if (gx < nx && gy < ny) jb.dst[plane + (size_t)gy * nx + gx] = v;
+    }
+}
+
+template <int R, bool DOG>
+__global__ void __launch_bounds__(kZThreads) blur_z_kernel(const ZArgs a)
+{
+    constexpr int ZS = kZPlanes, M = 2 * R + 1, WN = ZS + 2 * R;
+    static_assert(ZS % 2 == 0, "sub-sampling pairs planes inside a thread");
+    const int j = find_job(a, blockIdx.x);
+    const ZJob &jb = a.job[j];
+    const int local = blockIdx.x - jb.block0;
+    const int gxy = jb.gx * jb.gy;
+    const int bz = local / gxy;
+    const int t2 = local - bz * gxy;
+    const int byi = t2 / jb.gx, bxi = t2 - byi * jb.gx;
+    const int tid = threadIdx.x;
+    const int tx = tid & 31, ty = tid >> 5;
+    const int nx = jb.nx, ny = jb.ny, nz = jb.nz;
+    const int x = bxi * 32 + tx, y = byi * 8 + ty, z0 = bz * ZS;
+    const int xc = min(x, nx - 1), yc = min(y, ny - 1);
+    const size_t nxy = (size_t)nx * ny;
+    const size_t col = (size_t)yc * nx + xc;
+
+    float w[M];
+#pragma unroll
+    for (int t = 0; t < M; ++t) w[t] = a.w[t];
+    float win[WN];
+#pragma unroll
+    for (int q = 0; q < WN; ++q) win[q] = jb.t[(size_t)clampi(z0 - R + q, 0, nz - 1) * nxy + col];
+    float g[ZS];
+#pragma unroll
+    for (int k = 0; k < ZS; ++k) g[k] = sym_stencil<R>(w, [&](int t) { return win[k + t]; });
+
+    const bool in_xy = x < nx && y < ny;
+#pragma unroll
+    for (int k = 0; k < ZS; ++k) {
+        const int z = z0 + k;
+        if (in_xy && z < nz) {
+            const size_t i = (size_t)z * nxy + col;
+            jb.dst[i] = g[k];
+            if constexpr (DOG) jb.dog[i] = jb.center[i] - g[k];
+        }
+    }
+    if (jb.sub != nullptr) {
+#pragma unroll
+        for (int k = 0; k < ZS; k += 2) {
+            float s = g[k] + g[k + 1];
+            s += __shfl_xor(s, 1);   // x pair: neighbouring lane
+            s += __shfl_xor(s, 32);  // y pair: same lane of the other half-wave
+            const int X = x >> 1, Y = y >> 1, Z = (z0 + k) >> 1;
+            if ((tx & 1) == 0 && (ty & 1) == 0 && X < jb.mx && Y < jb.my && Z < jb.mz)
+                jb.sub[((size_t)Z * jb.my + Y) * jb.mx + X] = s * 0.125f;
+        }
+    }
+}
+
+template <int R>
+hipError_t launch_xy_r(const XYArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((blur_xy_kernel<R>), dim3(a.n_blocks), dim3(kXYThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_z_r(const ZArgs &a, bool dog, hipStream_t st)
+{
+    if (dog)
+        hipLaunchKernelGGL((blur_z_kernel<R, true>), dim3(a.n_blocks), dim3(kZThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL((blur_z_kernel<R, false>), dim3(a.n_blocks), dim3(kZThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define S3D_RADIUS_SWITCH(r, CALL)   \
+    switch (r) {                     \
+    case 0: return CALL(0);          \
+    case 1: return CALL(1);          \
+    case 2: return CALL(2);          \
+    case 3: return CALL(3);          \
+    case 4: return CALL(4);          \
+    case 5: return CALL(5);          \
+    case 6: return CALL(6);          \
+    case 7: return CALL(7);          \
+    case 8: return CALL(8);          \
+    case 9: return CALL(9);          \
+    case 10: return CALL(10);        \
+    case 11: return CALL(11);        \
+    case 12: return CALL(12);        \
+    case 13: return CALL(13);        \
+    case 14: return CALL(14);        \
+    case 15: return CALL(15);        \
+    case 16: return CALL(16);        \
+    default: return hipErrorInvalidValue; \
+    }
+
+hipError_t launch_blur_xy(const XYArgs &a, int r, hipStream_t st)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+#define S3D_XY(R) launch_xy_r<R>(a, st)
+    S3D_RADIUS_SWITCH(r, S3D_XY)
+#undef S3D_XY
+}
+
+hipError_t launch_blur_z(const ZArgs &a, int r, bool dog, hipStream_t st)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+#define S3D_Z(R) launch_z_r<R>(a, dog, st)
+    S3D_RADIUS_SWITCH(r, S3D_Z)
+#undef S3D_Z
+}
+
+}  // namespace s3d

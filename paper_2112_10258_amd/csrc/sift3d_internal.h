@@ -26,11 +26,25 @@ constexpr int kBlurTY = 16;                 // tile height in y
 constexpr int kBlurNY = 2;                  // consecutive y outputs per thread
 constexpr int kBlurThreads = kBlurTX * kBlurTY / kBlurNY;
 
+// Two-launch (xy, then z) level geometry.
+constexpr int kXYTX = 64;                   // xy tile width (one wavefront per row)
+constexpr int kXYTY = 16;                   // xy tile height
+constexpr int kXYThreads = 256;
+constexpr int kZPlanes = 16;                // z outputs per thread
+constexpr int kZThreads = 256;              // 32 (x) x 8 (y) columns
+constexpr int kMaxJobs = 16;                // jobs per xy / z launch
+// Octaves with at least this many voxels use the fused streaming pass.
+constexpr long long kFusedMinVoxels = 24LL << 20;
+
 // Detection geometry.
 constexpr int kDetThreads = 256;            // 4 waves
 constexpr int kDetRowsPerWave = 4;
 constexpr int kDetRowsPerBlock = (kDetThreads / 64) * kDetRowsPerWave;
 constexpr int kScanThreads = 1024;
+// Strict-extremum path (votes == 80): one wavefront per (64 x, one y row,
+// kDTZ planes); 4 wavefronts (4 consecutive y rows) per block.
+constexpr int kDTX = 64, kDTY = 4, kDTZ = 16;
+constexpr int kRowBlock = 256;              // rows per count / emit block
 
 // One launch of the fused blur -> DoG -> sub-sample pass.
 struct BlurArgs {
@@ -46,6 +60,40 @@ struct BlurArgs {
     float w[kMaxTaps];    // taps w[t + r], t = -r..r
 };
 
+struct XYJob {
+    const float *src;
+    float *dst;
+    int nx, ny, nz;
+    int tiles_x, tiles_y;
+    int block0;           // first block of this job in the launch
+};
+
+struct XYArgs {
+    XYJob job[kMaxJobs];
+    int n_jobs;
+    int n_blocks;
+    float w[kMaxTaps];
+};
+
+struct ZJob {
+    const float *t;       // xy-blurred input
+    const float *center;  // level the DoG subtracts from (DoG launches)
+    float *dst;
+    float *dog;
+    float *sub;           // or nullptr
+    int nx, ny, nz;
+    int mx, my, mz;
+    int gx, gy, gz;       // blocks per axis
+    int block0;
+};
+
+struct ZArgs {
+    ZJob job[kMaxJobs];
+    int n_jobs;
+    int n_blocks;
+    float w[kMaxTaps];
+};
+
 struct DetOctave {
     const float *D;       // D_0 of the octave
     long long lstride;    // floats between consecutive levels
@@ -54,6 +102,10 @@ struct DetOctave {
     long long row_base;   // first global row of the octave
     long long rows;       // S * (nz-2) * (ny-2)
     float sigma[kMaxScales + 1];  // input-space sigma per scale (index s)
+    unsigned long long *masks;    // [rows][words] keypoint bits, x = 64 w + bit
+    int words;            // ceil(nx / 64)
+    int tiles_x, tiles_y, tiles_z;
+    int block0;           // first tile block of the octave
 };
 
 struct DetectArgs {
@@ -70,10 +122,13 @@ struct DetectArgs {
     int *d_count;         // total keypoints (device)
     sift3d_keypoint *kp;
     int cap;
+    int tile_blocks;      // blocks of the tile launch (all octaves)
+    int row_blocks;       // blocks of kRowBlock rows
 };
 
 struct DescOctave {
     const float *G;       // G_0 of the octave
+    const float *B;       // pre-blurred B_1 (B_s = B + (s-1) * lstride)
     long long lstride;    // floats between consecutive levels
     int nx, ny, nz, pad_;
 };
@@ -90,9 +145,7 @@ struct DescribeArgs {
     uint64_t *brief;
     uint8_t *rrief;
     int brief_n;
-    int brief_rb;
     const int32_t *pairs;              // [S][brief_n][2][3] (scale s at index s-1)
-    double wb[2 * kMaxBriefR + 1];
 };
 
 struct OctaveGeom {
@@ -102,10 +155,14 @@ struct OctaveGeom {
     size_t base;          // byte offset of G_0 in the workspace
 };
 
+// One pyramid level: G_dst of `octave` from G_src (or the input volume).
 struct BlurLaunch {
     int r;
     bool dog;
-    BlurArgs a;           // pointers are workspace-relative until bound
+    bool fused;           // fused streaming pass, else xy + z launches
+    BlurArgs a;           // fused geometry (pointers bound per call)
+    XYArgs xy;            // split geometry (pointers bound per call)
+    ZArgs z;
     int src_kind;         // -1 = input volume, 0 = G level of the octave
     int src_idx, dst_idx, dog_idx;
     int octave;
@@ -129,11 +186,13 @@ struct sift3d_plan {
     int S;
     std::vector<s3d::OctaveGeom> oct;
     size_t pyramid_bytes;
-    size_t row_count_off, block_sum_off, block_off_off;
+    size_t row_count_off, block_sum_off, block_off_off, masks_off;
     size_t ws_bytes;
     long long total_rows;
     int det_blocks;
     std::vector<s3d::BlurLaunch> blur;  // in launch order
+    int brief_rb;                       // pre-blur radius (-1: none, B_s = G_s)
+    std::vector<float> wb;              // pre-blur taps
     double base_sigma;
     std::vector<double> inc_sigma;      // G_1..G_{S+2}
 };
@@ -143,4 +202,14 @@ namespace s3d {
 hipError_t launch_blur(const BlurArgs &a, int r, bool dog, hipStream_t st);
 hipError_t launch_detect(const DetectArgs &a, hipStream_t st);
 hipError_t launch_describe(const DescribeArgs &a, int grid, hipStream_t st);
+hipError_t launch_blur_xy(const XYArgs &a, int r, hipStream_t st);
+hipError_t launch_blur_z(const ZArgs &a, int r, bool dog, hipStream_t st);
+
+// Workspace levels of an octave, in units of one padded level.
+inline int lev_G(int i) { return i; }
+inline int lev_D(int S, int i) { return S + 3 + i; }
+inline int lev_B(int S, int s) { return 2 * S + 5 + (s - 1); }   // s = 1..S
+inline int lev_T(int S) { return 3 * S + 5; }
+inline int lev_Tb(int S, int s) { return 3 * S + 6 + (s - 1); }
+inline int levels_per_octave(int S) { return 4 * S + 6; }
 }  // namespace s3d
