@@ -155,17 +155,19 @@ def main():
         pass_ms.append(time_calls(lambda i=i: plan.pyramid_pass(i, dvol, buf.ws, stream), reps, stream))
     log("[bench] stages ms: pyramid %.4f detect %.4f siftrank %.4f brief+rrief %.4f"
         % (st_pyr, st_det, st_sr, st_br))
-    for (o, lev, r, sub, b), t in zip(passes, pass_ms):
+    for (o, lev, r, sub, b, fused), t in zip(passes, pass_ms):
         log(f"[bench]   pass o={o} G{lev} r={r} sub={sub}: {t * 1e3:.2f} us, {b / t / 1e6:.0f} GB/s algorithmic")
 
     # roofline of the blur/DoG pass: octave-0 incremental passes (G_1..G_{S+2})
-    sel = [i for i, (o, lev, r, sub, b) in enumerate(passes) if o == 0 and lev > 0]
+    sel = [i for i, p in enumerate(passes) if p[0] == 0 and p[1] > 0]
+    fused = bool(passes[sel[0]][5])
     bytes_per_launch = sum(passes[i][4] for i in sel) / len(sel)
     dur_ms = sum(pass_ms[i] for i in sel) / len(sel)
     achieved = bytes_per_launch / (dur_ms * 1e-3) / 1e9
     traffic = read_traffic(args.workload)
     roofline = {
-        "kernel": "blur_level_kernel (octave-0 fused blur+DoG passes G_1..G_5)",
+        "kernel": ("blur_level_kernel" if fused else "blur_xy_kernel + blur_z_kernel")
+                  + " (octave-0 pyramid level passes G_1..G_5: blur + DoG + sub-sample)",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,

@@ -56,6 +56,9 @@ typedef struct sift3d_params {
     int brief_n;            /* [256] BRIEF/RRIEF pairs, multiple of 64, <= 256   */
     double brief_blur;      /* [0.95] patch pre-blur sigma_b (0 = none), <= 2.0  */
     double siftrank_factor; /* [2.0] SIFT-Rank half-width R = ceil(f * sigma_s), R <= 7 */
+    int pyramid_mode;       /* [0] 0 = by size (fused streaming pass for octaves of
+                               >= 24M voxels, xy + z launches below), 1 = always
+                               fused, 2 = always xy + z; results agree to rounding */
 } sift3d_params;
 
 /*
@@ -129,7 +132,12 @@ int sift3d_level(const sift3d_plan *plan, void *d_ws, int octave, int kind, int 
  *   G_i = G_{i-1} blurred by sigma0 sqrt(kappa^(2i) - kappa^(2i-2)),
  *         kappa = 2^(1/S), i = 1..S+2 (separable x, y, z passes, taps a
  *         normalised sampled Gaussian, clamp-to-edge);
- *   D_i = G_i - G_{i+1}, i = 0..S+1.
+ *   D_i = G_i - G_{i+1}, i = 0..S+1;
+ *   and, when brief_n > 0 and brief_blur > 0, the BRIEF patch pre-blur of
+ *   G_s, s = 1..S (Section 3.2.3: the patch is Gaussian-blurred before the
+ *   pair differences), as whole levels with the same clamp-to-edge rule.
+ * Independent levels (the last levels of octave o, the first of octave o+1,
+ * the pre-blurs) share launches.
  * d_vol: [nz][ny][nx] float32, read only. d_ws: workspace of at least the
  * planned size (256-byte aligned); all levels are written into it.
  */
@@ -142,14 +150,16 @@ int sift3d_build_pyramid(const sift3d_plan *plan, const float *d_vol, void *d_ws
  * once and writes G_level of `octave`, D_{level-1} (level > 0) and, for
  * level S of a non-final octave, G_0 of the next octave. Exposed so that a
  * caller can time or re-run single passes; the workspace must hold the
- * passes' inputs (pass 0 reads d_vol).
+ * passes' inputs (pass 0 reads d_vol). The passes do not write the BRIEF
+ * pre-blurred levels; sift3d_build_pyramid does.
  *   info[0] = octave, info[1] = level, info[2] = tap radius, info[3] = 1 if
- *   the pass also writes the next octave's G_0;
+ *   the pass also writes the next octave's G_0, info[4] = 1 if it is one
+ *   fused streaming launch, 0 if an xy launch followed by a z launch;
  *   *bytes = algorithmic HBM bytes of the pass: 4 per voxel read, 4 per
  *   voxel written for G and D, 4 per sub-sampled voxel.
  */
 int sift3d_pyramid_pass_count(const sift3d_plan *plan, int *n_passes);
-int sift3d_pyramid_pass_info(const sift3d_plan *plan, int pass, int info[4], size_t *bytes);
+int sift3d_pyramid_pass_info(const sift3d_plan *plan, int pass, int info[5], size_t *bytes);
 int sift3d_pyramid_pass(const sift3d_plan *plan, int pass, const float *d_vol, void *d_ws, size_t ws_bytes,
                         void *stream);
 
@@ -180,7 +190,8 @@ int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_k
  *     among the 64 (ties broken by index).
  *   d_brief [cap][brief_n/64] uint64: bit i (least significant first) is
  *     [B(p1_i) - B(p2_i) > 0] with p = clamp(v + offset) and B the
- *     sigma_b Gaussian pre-blur of G_s evaluated at p (Section 3.2.3).
+ *     sigma_b Gaussian pre-blur of G_s evaluated at p (Section 3.2.3),
+ *     read from the pre-blurred level sift3d_build_pyramid wrote.
  *   d_rrief [cap][brief_n] uint8: rank of d_i = B(p1_i) - B(p2_i) among
  *     the brief_n differences (Section 3.2.3, RRIEF; ties by index).
  */

@@ -53,6 +53,7 @@ int check_params(const sift3d_params *p)
     if (!(p->dog_threshold >= 0.0f) || p->votes < 1 || p->votes > 80) return SIFT3D_E_ARG;
     if (p->brief_n < 0 || p->brief_n > kMaxPairs || p->brief_n % 64 != 0) return SIFT3D_E_ARG;
     if (p->brief_blur < 0.0 || !(p->siftrank_factor > 0.0)) return SIFT3D_E_ARG;
+    if (p->pyramid_mode < 0 || p->pyramid_mode > 2) return SIFT3D_E_ARG;
     // kernel limits
     const double top = scale_sigma(*p, p->scales + 2);
     const double prev = scale_sigma(*p, p->scales + 1);
@@ -129,6 +130,90 @@ void set_z_job(ZArgs &a, int j, const OctaveGeom &g, const OctaveGeom *sub)
     jb.block0 = j == 0 ? 0 : a.job[j - 1].block0 + a.job[j - 1].gx * a.job[j - 1].gy * a.job[j - 1].gz;
 }
 
+int pass_index(const sift3d_plan *pl, int o, int level)
+{
+    for (size_t b = 0; b < pl->blur.size(); ++b)
+        if (pl->blur[b].octave == o && pl->blur[b].dst_idx == level) return (int)b;
+    return -1;
+}
+
+// List scheduler: alternating xy and z launches, each holding every split
+// task whose inputs are ready (at most kMaxJobs jobs and kMaxTapSets tap
+// sets per launch); fused passes are launches of their own.
+void build_schedule(sift3d_plan *pl)
+{
+    const int S = pl->S;
+    pl->tasks.clear();
+    pl->sched.clear();
+    for (size_t b = 0; b < pl->blur.size(); ++b) pl->tasks.push_back(Task{0, (int)b, pl->blur[b].octave, 0});
+    if (pl->brief_rb >= 0)
+        for (int o = 0; o < pl->n_oct; ++o)
+            for (int s = 1; s <= S; ++s) pl->tasks.push_back(Task{1, -1, o, s});
+    const int nt = (int)pl->tasks.size();
+    std::vector<char> xy_done(nt, 0), done(nt, 0);
+    std::vector<int> task_of_pass(pl->blur.size(), -1);
+    for (int t = 0; t < nt; ++t)
+        if (pl->tasks[t].kind == 0) task_of_pass[pl->tasks[t].pass] = t;
+    auto pass_done = [&](int o, int level) {
+        const int b = pass_index(pl, o, level);
+        return b >= 0 && done[task_of_pass[b]];
+    };
+    auto ready = [&](int t) {
+        const Task &k = pl->tasks[t];
+        if (k.kind == 1) return pass_done(k.octave, k.s);
+        const BlurLaunch &L = pl->blur[k.pass];
+        if (L.src_kind < 0) return true;
+        if (L.src_idx == 0 && L.octave > 0) return pass_done(L.octave - 1, S);  // G_0 from the sub-sample
+        return pass_done(L.octave, L.src_idx);
+    };
+    auto is_fused = [&](int t) { return pl->tasks[t].kind == 0 && pl->blur[pl->tasks[t].pass].fused; };
+    auto tapset_of = [&](int t) {
+        return pl->tasks[t].kind == 0 ? pl->blur[pl->tasks[t].pass].tapset : pl->brief_tapset;
+    };
+    auto emit = [&](int type, const std::vector<int> &ts) {
+        Step st{type, {}};
+        std::vector<int> sets;
+        for (int t : ts) {
+            const int id = tapset_of(t);
+            const bool known = std::find(sets.begin(), sets.end(), id) != sets.end();
+            if ((int)st.tasks.size() == kMaxJobs || (!known && (int)sets.size() == kMaxTapSets)) {
+                pl->sched.push_back(st);
+                st.tasks.clear();
+                sets.clear();
+            }
+            if (std::find(sets.begin(), sets.end(), id) == sets.end()) sets.push_back(id);
+            st.tasks.push_back(t);
+        }
+        if (!st.tasks.empty()) pl->sched.push_back(st);
+    };
+    int remaining = nt;
+    while (remaining > 0) {
+        bool progress = false;
+        for (int t = 0; t < nt; ++t)
+            if (!done[t] && is_fused(t) && ready(t)) {
+                pl->sched.push_back(Step{0, {t}});
+                done[t] = 1;
+                --remaining;
+                progress = true;
+            }
+        std::vector<int> xs;
+        for (int t = 0; t < nt; ++t)
+            if (!done[t] && !xy_done[t] && !is_fused(t) && ready(t)) xs.push_back(t);
+        emit(1, xs);
+        for (int t : xs) xy_done[t] = 1;
+        std::vector<int> zs;
+        for (int t = 0; t < nt; ++t)
+            if (!done[t] && xy_done[t]) zs.push_back(t);
+        emit(2, zs);
+        for (int t : zs) {
+            done[t] = 1;
+            --remaining;
+        }
+        if (!zs.empty()) progress = true;
+        if (!progress) break;  // not reachable for a well-formed pyramid
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -147,6 +232,7 @@ int sift3d_default_params(sift3d_params *p)
     p->brief_n = 256;
     p->brief_blur = 0.95;
     p->siftrank_factor = 2.0;
+    p->pyramid_mode = 0;
     return SIFT3D_OK;
 }
 
@@ -270,13 +356,26 @@ int sift3d_plan_create(sift3d_ctx *ctx, int nx, int ny, int nz, int kp_capacity,
         const double a = scale_sigma(p, i), b = scale_sigma(p, i - 1);
         pl->inc_sigma.push_back(std::sqrt(a * a - b * b));
     }
+    // tap sets: 0 = base blur, i = increment of G_i, S+3 = BRIEF pre-blur
+    auto add_taps = [&](double sigma) {
+        const std::vector<double> w = gaussian(sigma, p.trunc);
+        std::vector<float> f(kMaxTaps, 0.0f);
+        for (size_t t = 0; t < w.size(); ++t) f[t] = (float)w[t];
+        pl->tapsets.push_back(f);
+        pl->tapset_r.push_back((int)(w.size() - 1) / 2);
+    };
+    add_taps(pl->base_sigma);
+    for (int i = 1; i <= S + 2; ++i) add_taps(pl->inc_sigma[i - 1]);
+    add_taps(p.brief_blur);
+    pl->brief_tapset = S + 3;
+    pl->brief_rb = (p.brief_blur > 0.0 && p.brief_n > 0) ? pl->tapset_r[S + 3] : -1;
+
     for (int o = 0; o < pl->n_oct; ++o) {
         const OctaveGeom &g = pl->oct[o];
         for (int i = (o == 0 ? 0 : 1); i <= S + 2; ++i) {
-            const double sig = i == 0 ? pl->base_sigma : pl->inc_sigma[i - 1];
-            const std::vector<double> w = gaussian(sig, p.trunc);
             BlurLaunch L{};
-            L.r = (int)(w.size() - 1) / 2;
+            L.tapset = i;
+            L.r = pl->tapset_r[i];
             L.dog = i > 0;
             L.octave = o;
             L.src_kind = i == 0 ? -1 : 0;
@@ -284,7 +383,7 @@ int sift3d_plan_create(sift3d_ctx *ctx, int nx, int ny, int nz, int kp_capacity,
             L.dst_idx = i;
             L.dog_idx = i - 1;
             L.sub_octave = (i == S && o + 1 < pl->n_oct) ? o + 1 : -1;
-            L.fused = (long long)g.n >= kFusedMinVoxels;
+            L.fused = p.pyramid_mode == 1 || (p.pyramid_mode == 0 && (long long)g.n >= kFusedMinVoxels);
             if (L.fused) {
                 BlurArgs &a = L.a;
                 a.nx = g.nx;
@@ -300,27 +399,12 @@ int sift3d_plan_create(sift3d_ctx *ctx, int nx, int ny, int nz, int kp_capacity,
                 a.L = choose_slab(g.nz, a.tiles_x * a.tiles_y, L.r);
                 a.slabs = (g.nz + a.L - 1) / a.L;
                 a.n_blocks = a.tiles_x * a.tiles_y * a.slabs;
-                for (int t = 0; t < kMaxTaps; ++t) a.w[t] = t < (int)w.size() ? (float)w[t] : 0.0f;
-            } else {
-                const OctaveGeom *sub = L.sub_octave >= 0 ? &pl->oct[o + 1] : nullptr;
-                set_xy_job(L.xy, 0, g);
-                L.xy.n_jobs = 1;
-                L.xy.n_blocks = L.xy.job[0].block0 + xy_blocks(g);
-                set_z_job(L.z, 0, g, sub);
-                L.z.n_jobs = 1;
-                L.z.n_blocks = z_blocks(g);
-                for (int t = 0; t < kMaxTaps; ++t) L.xy.w[t] = L.z.w[t] = t < (int)w.size() ? (float)w[t] : 0.0f;
+                for (int t = 0; t < kMaxTaps; ++t) a.w[t] = pl->tapsets[i][t];
             }
             pl->blur.push_back(L);
         }
     }
-    // BRIEF pre-blur: B_s = G_s blurred by sigma_b (none when sigma_b == 0)
-    {
-        const std::vector<double> wb = gaussian(p.brief_blur, p.trunc);
-        pl->brief_rb = p.brief_blur > 0.0 ? (int)(wb.size() - 1) / 2 : -1;
-        pl->wb.assign(kMaxTaps, 0.0f);
-        for (size_t t = 0; t < wb.size(); ++t) pl->wb[t] = (float)wb[t];
-    }
+    build_schedule(pl);
     *out = pl;
     return SIFT3D_OK;
 }
@@ -378,74 +462,106 @@ static int check_ws(const sift3d_plan *plan, const void *ws, size_t bytes)
     return SIFT3D_OK;
 }
 
-static int run_pass(const sift3d_plan *plan, const BlurLaunch &L, const float *d_vol, void *d_ws, hipStream_t st)
+// Device pointers of a task's xy and z halves for one call.
+struct TaskPtrs {
+    const float *src;
+    float *t, *dst, *dog, *sub;
+    const OctaveGeom *g, *sub_g;
+    int r, tapset;
+};
+
+static TaskPtrs task_ptrs(const sift3d_plan *plan, const Task &k, const float *d_vol, const void *d_ws)
 {
-    const float *src = L.src_kind < 0 ? d_vol : level_ptr(plan, d_ws, L.octave, 0, L.src_idx);
-    float *dst = level_ptr(plan, d_ws, L.octave, 0, L.dst_idx);
-    float *dog = L.dog ? level_ptr(plan, d_ws, L.octave, 1, L.dog_idx) : nullptr;
-    float *sub = L.sub_octave >= 0 ? level_ptr(plan, d_ws, L.sub_octave, 0, 0) : nullptr;
-    hipError_t e;
-    if (L.fused) {
-        BlurArgs a = L.a;
-        a.src = src;
-        a.dst = dst;
-        a.dog = dog;
-        a.sub = sub;
-        e = launch_blur(a, L.r, L.dog, st);
+    TaskPtrs q{};
+    const int S = plan->S;
+    if (k.kind == 0) {
+        const BlurLaunch &L = plan->blur[k.pass];
+        q.src = L.src_kind < 0 ? d_vol : level_ptr(plan, d_ws, L.octave, 0, L.src_idx);
+        q.t = raw_level(plan, d_ws, L.octave, lev_T(S));
+        q.dst = level_ptr(plan, d_ws, L.octave, 0, L.dst_idx);
+        q.dog = L.dog ? level_ptr(plan, d_ws, L.octave, 1, L.dog_idx) : nullptr;
+        q.sub = L.sub_octave >= 0 ? level_ptr(plan, d_ws, L.sub_octave, 0, 0) : nullptr;
+        q.g = &plan->oct[L.octave];
+        q.sub_g = L.sub_octave >= 0 ? &plan->oct[L.sub_octave] : nullptr;
+        q.r = L.r;
+        q.tapset = L.tapset;
     } else {
-        float *t = raw_level(plan, d_ws, L.octave, lev_T(plan->S));
-        XYArgs xy = L.xy;
-        xy.job[0].src = src;
-        xy.job[0].dst = t;
-        e = launch_blur_xy(xy, L.r, st);
-        if (e == hipSuccess) {
-            ZArgs z = L.z;
-            z.job[0].t = t;
-            z.job[0].center = src;
-            z.job[0].dst = dst;
-            z.job[0].dog = dog;
-            z.job[0].sub = sub;
-            e = launch_blur_z(z, L.r, L.dog, st);
-        }
+        q.src = raw_level(plan, d_ws, k.octave, lev_G(k.s));
+        q.t = raw_level(plan, d_ws, k.octave, lev_Tb(S, k.s));
+        q.dst = raw_level(plan, d_ws, k.octave, lev_B(S, k.s));
+        q.dog = nullptr;
+        q.sub = nullptr;
+        q.g = &plan->oct[k.octave];
+        q.sub_g = nullptr;
+        q.r = plan->brief_rb;
+        q.tapset = plan->brief_tapset;
     }
-    return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
+    return q;
 }
 
-// B_s = G_s blurred by the BRIEF pre-blur, for every octave and s = 1..S,
-// as job lists of at most kMaxJobs (octave, s) levels per launch pair.
-static int run_preblur(const sift3d_plan *plan, const void *d_ws, hipStream_t st)
+extern "C++" {
+// Tap-set slot of a launch (deduplicated, at most kMaxTapSets per launch).
+template <typename Args>
+static int tap_slot(const sift3d_plan *plan, Args &a, std::vector<int> &sets, int tapset)
 {
-    if (plan->brief_rb < 0) return SIFT3D_OK;
-    const int S = plan->S;
-    std::vector<std::pair<int, int>> jobs;
-    for (int o = 0; o < plan->n_oct; ++o)
-        for (int s = 1; s <= S; ++s) jobs.emplace_back(o, s);
-    for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxJobs) {
-        XYArgs xy{};
-        ZArgs z{};
-        const int nj = (int)std::min<size_t>(kMaxJobs, jobs.size() - j0);
-        for (int j = 0; j < nj; ++j) {
-            const int o = jobs[j0 + j].first, s = jobs[j0 + j].second;
-            const OctaveGeom &g = plan->oct[o];
-            set_xy_job(xy, j, g);
-            xy.job[j].src = raw_level(plan, d_ws, o, lev_G(s));
-            xy.job[j].dst = raw_level(plan, d_ws, o, lev_Tb(S, s));
-            set_z_job(z, j, g, nullptr);
-            z.job[j].t = xy.job[j].dst;
-            z.job[j].center = nullptr;
-            z.job[j].dst = raw_level(plan, d_ws, o, lev_B(S, s));
-            z.job[j].dog = nullptr;
-            z.job[j].sub = nullptr;
+    for (size_t i = 0; i < sets.size(); ++i)
+        if (sets[i] == tapset) return (int)i;
+    const int slot = (int)sets.size();
+    sets.push_back(tapset);
+    for (int t = 0; t < kMaxTaps; ++t) a.w[slot][t] = plan->tapsets[tapset][t];
+    return slot;
+}
+}  // extern "C++"
+
+static int run_step(const sift3d_plan *plan, int type, const std::vector<int> &tasks, const float *d_vol,
+                    void *d_ws, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    if (type == 0) {
+        const BlurLaunch &L = plan->blur[plan->tasks[tasks[0]].pass];
+        BlurArgs a = L.a;
+        a.src = L.src_kind < 0 ? d_vol : level_ptr(plan, d_ws, L.octave, 0, L.src_idx);
+        a.dst = level_ptr(plan, d_ws, L.octave, 0, L.dst_idx);
+        a.dog = L.dog ? level_ptr(plan, d_ws, L.octave, 1, L.dog_idx) : nullptr;
+        a.sub = L.sub_octave >= 0 ? level_ptr(plan, d_ws, L.sub_octave, 0, 0) : nullptr;
+        e = launch_blur(a, L.r, L.dog, st);
+    } else if (type == 1) {
+        XYArgs a{};
+        std::vector<int> sets;
+        int j = 0;
+        for (int t : tasks) {
+            const TaskPtrs q = task_ptrs(plan, plan->tasks[t], d_vol, d_ws);
+            set_xy_job(a, j, *q.g);
+            a.job[j].src = q.src;
+            a.job[j].dst = q.t;
+            a.job[j].r = q.r;
+            a.job[j].taps = tap_slot(plan, a, sets, q.tapset);
+            ++j;
         }
-        xy.n_jobs = z.n_jobs = nj;
-        xy.n_blocks = xy.job[nj - 1].block0 + xy_blocks(plan->oct[jobs[j0 + nj - 1].first]);
-        z.n_blocks = z.job[nj - 1].block0 + z_blocks(plan->oct[jobs[j0 + nj - 1].first]);
-        for (int t = 0; t < kMaxTaps; ++t) xy.w[t] = z.w[t] = plan->wb[t];
-        hipError_t e = launch_blur_xy(xy, plan->brief_rb, st);
-        if (e == hipSuccess) e = launch_blur_z(z, plan->brief_rb, false, st);
-        if (e != hipSuccess) return hip_fail(e);
+        a.n_jobs = j;
+        a.n_blocks = a.job[j - 1].block0 + a.job[j - 1].tiles_x * a.job[j - 1].tiles_y * a.job[j - 1].nz;
+        e = launch_blur_xy(a, st);
+    } else {
+        ZArgs a{};
+        std::vector<int> sets;
+        int j = 0;
+        for (int t : tasks) {
+            const TaskPtrs q = task_ptrs(plan, plan->tasks[t], d_vol, d_ws);
+            set_z_job(a, j, *q.g, q.sub_g);
+            a.job[j].t = q.t;
+            a.job[j].center = q.src;
+            a.job[j].dst = q.dst;
+            a.job[j].dog = q.dog;
+            a.job[j].sub = q.sub;
+            a.job[j].r = q.r;
+            a.job[j].taps = tap_slot(plan, a, sets, q.tapset);
+            ++j;
+        }
+        a.n_jobs = j;
+        a.n_blocks = a.job[j - 1].block0 + a.job[j - 1].gx * a.job[j - 1].gy * a.job[j - 1].gz;
+        e = launch_blur_z(a, st);
     }
-    return SIFT3D_OK;
+    return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }
 
 int sift3d_build_pyramid(const sift3d_plan *plan, const float *d_vol, void *d_ws, size_t ws_bytes, void *stream)
@@ -453,8 +569,8 @@ int sift3d_build_pyramid(const sift3d_plan *plan, const float *d_vol, void *d_ws
     int rc = check_ws(plan, d_ws, ws_bytes);
     if (rc != SIFT3D_OK) return rc;
     if (d_vol == nullptr) return SIFT3D_E_ARG;
-    for (const BlurLaunch &L : plan->blur) {
-        rc = run_pass(plan, L, d_vol, d_ws, static_cast<hipStream_t>(stream));
+    for (const Step &stp : plan->sched) {
+        rc = run_step(plan, stp.type, stp.tasks, d_vol, d_ws, static_cast<hipStream_t>(stream));
         if (rc != SIFT3D_OK) return rc;
     }
     return SIFT3D_OK;
@@ -467,7 +583,7 @@ int sift3d_pyramid_pass_count(const sift3d_plan *plan, int *n_passes)
     return SIFT3D_OK;
 }
 
-int sift3d_pyramid_pass_info(const sift3d_plan *plan, int pass, int info[4], size_t *bytes)
+int sift3d_pyramid_pass_info(const sift3d_plan *plan, int pass, int info[5], size_t *bytes)
 {
     if (plan == nullptr || pass < 0 || pass >= (int)plan->blur.size()) return SIFT3D_E_ARG;
     const BlurLaunch &L = plan->blur[pass];
@@ -476,6 +592,7 @@ int sift3d_pyramid_pass_info(const sift3d_plan *plan, int pass, int info[4], siz
         info[1] = L.dst_idx;
         info[2] = L.r;
         info[3] = L.sub_octave >= 0 ? 1 : 0;
+        info[4] = L.fused ? 1 : 0;
     }
     if (bytes != nullptr) {
         const size_t n = plan->oct[L.octave].n;
@@ -494,7 +611,15 @@ int sift3d_pyramid_pass(const sift3d_plan *plan, int pass, const float *d_vol, v
     if (pass < 0 || pass >= (int)plan->blur.size()) return SIFT3D_E_ARG;
     const BlurLaunch &L = plan->blur[pass];
     if (L.src_kind < 0 && d_vol == nullptr) return SIFT3D_E_ARG;
-    return run_pass(plan, L, d_vol, d_ws, static_cast<hipStream_t>(stream));
+    int t = -1;
+    for (size_t k = 0; k < plan->tasks.size(); ++k)
+        if (plan->tasks[k].kind == 0 && plan->tasks[k].pass == pass) t = (int)k;
+    const std::vector<int> one{t};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (L.fused) return run_step(plan, 0, one, d_vol, d_ws, st);
+    rc = run_step(plan, 1, one, d_vol, d_ws, st);
+    if (rc != SIFT3D_OK) return rc;
+    return run_step(plan, 2, one, d_vol, d_ws, st);
 }
 
 int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_keypoint *d_kp, int kp_capacity,
@@ -580,10 +705,6 @@ int sift3d_describe(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes, 
     a.rrief = d_rrief;
     a.brief_n = p.brief_n;
     a.pairs = plan->ctx->d_offsets;
-    if (d_brief != nullptr || d_rrief != nullptr) {
-        rc = run_preblur(plan, d_ws, static_cast<hipStream_t>(stream));
-        if (rc != SIFT3D_OK) return rc;
-    }
     const int grid = std::min(kp_capacity, 4096);
     const hipError_t e = launch_describe(a, grid, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);

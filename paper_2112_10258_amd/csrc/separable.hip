@@ -4,14 +4,17 @@
 //   xy launch: per (plane, 64x16 tile), stage the (16+2R) x (64+2R) halo
 //              tile in LDS, blur along x into a second LDS tile, then along
 //              y, write the xy-blurred plane T;
-//   z launch:  per (32x8 columns, 8 output planes), slide a register window
-//              of 8+2R samples of T down each column, blur along z, and
+//   z launch:  per (32x8 columns, 16 output planes), slide a register window
+//              of 16+2R samples of T down each column, blur along z, and
 //              write G, optionally D = centre - G and the 2x2x2 mean of G.
 // Neither launch has a serial plane chain, so every block finishes in a
 // few microseconds; the price is the T round trip through the cache.
 //
-// Both launches take a list of jobs (one per volume/level) that share the
-// tap radius, so several levels or volumes are processed by one launch.
+// Both launches take a list of jobs (levels of one or several volumes or
+// octaves) that may differ in tap radius: each block reads its job and
+// branches once to the body compiled for that radius. Independent levels
+// (later levels of octave o, early levels of octave o+1, BRIEF pre-blurs)
+// therefore share launches.
 #include "sift3d_internal.h"
 
 namespace s3d {
@@ -41,7 +44,7 @@ __device__ __forceinline__ int find_job(const Args &a, int bid)
 }
 
 template <int R>
-__global__ void __launch_bounds__(kXYThreads) blur_xy_kernel(const XYArgs a)
+__device__ __forceinline__ void xy_body(const float *__restrict__ wt, const XYJob &jb, int local, float *smem)
 {
     constexpr int TX = kXYTX, TY = kXYTY, NT = kXYThreads, M = 2 * R + 1;
     constexpr int NYo = TX * TY / NT;               // y outputs per thread
@@ -51,12 +54,9 @@ __global__ void __launch_bounds__(kXYThreads) blur_xy_kernel(const XYArgs a)
     constexpr int AE = AH * AWL;
     constexpr int XQ = TX / 4;
     constexpr int XIN = 4 + ((2 * R + 3) & ~3);
-    __shared__ __align__(16) float A[AH * AW];
-    __shared__ __align__(16) float B[AH * TX];
+    float *A = smem;                                // [AH][AW]
+    float *B = smem + AH * AW;                      // [AH][TX]
 
-    const int j = find_job(a, blockIdx.x);
-    const XYJob &jb = a.job[j];
-    const int local = blockIdx.x - jb.block0;
     const int ntile = jb.tiles_x * jb.tiles_y;
     const int z = local / ntile;
     const int t2 = local - z * ntile;
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(kXYThreads) blur_xy_kernel(const XYArgs a)
 
     float w[M];
 #pragma unroll
-    for (int t = 0; t < M; ++t) w[t] = a.w[t];
+    for (int t = 0; t < M; ++t) w[t] = wt[t];
 
     for (int idx = tid; idx < AE; idx += NT) {
         const int r = idx / AWL, c = idx - r * AWL;
@@ -107,14 +107,11 @@ __global__ void __launch_bounds__(kXYThreads) blur_xy_kernel(const XYArgs a)
     }
 }
 
-template <int R, bool DOG>
-__global__ void __launch_bounds__(kZThreads) blur_z_kernel(const ZArgs a)
+template <int R>
+__device__ __forceinline__ void z_body(const float *__restrict__ wt, const ZJob &jb, int local)
 {
     constexpr int ZS = kZPlanes, M = 2 * R + 1, WN = ZS + 2 * R;
     static_assert(ZS % 2 == 0, "sub-sampling pairs planes inside a thread");
-    const int j = find_job(a, blockIdx.x);
-    const ZJob &jb = a.job[j];
-    const int local = blockIdx.x - jb.block0;
     const int gxy = jb.gx * jb.gy;
     const int bz = local / gxy;
     const int t2 = local - bz * gxy;
@@ -129,7 +126,7 @@ __global__ void __launch_bounds__(kZThreads) blur_z_kernel(const ZArgs a)
 
     float w[M];
 #pragma unroll
-    for (int t = 0; t < M; ++t) w[t] = a.w[t];
+    for (int t = 0; t < M; ++t) w[t] = wt[t];
     float win[WN];
 #pragma unroll
     for (int q = 0; q < WN; ++q) win[q] = jb.t[(size_t)clampi(z0 - R + q, 0, nz - 1) * nxy + col];
@@ -144,7 +141,7 @@ __global__ void __launch_bounds__(kZThreads) blur_z_kernel(const ZArgs a)
         if (in_xy && z < nz) {
             const size_t i = (size_t)z * nxy + col;
             jb.dst[i] = g[k];
-            if constexpr (DOG) jb.dog[i] = jb.center[i] - g[k];
+            if (jb.dog != nullptr) jb.dog[i] = jb.center[i] - g[k];
         }
     }
     if (jb.sub != nullptr) {
@@ -160,61 +157,77 @@ __global__ void __launch_bounds__(kZThreads) blur_z_kernel(const ZArgs a)
     }
 }
 
-template <int R>
-hipError_t launch_xy_r(const XYArgs &a, hipStream_t st)
+#define S3D_RADIUS_CASES(BODY) \
+    case 0: BODY(0); break;    \
+    case 1: BODY(1); break;    \
+    case 2: BODY(2); break;    \
+    case 3: BODY(3); break;    \
+    case 4: BODY(4); break;    \
+    case 5: BODY(5); break;    \
+    case 6: BODY(6); break;    \
+    case 7: BODY(7); break;    \
+    case 8: BODY(8); break;    \
+    case 9: BODY(9); break;    \
+    case 10: BODY(10); break;  \
+    case 11: BODY(11); break;  \
+    case 12: BODY(12); break;  \
+    case 13: BODY(13); break;  \
+    case 14: BODY(14); break;  \
+    case 15: BODY(15); break;  \
+    case 16: BODY(16); break;  \
+    default: break;
+
+__global__ void __launch_bounds__(kXYThreads) blur_xy_kernel(const XYArgs a)
 {
-    hipLaunchKernelGGL((blur_xy_kernel<R>), dim3(a.n_blocks), dim3(kXYThreads), 0, st, a);
-    return hipGetLastError();
+    extern __shared__ __align__(16) float smem[];
+    const int j = find_job(a, blockIdx.x);
+    const XYJob jb = a.job[j];
+    const float *wt = a.w[jb.taps];
+    const int local = blockIdx.x - jb.block0;
+#define S3D_XY(R) xy_body<R>(wt, jb, local, smem)
+    switch (jb.r) { S3D_RADIUS_CASES(S3D_XY) }
+#undef S3D_XY
 }
 
-template <int R>
-hipError_t launch_z_r(const ZArgs &a, bool dog, hipStream_t st)
+__global__ void __launch_bounds__(kZThreads) blur_z_kernel(const ZArgs a)
 {
-    if (dog)
-        hipLaunchKernelGGL((blur_z_kernel<R, true>), dim3(a.n_blocks), dim3(kZThreads), 0, st, a);
-    else
-        hipLaunchKernelGGL((blur_z_kernel<R, false>), dim3(a.n_blocks), dim3(kZThreads), 0, st, a);
-    return hipGetLastError();
+    const int j = find_job(a, blockIdx.x);
+    const ZJob jb = a.job[j];
+    const float *wt = a.w[jb.taps];
+    const int local = blockIdx.x - jb.block0;
+#define S3D_Z(R) z_body<R>(wt, jb, local)
+    switch (jb.r) { S3D_RADIUS_CASES(S3D_Z) }
+#undef S3D_Z
 }
 
 }  // namespace
 
-#define S3D_RADIUS_SWITCH(r, CALL)   \
-    switch (r) {                     \
-    case 0: return CALL(0);          \
-    case 1: return CALL(1);          \
-    case 2: return CALL(2);          \
-    case 3: return CALL(3);          \
-    case 4: return CALL(4);          \
-    case 5: return CALL(5);          \
-    case 6: return CALL(6);          \
-    case 7: return CALL(7);          \
-    case 8: return CALL(8);          \
-    case 9: return CALL(9);          \
-    case 10: return CALL(10);        \
-    case 11: return CALL(11);        \
-    case 12: return CALL(12);        \
-    case 13: return CALL(13);        \
-    case 14: return CALL(14);        \
-    case 15: return CALL(15);        \
-    case 16: return CALL(16);        \
-    default: return hipErrorInvalidValue; \
-    }
-
-hipError_t launch_blur_xy(const XYArgs &a, int r, hipStream_t st)
+// LDS bytes of the xy body for radius r.
+static size_t xy_lds_bytes(int r)
 {
-    if (a.n_blocks <= 0) return hipSuccess;
-#define S3D_XY(R) launch_xy_r<R>(a, st)
-    S3D_RADIUS_SWITCH(r, S3D_XY)
-#undef S3D_XY
+    const int aw = (kXYTX + 2 * r + 3) & ~3, ah = kXYTY + 2 * r;
+    return (size_t)(ah * aw + ah * kXYTX) * sizeof(float);
 }
 
-hipError_t launch_blur_z(const ZArgs &a, int r, bool dog, hipStream_t st)
+hipError_t launch_blur_xy(const XYArgs &a, hipStream_t st)
 {
     if (a.n_blocks <= 0) return hipSuccess;
-#define S3D_Z(R) launch_z_r<R>(a, dog, st)
-    S3D_RADIUS_SWITCH(r, S3D_Z)
-#undef S3D_Z
+    size_t lds = 0;
+    for (int j = 0; j < a.n_jobs; ++j) {
+        if (a.job[j].r < 0 || a.job[j].r > kMaxR) return hipErrorInvalidValue;
+        lds = lds > xy_lds_bytes(a.job[j].r) ? lds : xy_lds_bytes(a.job[j].r);
+    }
+    hipLaunchKernelGGL(blur_xy_kernel, dim3(a.n_blocks), dim3(kXYThreads), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_blur_z(const ZArgs &a, hipStream_t st)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+    for (int j = 0; j < a.n_jobs; ++j)
+        if (a.job[j].r < 0 || a.job[j].r > kMaxR) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(blur_z_kernel, dim3(a.n_blocks), dim3(kZThreads), 0, st, a);
+    return hipGetLastError();
 }
 
 }  // namespace s3d

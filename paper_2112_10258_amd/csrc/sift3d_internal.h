@@ -60,38 +60,46 @@ struct BlurArgs {
     float w[kMaxTaps];    // taps w[t + r], t = -r..r
 };
 
+constexpr int kMaxTapSets = 8;              // distinct tap sets per xy / z launch
+
+// One job of an xy or z launch: one level of one volume. Jobs of one launch
+// may have different tap radii; each block dispatches on its job's radius.
 struct XYJob {
     const float *src;
     float *dst;
     int nx, ny, nz;
     int tiles_x, tiles_y;
     int block0;           // first block of this job in the launch
+    int r;                // tap radius
+    int taps;             // index into XYArgs::w
 };
 
 struct XYArgs {
     XYJob job[kMaxJobs];
     int n_jobs;
     int n_blocks;
-    float w[kMaxTaps];
+    float w[kMaxTapSets][kMaxTaps];
 };
 
 struct ZJob {
     const float *t;       // xy-blurred input
-    const float *center;  // level the DoG subtracts from (DoG launches)
+    const float *center;  // level the DoG subtracts from (when dog != nullptr)
     float *dst;
-    float *dog;
+    float *dog;           // or nullptr
     float *sub;           // or nullptr
     int nx, ny, nz;
     int mx, my, mz;
     int gx, gy, gz;       // blocks per axis
     int block0;
+    int r;
+    int taps;
 };
 
 struct ZArgs {
     ZJob job[kMaxJobs];
     int n_jobs;
     int n_blocks;
-    float w[kMaxTaps];
+    float w[kMaxTapSets][kMaxTaps];
 };
 
 struct DetOctave {
@@ -159,14 +167,28 @@ struct OctaveGeom {
 struct BlurLaunch {
     int r;
     bool dog;
-    bool fused;           // fused streaming pass, else xy + z launches
+    bool fused;           // fused streaming pass, else xy + z jobs
     BlurArgs a;           // fused geometry (pointers bound per call)
-    XYArgs xy;            // split geometry (pointers bound per call)
-    ZArgs z;
+    int tapset;           // index into sift3d_plan::tapsets
     int src_kind;         // -1 = input volume, 0 = G level of the octave
     int src_idx, dst_idx, dog_idx;
     int octave;
     int sub_octave;       // -1 = no sub-sample output
+};
+
+// A unit of work of the pyramid schedule: a level pass (index into
+// sift3d_plan::blur) or the BRIEF pre-blur of G_s of one octave.
+struct Task {
+    int kind;             // 0 = level pass, 1 = pre-blur
+    int pass;             // level pass index (kind 0)
+    int octave, s;        // pre-blur target (kind 1)
+};
+
+// One launch of the schedule: a fused pass, or the xy / z half of a set of
+// split tasks.
+struct Step {
+    int type;             // 0 = fused pass, 1 = xy launch, 2 = z launch
+    std::vector<int> tasks;
 };
 
 }  // namespace s3d
@@ -190,9 +212,13 @@ struct sift3d_plan {
     size_t ws_bytes;
     long long total_rows;
     int det_blocks;
-    std::vector<s3d::BlurLaunch> blur;  // in launch order
+    std::vector<s3d::BlurLaunch> blur;  // level passes in dependency order
     int brief_rb;                       // pre-blur radius (-1: none, B_s = G_s)
-    std::vector<float> wb;              // pre-blur taps
+    int brief_tapset;
+    std::vector<std::vector<float>> tapsets;  // kMaxTaps floats each
+    std::vector<int> tapset_r;
+    std::vector<s3d::Task> tasks;
+    std::vector<s3d::Step> sched;       // launches of sift3d_build_pyramid
     double base_sigma;
     std::vector<double> inc_sigma;      // G_1..G_{S+2}
 };
@@ -202,8 +228,8 @@ namespace s3d {
 hipError_t launch_blur(const BlurArgs &a, int r, bool dog, hipStream_t st);
 hipError_t launch_detect(const DetectArgs &a, hipStream_t st);
 hipError_t launch_describe(const DescribeArgs &a, int grid, hipStream_t st);
-hipError_t launch_blur_xy(const XYArgs &a, int r, hipStream_t st);
-hipError_t launch_blur_z(const ZArgs &a, int r, bool dog, hipStream_t st);
+hipError_t launch_blur_xy(const XYArgs &a, hipStream_t st);
+hipError_t launch_blur_z(const ZArgs &a, hipStream_t st);
 
 // Workspace levels of an octave, in units of one padded level.
 inline int lev_G(int i) { return i; }

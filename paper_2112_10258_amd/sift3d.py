@@ -39,6 +39,7 @@ class Params(ctypes.Structure):
         ("brief_n", ctypes.c_int),
         ("brief_blur", ctypes.c_double),
         ("siftrank_factor", ctypes.c_double),
+        ("pyramid_mode", ctypes.c_int),
     ]
 
 
@@ -214,16 +215,16 @@ class Plan:
                                             _vp(_stream(stream))), "sift3d_build_pyramid")
 
     def pyramid_passes(self):
-        """[(octave, level, radius, writes_sub, algorithmic_bytes)] in launch order."""
+        """[(octave, level, radius, writes_sub, algorithmic_bytes, fused)] in dependency order."""
         lib = _load()
         n = ctypes.c_int()
         _check(lib.sift3d_pyramid_pass_count(self.handle, ctypes.byref(n)), "sift3d_pyramid_pass_count")
         out = []
         for i in range(n.value):
-            info = (ctypes.c_int * 4)()
+            info = (ctypes.c_int * 5)()
             b = ctypes.c_size_t()
             _check(lib.sift3d_pyramid_pass_info(self.handle, i, info, ctypes.byref(b)), "sift3d_pyramid_pass_info")
-            out.append((info[0], info[1], info[2], info[3], b.value))
+            out.append((info[0], info[1], info[2], info[3], b.value, info[4]))
         return out
 
     def pyramid_pass(self, i, vol, ws, stream=None):

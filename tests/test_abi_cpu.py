@@ -41,7 +41,7 @@ def test_default_params_and_error_strings():
     lib = S.sift3d._load()
     for code in (0, -1, -2, -3, -5, -6):
         assert lib.sift3d_error_string(code)
-    assert ctypes.sizeof(S.Params) == 72
+    assert ctypes.sizeof(S.Params) == 80
 
 
 def test_pair_offsets_host_function_matches_oracle():
@@ -56,7 +56,8 @@ def test_pair_offsets_host_function_matches_oracle():
 def test_bad_params_rejected():
     import paper_2112_10258_amd as S
     draws = P.pair_draws()
-    for kw in (dict(brief_n=100), dict(votes=0), dict(votes=81), dict(scales=0), dict(min_dim=2)):
+    for kw in (dict(brief_n=100), dict(votes=0), dict(votes=81), dict(scales=0), dict(min_dim=2),
+               dict(pyramid_mode=3)):
         with pytest.raises(S.Sift3dError) as ei:
             S.pair_offsets(S.default_params(**kw), draws, 1)
         assert ei.value.code == -1

@@ -27,10 +27,15 @@ def _vol(name):
         return P.noise_blob_volume((45, 38, 53), 21, n_blobs=10, margin=6), dict(min_dim=8)
     if name == "flat":
         return P.noise_blob_volume((70, 33, 34), 22, n_blobs=6, margin=6), dict(min_dim=8)
+    if name == "config1_fused":
+        # the fused streaming pass on every octave
+        return P.config1(), dict(n_octaves=2, pyramid_mode=1)
+    if name == "ragged_fused":
+        return P.noise_blob_volume((45, 38, 53), 21, n_blobs=10, margin=6), dict(min_dim=8, pyramid_mode=1)
     raise KeyError(name)
 
 
-CASES = ["config1", "ragged", "flat", "config2"]
+CASES = ["config1", "ragged", "flat", "config2", "config1_fused", "ragged_fused"]
 _cache = {}
 
 
@@ -100,7 +105,7 @@ def test_descriptors_stagewise(name):
     print(f"[parity] {name}: siftrank rows differing (excused) {bad_sr}, brief bits differing {int(diff.sum())}")
 
 
-@pytest.mark.parametrize("name", ["config1", "ragged", "config2"])
+@pytest.mark.parametrize("name", ["config1", "ragged", "config2", "config1_fused"])
 def test_end_to_end_keypoints(name):
     vol, g, p, ref = _run(name)
     want = O.detect([oc.D for oc in ref], p)
