@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -74,6 +76,58 @@ def read_traffic(workload):
     return None if w is None else w.get("hbm_bytes_per_launch")
 
 
+def batch_vs_plain(steps, stream):
+    """32 mixed-size volumes (each axis U{96..192}): one batch-plan call per step
+    against 32 one-volume calls per step. Inputs resident in HBM."""
+    import torch
+
+    import paper_2112_10258_amd as S
+    from gen import phantoms as P
+    vols = P.config3()
+    shapes = [(v.shape[2], v.shape[1], v.shape[0]) for v in vols]
+    cap = 1 << 14
+    ctx = S.Context(S.default_params(), P.pair_draws())
+    bplan = S.Plan(ctx, shapes, cap, batch=True)
+    bbuf = S.Buffers(bplan)
+    packed = bplan.pack_volumes(vols)
+    plain = []
+    for v, sh in zip(vols, shapes):
+        pl = S.Plan(ctx, sh, cap)
+        plain.append((pl, S.Buffers(pl), torch.from_numpy(v).cuda()))
+
+    def batched():
+        S.run_extract(bplan, packed, bbuf, stream=stream)
+
+    def one_by_one():
+        for pl, b, dv in plain:
+            S.run_extract(pl, dv, b, stream=stream)
+
+    for _ in range(2):
+        batched()
+        one_by_one()
+    torch.cuda.synchronize()
+    ms_b = time_calls(batched, steps, stream)
+    ms_p = time_calls(one_by_one, steps, stream)
+    n = len(vols)
+    counts_b = bbuf.count.cpu().tolist()
+    counts_p = [int(b.count.item()) for _, b, _ in plain]
+    vox = sum(int(np.prod(sh)) for sh in shapes)
+    del bbuf, plain
+    torch.cuda.empty_cache()
+    return {
+        "workload": "config3: 32 smoothed-noise + blob volumes, each axis U{96..192}",
+        "volumes": n,
+        "voxels": vox,
+        "batched_ms_per_call": round(ms_b, 4),
+        "batched_volumes_per_s": round(n * 1000.0 / ms_b, 1),
+        "plain_ms_for_all": round(ms_p, 4),
+        "plain_volumes_per_s": round(n * 1000.0 / ms_p, 1),
+        "batched_vs_plain": round(ms_p / ms_b, 3),
+        "keypoints_total": int(sum(counts_b)),
+        "same_counts_as_plain": counts_b == counts_p,
+    }
+
+
 def cpu_baseline(vol, kw, budget_s):
     import oracle as O
     from gen import phantoms as P
@@ -100,13 +154,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=20)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--batch-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); volumes are independent, "
               "a multi-GPU run would be N copies of this one", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2112_10258_amd as S
@@ -155,7 +210,7 @@ def main():
         pass_ms.append(time_calls(lambda i=i: plan.pyramid_pass(i, dvol, buf.ws, stream), reps, stream))
     log("[bench] stages ms: pyramid %.4f detect %.4f siftrank %.4f brief+rrief %.4f"
         % (st_pyr, st_det, st_sr, st_br))
-    for (o, lev, r, sub, b, fused), t in zip(passes, pass_ms):
+    for (o, lev, r, sub, b, fused, vv), t in zip(passes, pass_ms):
         log(f"[bench]   pass o={o} G{lev} r={r} sub={sub}: {t * 1e3:.2f} us, {b / t / 1e6:.0f} GB/s algorithmic")
 
     # roofline of the blur/DoG pass: octave-0 incremental passes (G_1..G_{S+2})
@@ -177,6 +232,13 @@ def main():
         "bytes_per_launch": int(bytes_per_launch),
         "avg_launch_us": round(dur_ms * 1e3, 3),
     }
+
+    batch = None
+    if not args.no_batch:
+        del buf
+        torch.cuda.empty_cache()
+        batch = batch_vs_plain(args.batch_steps, stream)
+        log(f"[bench] batch: {batch}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -207,6 +269,7 @@ def main():
         "stages_ms": {"pyramid": round(st_pyr, 4), "detect": round(st_det, 4), "siftrank": round(st_sr, 4),
                       "brief_rrief": round(st_br, 4)},
         "roofline": roofline,
+        "batch": batch,
         "cpu_baseline": cpu,
         "paper_context": "paper: 1.4 s CPU, 0.2 s GPU per 145x174x145 volume (~3000 keypoints, hardware unnamed)",
     }

@@ -39,7 +39,8 @@ enum {
     SIFT3D_E_TOO_SMALL = -2,  /* volume gives no octave (min dim < min_dim) */
     SIFT3D_E_WORKSPACE = -3,  /* workspace smaller than the plan needs      */
     SIFT3D_E_HIP = -5,        /* a HIP runtime call failed                  */
-    SIFT3D_E_UNSUPPORTED = -6 /* parameter outside what the kernels support */
+    SIFT3D_E_UNSUPPORTED = -6, /* parameter outside what the kernels support */
+    SIFT3D_PENDING = 1         /* sift3d_server_result: not finished yet   */
 };
 
 /* Method parameters. sift3d_default_params() fills the defaults in []. */
@@ -95,6 +96,9 @@ int sift3d_default_params(sift3d_params *p);
 int sift3d_create(const sift3d_params *p, const double *pair_draws, int n_draws, sift3d_ctx **out);
 int sift3d_destroy(sift3d_ctx *ctx);
 
+/* Copy of the parameters a context was created with. */
+int sift3d_ctx_params(const sift3d_ctx *ctx, sift3d_params *out);
+
 /*
  * Integer pair offsets of scale s (1..S) that a context built from the same
  * parameters and draws uses: out is [brief_n][2][3] (x,y,z). Pure host
@@ -104,25 +108,44 @@ int sift3d_pair_offsets(const sift3d_params *p, const double *pair_draws, int n_
                         int32_t *out);
 
 /*
- * Plan extraction for one volume shape. Host only, allocates nothing on
- * the device. kp_capacity >= 0 is the size of the caller's keypoint and
- * descriptor buffers. The plan keeps a pointer to ctx, which must outlive it.
+ * Plan extraction for one volume shape (a plan over one volume). Host
+ * planning plus one small device table (the plan's job descriptors, holding
+ * offsets only) uploaded synchronously; freed by sift3d_plan_destroy.
+ * kp_capacity >= 0 is the size of the caller's keypoint and descriptor
+ * buffers per volume. The plan keeps a pointer to ctx, which must outlive it.
  */
 int sift3d_plan_create(sift3d_ctx *ctx, int nx, int ny, int nz, int kp_capacity, sift3d_plan **out);
+
+/*
+ * Plan extraction for a batch of n_volumes volumes of any sizes; dims is
+ * [n_volumes][3] (nx, ny, nz). Every call on such a plan processes all
+ * volumes together: each launch covers the same stage of every volume.
+ * Per-volume results are identical to a one-volume plan's. The input is one
+ * packed buffer: volume v starts at element offset input_offset(v)
+ * (sift3d_plan_volume), 256-byte aligned. Outputs are [n_volumes] blocks:
+ * keypoints [n_volumes][kp_capacity], counts [n_volumes], descriptors
+ * [n_volumes][kp_capacity][...]. n_volumes <= 4096.
+ */
+int sift3d_plan_create_batch(sift3d_ctx *ctx, int n_volumes, const int *dims, int kp_capacity,
+                             sift3d_plan **out);
 int sift3d_plan_destroy(sift3d_plan *plan);
 
-/* Workspace size in bytes and number of octaves of a plan. */
-int sift3d_plan_info(const sift3d_plan *plan, size_t *workspace_bytes, int *n_octaves);
+/* Workspace size in bytes, number of volumes, and floats of the packed input. */
+int sift3d_plan_info(const sift3d_plan *plan, size_t *workspace_bytes, int *n_volumes, size_t *input_elems);
 
-/* Dims (nx, ny, nz) of octave o. */
-int sift3d_plan_octave_dims(const sift3d_plan *plan, int octave, int dims[3]);
+/* Dims, element offset in the packed input, and octave count of volume v. */
+int sift3d_plan_volume(const sift3d_plan *plan, int volume, int dims[3], size_t *input_offset, int *n_octaves);
+
+/* Dims (nx, ny, nz) of octave o of volume v. */
+int sift3d_plan_octave_dims(const sift3d_plan *plan, int volume, int octave, int dims[3]);
 
 /*
  * Device pointer of one pyramid level inside a workspace: kind 0 = G_idx
  * (idx 0..S+2), kind 1 = D_idx (idx 0..S+1). A view, no copy; the level is
- * a [nz][ny][nx] float32 array of octave `octave`'s dims.
+ * a [nz][ny][nx] float32 array of the octave's dims.
  */
-int sift3d_level(const sift3d_plan *plan, void *d_ws, int octave, int kind, int idx, float **d_ptr);
+int sift3d_level(const sift3d_plan *plan, void *d_ws, int volume, int octave, int kind, int idx,
+                 float **d_ptr);
 
 /*
  * Gaussian scale space, DoG and sub-sampling (Section 3.2.2, Gaussian
@@ -138,8 +161,9 @@ int sift3d_level(const sift3d_plan *plan, void *d_ws, int octave, int kind, int 
  *   pair differences), as whole levels with the same clamp-to-edge rule.
  * Independent levels (the last levels of octave o, the first of octave o+1,
  * the pre-blurs) share launches.
- * d_vol: [nz][ny][nx] float32, read only. d_ws: workspace of at least the
- * planned size (256-byte aligned); all levels are written into it.
+ * d_vol: the input, [nz][ny][nx] float32 (the packed volumes of a batch
+ * plan), read only. d_ws: workspace of at least the planned size (256-byte
+ * aligned); all levels are written into it.
  */
 int sift3d_build_pyramid(const sift3d_plan *plan, const float *d_vol, void *d_ws, size_t ws_bytes,
                          void *stream);
@@ -154,12 +178,13 @@ int sift3d_build_pyramid(const sift3d_plan *plan, const float *d_vol, void *d_ws
  * pre-blurred levels; sift3d_build_pyramid does.
  *   info[0] = octave, info[1] = level, info[2] = tap radius, info[3] = 1 if
  *   the pass also writes the next octave's G_0, info[4] = 1 if it is one
- *   fused streaming launch, 0 if an xy launch followed by a z launch;
+ *   fused streaming launch, 0 if an xy launch followed by a z launch,
+ *   info[5] = volume;
  *   *bytes = algorithmic HBM bytes of the pass: 4 per voxel read, 4 per
  *   voxel written for G and D, 4 per sub-sampled voxel.
  */
 int sift3d_pyramid_pass_count(const sift3d_plan *plan, int *n_passes);
-int sift3d_pyramid_pass_info(const sift3d_plan *plan, int pass, int info[5], size_t *bytes);
+int sift3d_pyramid_pass_info(const sift3d_plan *plan, int pass, int info[6], size_t *bytes);
 int sift3d_pyramid_pass(const sift3d_plan *plan, int pass, const float *d_vol, void *d_ws, size_t ws_bytes,
                         void *stream);
 
@@ -168,18 +193,20 @@ int sift3d_pyramid_pass(const sift3d_plan *plan, int pass, const float *d_vol, v
  * octave, scale s = 1..S and interior voxel v (1 <= x <= nx-2, same for y,
  * z) keep v if |D_s(v)| > dog_threshold and the sum over its 80 neighbours
  * in D_{s-1}, D_s, D_{s+1} of sign(D_s(v) - neighbour) is >= votes (peak)
- * or <= -votes (valley). Keypoints are written to d_kp in (octave, scale,
- * z, y, x) order, at most kp_capacity of them; *d_count (device int)
- * receives the total number found, which may exceed kp_capacity (then the
- * list is the first kp_capacity in that order). Uses the workspace's
- * scratch area; the pyramid must have been built in d_ws.
+ * or <= -votes (valley). Each volume's keypoints are written to its block
+ * d_kp[v * kp_capacity ...] in (octave, scale, z, y, x) order, at most
+ * kp_capacity of them; d_count[v] (device ints) receives the total number
+ * found, which may exceed kp_capacity (then the list is the first
+ * kp_capacity in that order). Uses the workspace's scratch area; the
+ * pyramid must have been built in d_ws. Inputs must be finite.
  */
 int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_keypoint *d_kp,
                   int kp_capacity, int *d_count, void *stream);
 
 /*
- * Descriptors of keypoints 0 .. min(*d_count, kp_capacity) - 1, each on
- * G_s of its octave. Any of the three outputs may be NULL to skip it.
+ * Descriptors of keypoints 0 .. min(d_count[v], kp_capacity) - 1 of every
+ * volume v, each on G_s of its octave; row k of volume v is at
+ * v * kp_capacity + k. Any of the three outputs may be NULL to skip it.
  *   d_siftrank [cap][64] uint8: upright SIFT-Rank (Section 2, 2x2x2
  *     spatial x 8 orientation bins, normalised by ranking): over the
  *     window d in [-R, R]^3, R = ceil(siftrank_factor * sigma_s), the
@@ -203,6 +230,98 @@ int sift3d_describe(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes,
 int sift3d_extract(const sift3d_plan *plan, const float *d_vol, void *d_ws, size_t ws_bytes,
                    sift3d_keypoint *d_kp, int kp_capacity, int *d_count, uint8_t *d_siftrank,
                    uint64_t *d_brief, uint8_t *d_rrief, void *stream);
+
+/*
+ * Request server: continuous batching of independent extractions on one GPU
+ * (the per-volume work of sift3d_extract, for volumes that arrive over
+ * time). A scheduler thread owned by the server admits requests in arrival
+ * order while (a) fewer than max_inflight are on the device and (b) a slot
+ * of the request's shape is idle or can be allocated within hbm_budget
+ * bytes (idle slots of other shapes are freed, least recently used first,
+ * to make room). A slot is one device allocation holding the pyramid
+ * workspace and the keypoint and descriptor buffers of one request; slots
+ * and plans are cached per shape. Admitted requests are spread over
+ * n_streams non-blocking streams (default priority) so that several run on
+ * the device at once. Each request runs the same kernels as sift3d_extract
+ * on its own slot, so its result is the same alone and among others.
+ * The server owns its slots, plans, streams and thread; the context must
+ * outlive it.
+ */
+typedef struct sift3d_server sift3d_server;
+
+typedef struct sift3d_server_config {
+    size_t hbm_budget;  /* device bytes that slots may occupy in total (> 0)  */
+    int n_streams;      /* 1..8                                             */
+    int max_inflight;   /* requests on the device at once, 1..256           */
+    int kp_capacity;    /* keypoint and descriptor rows per request, >= 1    */
+} sift3d_server_config;
+
+/* Result of one request; device pointers stay valid until its release. */
+typedef struct sift3d_result {
+    int status;                  /* SIFT3D_OK, or the error that ended the request */
+    int hip_error;               /* hipError_t when status == SIFT3D_E_HIP           */
+    int count;                   /* keypoints found (rows held: min(count, capacity)) */
+    int capacity;
+    const sift3d_keypoint *d_kp; /* [capacity], canonical order                       */
+    const uint8_t *d_siftrank;   /* [capacity][64]                                    */
+    const uint64_t *d_brief;     /* [capacity][brief_n/64] (NULL if brief_n == 0)     */
+    const uint8_t *d_rrief;      /* [capacity][brief_n]    (NULL if brief_n == 0)     */
+    int stream;                  /* index of the server stream it ran on              */
+    double t_submit, t_start, t_done; /* seconds on sift3d_server_clock: submitted,
+                                        launched, completion seen by the scheduler   */
+} sift3d_result;
+
+typedef struct sift3d_server_counters {
+    int64_t submitted, completed, failed;
+    int in_flight, pending;
+    size_t allocated, peak_allocated, hbm_budget;   /* slot bytes */
+    int64_t slot_allocations, slot_evictions;
+} sift3d_server_counters;
+
+/* Create a server on the current HIP device and start its scheduler thread. */
+int sift3d_server_create(sift3d_ctx *ctx, const sift3d_server_config *cfg, sift3d_server **out);
+
+/* Device bytes of the slot a request of this shape occupies (plans it). */
+int sift3d_server_footprint(sift3d_server *srv, int nx, int ny, int nz, size_t *bytes);
+
+/*
+ * Queue the extraction of one volume d_vol ([nz][ny][nx] float32 device
+ * memory, owned by the caller, complete before the call and left untouched
+ * until the request finishes). Returns at once with a ticket.
+ * SIFT3D_E_WORKSPACE if the slot alone exceeds hbm_budget; SIFT3D_E_TOO_SMALL
+ * if the shape gives no octave.
+ */
+int sift3d_server_submit(sift3d_server *srv, const float *d_vol, int nx, int ny, int nz, int64_t *ticket);
+
+/*
+ * Result of a ticket. wait != 0 blocks until it is finished; wait == 0
+ * returns SIFT3D_PENDING if it is not. The request keeps its slot (and the
+ * device pointers in *out stay valid) until sift3d_server_release.
+ */
+int sift3d_server_result(sift3d_server *srv, int64_t ticket, int wait, sift3d_result *out);
+
+/*
+ * Copy the first min(count, capacity) rows of a finished request's results
+ * to host memory (any pointer may be NULL to skip that output). Waits for
+ * the copy on the request's stream only.
+ */
+int sift3d_server_fetch(sift3d_server *srv, int64_t ticket, sift3d_keypoint *h_kp, uint8_t *h_siftrank,
+                        uint64_t *h_brief, uint8_t *h_rrief);
+
+/* Give a finished request's slot back to the server; the ticket becomes invalid. */
+int sift3d_server_release(sift3d_server *srv, int64_t ticket);
+
+int sift3d_server_stats(sift3d_server *srv, sift3d_server_counters *out);
+
+/* Seconds on the server's monotonic clock (the t_* fields of sift3d_result). */
+double sift3d_server_clock(void);
+
+/*
+ * Stop the server: requests not yet admitted are cancelled (status
+ * SIFT3D_E_ARG), those on the device finish; then all slots, plans and
+ * streams are freed. Tickets and result pointers become invalid.
+ */
+int sift3d_server_destroy(sift3d_server *srv);
 
 /* Static description of an error code. */
 const char *sift3d_error_string(int code);

@@ -11,6 +11,7 @@ from .sift3d import (  # noqa: F401
     Context,
     Params,
     Plan,
+    Server,
     Sift3dError,
     default_params,
     pair_offsets,

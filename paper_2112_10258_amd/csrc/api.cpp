@@ -103,95 +103,135 @@ int z_blocks(const OctaveGeom &g)
     return ((g.nx + 31) / 32) * ((g.ny + 7) / 8) * ((g.nz + kZPlanes - 1) / kZPlanes);
 }
 
-// Geometry of job j of an xy launch; block0 continues after job j-1.
-void set_xy_job(XYArgs &a, int j, const OctaveGeom &g)
-{
-    XYJob &jb = a.job[j];
-    jb.nx = g.nx;
-    jb.ny = g.ny;
-    jb.nz = g.nz;
-    jb.tiles_x = (g.nx + kXYTX - 1) / kXYTX;
-    jb.tiles_y = (g.ny + kXYTY - 1) / kXYTY;
-    jb.block0 = j == 0 ? 0 : a.job[j - 1].block0 + a.job[j - 1].tiles_x * a.job[j - 1].tiles_y * a.job[j - 1].nz;
-}
+size_t level_off(const OctaveGeom &g, int lev) { return g.base + (size_t)lev * g.level_bytes; }
 
-void set_z_job(ZArgs &a, int j, const OctaveGeom &g, const OctaveGeom *sub)
-{
-    ZJob &jb = a.job[j];
-    jb.nx = g.nx;
-    jb.ny = g.ny;
-    jb.nz = g.nz;
-    jb.mx = sub ? sub->nx : 0;
-    jb.my = sub ? sub->ny : 0;
-    jb.mz = sub ? sub->nz : 0;
-    jb.gx = (g.nx + 31) / 32;
-    jb.gy = (g.ny + 7) / 8;
-    jb.gz = (g.nz + kZPlanes - 1) / kZPlanes;
-    jb.block0 = j == 0 ? 0 : a.job[j - 1].block0 + a.job[j - 1].gx * a.job[j - 1].gy * a.job[j - 1].gz;
-}
-
-int pass_index(const sift3d_plan *pl, int o, int level)
+int find_pass(const sift3d_plan *pl, int v, int o, int level)
 {
     for (size_t b = 0; b < pl->blur.size(); ++b)
-        if (pl->blur[b].octave == o && pl->blur[b].dst_idx == level) return (int)b;
+        if (pl->blur[b].vol == v && pl->blur[b].octave == o && pl->blur[b].dst_idx == level) return (int)b;
     return -1;
 }
 
-// List scheduler: alternating xy and z launches, each holding every split
-// task whose inputs are ready (at most kMaxJobs jobs and kMaxTapSets tap
-// sets per launch); fused passes are launches of their own.
+// The xy and z jobs of a split task (block0 left for the caller).
+void task_jobs(const sift3d_plan *pl, const Task &k, DXYJob &xy, DZJob &z)
+{
+    const int S = pl->S;
+    xy = DXYJob{};
+    z = DZJob{};
+    const VolPlan &vp = pl->vols[k.vol];
+    const OctaveGeom *g, *sub = nullptr;
+    if (k.kind == 0) {
+        const BlurLaunch &L = pl->blur[k.pass];
+        g = &vp.oct[L.octave];
+        if (L.src_kind < 0) {
+            xy.src = (long long)vp.in_off;
+            xy.src_input = 1;
+        } else {
+            xy.src = (long long)level_off(*g, lev_G(L.src_idx));
+        }
+        xy.dst = z.t = (long long)level_off(*g, lev_T(S));
+        z.center = L.dog ? xy.src : -1;
+        z.center_input = xy.src_input;
+        z.dst = (long long)level_off(*g, lev_G(L.dst_idx));
+        z.dog = L.dog ? (long long)level_off(*g, lev_D(S, L.dog_idx)) : -1;
+        if (L.sub_octave >= 0) {
+            sub = &vp.oct[L.sub_octave];
+            z.sub = (long long)level_off(*sub, lev_G(0));
+        } else {
+            z.sub = -1;
+        }
+        xy.r = z.r = L.r;
+        xy.taps = z.taps = L.tapset;
+    } else {
+        g = &vp.oct[k.octave];
+        xy.src = (long long)level_off(*g, lev_G(k.s));
+        xy.dst = z.t = (long long)level_off(*g, lev_Tb(S, k.s));
+        z.center = -1;
+        z.dst = (long long)level_off(*g, lev_B(S, k.s));
+        z.dog = -1;
+        z.sub = -1;
+        xy.r = z.r = pl->brief_rb;
+        xy.taps = z.taps = pl->brief_tapset;
+    }
+    xy.nx = z.nx = g->nx;
+    xy.ny = z.ny = g->ny;
+    xy.nz = z.nz = g->nz;
+    xy.tiles_x = (g->nx + kXYTX - 1) / kXYTX;
+    xy.tiles_y = (g->ny + kXYTY - 1) / kXYTY;
+    z.mx = sub ? sub->nx : 0;
+    z.my = sub ? sub->ny : 0;
+    z.mz = sub ? sub->nz : 0;
+    z.gx = (g->nx + 31) / 32;
+    z.gy = (g->ny + 7) / 8;
+    z.gz = (g->nz + kZPlanes - 1) / kZPlanes;
+}
+
+// List scheduler over all volumes: alternating xy and z launches, each
+// holding every split task whose inputs are ready; fused passes are
+// launches of their own. Fills the job tables (schedule entries first, then
+// one single-job entry per task for sift3d_pyramid_pass).
 void build_schedule(sift3d_plan *pl)
 {
     const int S = pl->S;
     pl->tasks.clear();
     pl->sched.clear();
-    for (size_t b = 0; b < pl->blur.size(); ++b) pl->tasks.push_back(Task{0, (int)b, pl->blur[b].octave, 0});
+    pl->xyjobs.clear();
+    pl->zjobs.clear();
+    for (size_t b = 0; b < pl->blur.size(); ++b)
+        pl->tasks.push_back(Task{0, (int)b, pl->blur[b].vol, pl->blur[b].octave, 0});
     if (pl->brief_rb >= 0)
-        for (int o = 0; o < pl->n_oct; ++o)
-            for (int s = 1; s <= S; ++s) pl->tasks.push_back(Task{1, -1, o, s});
+        for (int v = 0; v < pl->n_vol; ++v)
+            for (int o = 0; o < (int)pl->vols[v].oct.size(); ++o)
+                for (int s = 1; s <= S; ++s) pl->tasks.push_back(Task{1, -1, v, o, s});
     const int nt = (int)pl->tasks.size();
     std::vector<char> xy_done(nt, 0), done(nt, 0);
     std::vector<int> task_of_pass(pl->blur.size(), -1);
     for (int t = 0; t < nt; ++t)
         if (pl->tasks[t].kind == 0) task_of_pass[pl->tasks[t].pass] = t;
-    auto pass_done = [&](int o, int level) {
-        const int b = pass_index(pl, o, level);
+    auto pass_done = [&](int v, int o, int level) {
+        const int b = find_pass(pl, v, o, level);
         return b >= 0 && done[task_of_pass[b]];
     };
     auto ready = [&](int t) {
         const Task &k = pl->tasks[t];
-        if (k.kind == 1) return pass_done(k.octave, k.s);
+        if (k.kind == 1) return pass_done(k.vol, k.octave, k.s);
         const BlurLaunch &L = pl->blur[k.pass];
         if (L.src_kind < 0) return true;
-        if (L.src_idx == 0 && L.octave > 0) return pass_done(L.octave - 1, S);  // G_0 from the sub-sample
-        return pass_done(L.octave, L.src_idx);
+        if (L.src_idx == 0 && L.octave > 0) return pass_done(L.vol, L.octave - 1, S);  // G_0 from the sub-sample
+        return pass_done(L.vol, L.octave, L.src_idx);
     };
     auto is_fused = [&](int t) { return pl->tasks[t].kind == 0 && pl->blur[pl->tasks[t].pass].fused; };
-    auto tapset_of = [&](int t) {
-        return pl->tasks[t].kind == 0 ? pl->blur[pl->tasks[t].pass].tapset : pl->brief_tapset;
-    };
     auto emit = [&](int type, const std::vector<int> &ts) {
-        Step st{type, {}};
-        std::vector<int> sets;
+        if (ts.empty()) return;
+        Step st{type, ts, 0, (int)ts.size(), 0, 0};
+        st.first = type == 1 ? (int)pl->xyjobs.size() : (int)pl->zjobs.size();
+        int blocks = 0;
         for (int t : ts) {
-            const int id = tapset_of(t);
-            const bool known = std::find(sets.begin(), sets.end(), id) != sets.end();
-            if ((int)st.tasks.size() == kMaxJobs || (!known && (int)sets.size() == kMaxTapSets)) {
-                pl->sched.push_back(st);
-                st.tasks.clear();
-                sets.clear();
+            DXYJob xy;
+            DZJob z;
+            task_jobs(pl, pl->tasks[t], xy, z);
+            const VolPlan &vp = pl->vols[pl->tasks[t].vol];
+            const int o = pl->tasks[t].kind == 0 ? pl->blur[pl->tasks[t].pass].octave : pl->tasks[t].octave;
+            st.max_r = std::max(st.max_r, xy.r);
+            if (type == 1) {
+                xy.block0 = blocks;
+                blocks += xy_blocks(vp.oct[o]);
+                pl->xyjobs.push_back(xy);
+            } else {
+                z.block0 = blocks;
+                blocks += z_blocks(vp.oct[o]);
+                pl->zjobs.push_back(z);
             }
-            if (std::find(sets.begin(), sets.end(), id) == sets.end()) sets.push_back(id);
-            st.tasks.push_back(t);
         }
-        if (!st.tasks.empty()) pl->sched.push_back(st);
+        st.n_blocks = blocks;
+        pl->sched.push_back(st);
     };
     int remaining = nt;
     while (remaining > 0) {
         bool progress = false;
         for (int t = 0; t < nt; ++t)
             if (!done[t] && is_fused(t) && ready(t)) {
-                pl->sched.push_back(Step{0, {t}});
+                pl->sched.push_back(Step{0, {t}, 0, 1, 0, 0});
                 done[t] = 1;
                 --remaining;
                 progress = true;
@@ -212,6 +252,285 @@ void build_schedule(sift3d_plan *pl)
         if (!zs.empty()) progress = true;
         if (!progress) break;  // not reachable for a well-formed pyramid
     }
+    // single-job entries
+    pl->solo_xy.assign(nt, -1);
+    pl->solo_z.assign(nt, -1);
+    for (int t = 0; t < nt; ++t) {
+        if (is_fused(t)) continue;
+        DXYJob xy;
+        DZJob z;
+        task_jobs(pl, pl->tasks[t], xy, z);
+        xy.block0 = z.block0 = 0;
+        pl->solo_xy[t] = (int)pl->xyjobs.size();
+        pl->xyjobs.push_back(xy);
+        pl->solo_z[t] = (int)pl->zjobs.size();
+        pl->zjobs.push_back(z);
+    }
+}
+
+// Upload the plan's device tables (one allocation).
+int upload_tables(sift3d_plan *pl)
+{
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t b_units = al(pl->units.size() * sizeof(DUnit));
+    const size_t b_vols = al(pl->dvols.size() * sizeof(DVol));
+    const size_t b_xy = al(std::max<size_t>(1, pl->xyjobs.size()) * sizeof(DXYJob));
+    const size_t b_z = al(std::max<size_t>(1, pl->zjobs.size()) * sizeof(DZJob));
+    const size_t b_taps = al(pl->tapsets.size() * kMaxTaps * sizeof(float));
+    const size_t total = b_units + b_vols + b_xy + b_z + b_taps;
+    std::vector<char> host(total, 0);
+    size_t off = 0;
+    std::memcpy(host.data() + off, pl->units.data(), pl->units.size() * sizeof(DUnit));
+    off += b_units;
+    std::memcpy(host.data() + off, pl->dvols.data(), pl->dvols.size() * sizeof(DVol));
+    off += b_vols;
+    std::memcpy(host.data() + off, pl->xyjobs.data(), pl->xyjobs.size() * sizeof(DXYJob));
+    off += b_xy;
+    std::memcpy(host.data() + off, pl->zjobs.data(), pl->zjobs.size() * sizeof(DZJob));
+    off += b_z;
+    for (size_t i = 0; i < pl->tapsets.size(); ++i)
+        std::memcpy(host.data() + off + i * kMaxTaps * sizeof(float), pl->tapsets[i].data(), kMaxTaps * sizeof(float));
+    hipError_t e = hipMalloc(&pl->d_tables, total);
+    if (e != hipSuccess) {
+        pl->d_tables = nullptr;
+        return hip_fail(e);
+    }
+    e = hipMemcpy(pl->d_tables, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e);
+    char *d = static_cast<char *>(pl->d_tables);
+    pl->d_units = reinterpret_cast<DUnit *>(d);
+    pl->d_vols = reinterpret_cast<DVol *>(d + b_units);
+    pl->d_xy = reinterpret_cast<DXYJob *>(d + b_units + b_vols);
+    pl->d_z = reinterpret_cast<DZJob *>(d + b_units + b_vols + b_xy);
+    pl->d_taps = reinterpret_cast<float *>(d + b_units + b_vols + b_xy + b_z);
+    return SIFT3D_OK;
+}
+
+// Octave, level, detection and schedule geometry of a plan over n volumes.
+int make_plan(sift3d_ctx *ctx, int n, const int *dims, int kp_capacity, sift3d_plan **out)
+{
+    if (out == nullptr) return SIFT3D_E_ARG;
+    *out = nullptr;
+    if (ctx == nullptr || dims == nullptr || n < 1 || n > kMaxVolumes || kp_capacity < 0) return SIFT3D_E_ARG;
+    const sift3d_params &p = ctx->p;
+    const int S = p.scales, nlev = levels_per_octave(S);
+    sift3d_plan *pl = new (std::nothrow) sift3d_plan();
+    if (pl == nullptr) return SIFT3D_E_ARG;
+    pl->ctx = ctx;
+    pl->n_vol = n;
+    pl->cap = kp_capacity;
+    pl->S = S;
+    pl->d_tables = nullptr;
+    size_t off = 0, in_off = 0;
+    for (int v = 0; v < n; ++v) {
+        const int nx = dims[3 * v], ny = dims[3 * v + 1], nz = dims[3 * v + 2];
+        if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny > (1LL << 30) ||
+            (long long)nx * ny * nz > (1LL << 40)) {
+            delete pl;
+            return SIFT3D_E_ARG;
+        }
+        VolPlan vp;
+        vp.nx = nx;
+        vp.ny = ny;
+        vp.nz = nz;
+        vp.in_off = in_off;
+        in_off += (size_t)nx * ny * nz;
+        in_off = (in_off + 63) & ~(size_t)63;  // each volume 256-byte aligned in the packed input
+        // octave geometry: halve (floor) while the smallest dim stays >= min_dim
+        int cx = nx, cy = ny, cz = nz;
+        while (std::min(cx, std::min(cy, cz)) >= p.min_dim) {
+            if (p.n_octaves > 0 && (int)vp.oct.size() == p.n_octaves) break;
+            if ((int)vp.oct.size() == kMaxOctaves) break;
+            OctaveGeom g;
+            g.nx = cx;
+            g.ny = cy;
+            g.nz = cz;
+            g.n = (size_t)cx * cy * cz;
+            g.level_bytes = align256(g.n * sizeof(float));
+            g.base = off;
+            off += g.level_bytes * nlev;
+            vp.oct.push_back(g);
+            cx /= 2;
+            cy /= 2;
+            cz /= 2;
+        }
+        if (vp.oct.empty()) {
+            delete pl;
+            return SIFT3D_E_TOO_SMALL;
+        }
+        pl->vols.push_back(vp);
+    }
+    pl->in_elems = in_off;
+
+    // tap sets: 0 = base blur, i = increment of G_i, S+3 = BRIEF pre-blur
+    pl->base_sigma = std::sqrt(p.sigma0 * p.sigma0 - p.sigma_in * p.sigma_in);
+    for (int i = 1; i <= S + 2; ++i) {
+        const double a = scale_sigma(p, i), b = scale_sigma(p, i - 1);
+        pl->inc_sigma.push_back(std::sqrt(a * a - b * b));
+    }
+    auto add_taps = [&](double sigma) {
+        const std::vector<double> w = gaussian(sigma, p.trunc);
+        std::vector<float> f(kMaxTaps, 0.0f);
+        for (size_t t = 0; t < w.size(); ++t) f[t] = (float)w[t];
+        pl->tapsets.push_back(f);
+        pl->tapset_r.push_back((int)(w.size() - 1) / 2);
+    };
+    add_taps(pl->base_sigma);
+    for (int i = 1; i <= S + 2; ++i) add_taps(pl->inc_sigma[i - 1]);
+    add_taps(p.brief_blur);
+    pl->brief_tapset = S + 3;
+    pl->brief_rb = (p.brief_blur > 0.0 && p.brief_n > 0) ? pl->tapset_r[S + 3] : -1;
+
+    // detection units and rows (each volume starts on a kRowBlock boundary)
+    long long rows = 0;
+    int tile_blocks = 0;
+    for (int v = 0; v < n; ++v) {
+        VolPlan &vp = pl->vols[v];
+        rows = (rows + kRowBlock - 1) / kRowBlock * kRowBlock;
+        vp.unit0 = (int)pl->units.size();
+        pl->dvols.push_back(DVol{rows, vp.unit0, (int)vp.oct.size()});
+        for (int o = 0; o < (int)vp.oct.size(); ++o) {
+            const OctaveGeom &g = vp.oct[o];
+            DUnit u{};
+            u.g0 = (long long)g.base;
+            u.b1 = (long long)level_off(g, pl->brief_rb >= 0 ? lev_B(S, 1) : lev_G(1));
+            u.row_base = rows;
+            u.rows = (long long)S * (g.nz - 2) * (g.ny - 2);
+            u.lstride = (long long)(g.level_bytes / sizeof(float));
+            u.nx = g.nx;
+            u.ny = g.ny;
+            u.nz = g.nz;
+            u.octave = o;
+            u.vol = v;
+            u.words = (g.nx + 63) / 64;
+            u.tiles_x = u.words;
+            u.tiles_y = (g.ny - 2 + kDTY - 1) / kDTY;  // interior rows 1..ny-2
+            u.tiles_z = (g.nz - 2 + kDTZ - 1) / kDTZ;  // interior planes 1..nz-2
+            u.tile_block0 = tile_blocks;
+            tile_blocks += u.tiles_x * u.tiles_y * u.tiles_z;
+            for (int s = 0; s <= S; ++s) u.sigma[s] = (float)(scale_sigma(p, s) * std::ldexp(1.0, o));
+            rows += u.rows;
+            pl->units.push_back(u);
+        }
+    }
+    rows = (rows + kRowBlock - 1) / kRowBlock * kRowBlock;
+    pl->total_rows = rows;
+    pl->tile_blocks = tile_blocks;
+    const long long nblk = (rows + kDetRowsPerBlock - 1) / kDetRowsPerBlock;
+    pl->row_count_off = off;
+    off += align256((size_t)rows * sizeof(int));
+    pl->block_sum_off = off;
+    off += align256((size_t)nblk * sizeof(int));
+    pl->block_off_off = off;
+    off += align256((size_t)nblk * sizeof(int));
+    for (DUnit &u : pl->units) {
+        u.masks = (long long)off;
+        off += align256((size_t)u.rows * u.words * sizeof(unsigned long long));
+    }
+    pl->ws_bytes = off;
+
+    // level passes
+    for (int v = 0; v < n; ++v) {
+        const VolPlan &vp = pl->vols[v];
+        const int no = (int)vp.oct.size();
+        for (int o = 0; o < no; ++o) {
+            const OctaveGeom &g = vp.oct[o];
+            for (int i = (o == 0 ? 0 : 1); i <= S + 2; ++i) {
+                BlurLaunch L{};
+                L.vol = v;
+                L.tapset = i;
+                L.r = pl->tapset_r[i];
+                L.dog = i > 0;
+                L.octave = o;
+                L.src_kind = i == 0 ? -1 : 0;
+                L.src_idx = i - 1;
+                L.dst_idx = i;
+                L.dog_idx = i - 1;
+                L.sub_octave = (i == S && o + 1 < no) ? o + 1 : -1;
+                L.fused = p.pyramid_mode == 1 || (p.pyramid_mode == 0 && (long long)g.n >= kFusedMinVoxels);
+                if (L.fused) {
+                    BlurArgs &a = L.a;
+                    a.nx = g.nx;
+                    a.ny = g.ny;
+                    a.nz = g.nz;
+                    if (L.sub_octave >= 0) {
+                        a.mx = vp.oct[o + 1].nx;
+                        a.my = vp.oct[o + 1].ny;
+                        a.mz = vp.oct[o + 1].nz;
+                    }
+                    a.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
+                    a.tiles_y = (g.ny + kBlurTY - 1) / kBlurTY;
+                    a.L = choose_slab(g.nz, a.tiles_x * a.tiles_y, L.r);
+                    a.slabs = (g.nz + a.L - 1) / a.L;
+                    a.n_blocks = a.tiles_x * a.tiles_y * a.slabs;
+                    for (int t = 0; t < kMaxTaps; ++t) a.w[t] = pl->tapsets[i][t];
+                }
+                pl->blur.push_back(L);
+            }
+        }
+    }
+    build_schedule(pl);
+    const int rc = upload_tables(pl);
+    if (rc != SIFT3D_OK) {
+        if (pl->d_tables) (void)hipFree(pl->d_tables);
+        delete pl;
+        return rc;
+    }
+    *out = pl;
+    return SIFT3D_OK;
+}
+
+float *ws_float(const void *ws, size_t off)
+{
+    return reinterpret_cast<float *>(const_cast<char *>(static_cast<const char *>(ws)) + off);
+}
+
+int check_ws(const sift3d_plan *plan, const void *ws, size_t bytes)
+{
+    if (plan == nullptr || ws == nullptr) return SIFT3D_E_ARG;
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return SIFT3D_E_ARG;
+    if (bytes < plan->ws_bytes) return SIFT3D_E_WORKSPACE;
+    return SIFT3D_OK;
+}
+
+int run_step(const sift3d_plan *plan, const Step &stp, const float *d_in, void *d_ws, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    char *ws = static_cast<char *>(d_ws);
+    if (stp.type == 0) {
+        const BlurLaunch &L = plan->blur[plan->tasks[stp.tasks[0]].pass];
+        const VolPlan &vp = plan->vols[L.vol];
+        const OctaveGeom &g = vp.oct[L.octave];
+        BlurArgs a = L.a;
+        a.src = L.src_kind < 0 ? d_in + vp.in_off : ws_float(ws, level_off(g, lev_G(L.src_idx)));
+        a.dst = ws_float(ws, level_off(g, lev_G(L.dst_idx)));
+        a.dog = L.dog ? ws_float(ws, level_off(g, lev_D(plan->S, L.dog_idx))) : nullptr;
+        a.sub = L.sub_octave >= 0 ? ws_float(ws, level_off(vp.oct[L.sub_octave], lev_G(0))) : nullptr;
+        e = launch_blur(a, L.r, L.dog, st);
+    } else if (stp.type == 1) {
+        XYLaunch a{};
+        a.jobs = plan->d_xy + stp.first;
+        a.n_jobs = stp.count;
+        a.n_blocks = stp.n_blocks;
+        a.ws = ws;
+        a.in = d_in;
+        a.taps = plan->d_taps;
+        if (stp.count <= kInlineJobs)
+            for (int j = 0; j < stp.count; ++j) a.inl[j] = plan->xyjobs[stp.first + j];
+        e = launch_blur_xy(a, stp.max_r, st);
+    } else {
+        ZLaunch a{};
+        a.jobs = plan->d_z + stp.first;
+        a.n_jobs = stp.count;
+        a.n_blocks = stp.n_blocks;
+        a.ws = ws;
+        a.in = d_in;
+        a.taps = plan->d_taps;
+        if (stp.count <= kInlineJobs)
+            for (int j = 0; j < stp.count; ++j) a.inl[j] = plan->zjobs[stp.first + j];
+        e = launch_blur_z(a, st);
+    }
+    return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }
 
 }  // namespace
@@ -282,6 +601,13 @@ int sift3d_destroy(sift3d_ctx *ctx)
     return SIFT3D_OK;
 }
 
+int sift3d_ctx_params(const sift3d_ctx *ctx, sift3d_params *out)
+{
+    if (ctx == nullptr || out == nullptr) return SIFT3D_E_ARG;
+    *out = ctx->p;
+    return SIFT3D_OK;
+}
+
 int sift3d_pair_offsets(const sift3d_params *p, const double *pair_draws, int n_draws, int scale, int32_t *out)
 {
     const int rc = check_params(p);
@@ -292,276 +618,69 @@ int sift3d_pair_offsets(const sift3d_params *p, const double *pair_draws, int n_
     return SIFT3D_OK;
 }
 
+
 int sift3d_plan_create(sift3d_ctx *ctx, int nx, int ny, int nz, int kp_capacity, sift3d_plan **out)
 {
-    if (out == nullptr) return SIFT3D_E_ARG;
-    *out = nullptr;
-    if (ctx == nullptr || nx < 1 || ny < 1 || nz < 1 || kp_capacity < 0) return SIFT3D_E_ARG;
-    if ((long long)nx * ny > (1LL << 30) || (long long)nx * ny * nz > (1LL << 40)) return SIFT3D_E_ARG;
-    const sift3d_params &p = ctx->p;
-    sift3d_plan *pl = new (std::nothrow) sift3d_plan();
-    if (pl == nullptr) return SIFT3D_E_ARG;
-    pl->ctx = ctx;
-    pl->nx = nx;
-    pl->ny = ny;
-    pl->nz = nz;
-    pl->cap = kp_capacity;
-    pl->S = p.scales;
-    const int S = p.scales, nlev = levels_per_octave(S);
-    // octave geometry: halve (floor) while the smallest dim stays >= min_dim
-    int cx = nx, cy = ny, cz = nz;
-    size_t off = 0;
-    while (std::min(cx, std::min(cy, cz)) >= p.min_dim) {
-        if (p.n_octaves > 0 && (int)pl->oct.size() == p.n_octaves) break;
-        if ((int)pl->oct.size() == kMaxOctaves) break;
-        OctaveGeom g;
-        g.nx = cx;
-        g.ny = cy;
-        g.nz = cz;
-        g.n = (size_t)cx * cy * cz;
-        g.level_bytes = align256(g.n * sizeof(float));
-        g.base = off;
-        off += g.level_bytes * nlev;
-        pl->oct.push_back(g);
-        cx /= 2;
-        cy /= 2;
-        cz /= 2;
-    }
-    pl->n_oct = (int)pl->oct.size();
-    if (pl->n_oct == 0) {
-        delete pl;
-        return SIFT3D_E_TOO_SMALL;
-    }
-    pl->pyramid_bytes = off;
-    // detection scratch
-    long long rows = 0;
-    for (const auto &g : pl->oct) rows += (long long)S * (g.nz - 2) * (g.ny - 2);
-    pl->total_rows = rows;
-    pl->det_blocks = (int)((rows + kDetRowsPerBlock - 1) / kDetRowsPerBlock);
-    pl->row_count_off = off;
-    off += align256((size_t)rows * sizeof(int));
-    pl->block_sum_off = off;
-    off += align256((size_t)pl->det_blocks * sizeof(int));
-    pl->block_off_off = off;
-    off += align256((size_t)pl->det_blocks * sizeof(int));
-    pl->masks_off = off;
-    for (const auto &g : pl->oct)
-        off += align256((size_t)S * (g.nz - 2) * (g.ny - 2) * ((g.nx + 63) / 64) * sizeof(unsigned long long));
-    pl->ws_bytes = off;
+    const int dims[3] = {nx, ny, nz};
+    return make_plan(ctx, 1, dims, kp_capacity, out);
+}
 
-    // blur schedule: G_0 of octave 0 from the input, then G_1..G_{S+2} per
-    // octave, the pass writing G_S also writing the next octave's G_0
-    pl->base_sigma = std::sqrt(p.sigma0 * p.sigma0 - p.sigma_in * p.sigma_in);
-    for (int i = 1; i <= S + 2; ++i) {
-        const double a = scale_sigma(p, i), b = scale_sigma(p, i - 1);
-        pl->inc_sigma.push_back(std::sqrt(a * a - b * b));
-    }
-    // tap sets: 0 = base blur, i = increment of G_i, S+3 = BRIEF pre-blur
-    auto add_taps = [&](double sigma) {
-        const std::vector<double> w = gaussian(sigma, p.trunc);
-        std::vector<float> f(kMaxTaps, 0.0f);
-        for (size_t t = 0; t < w.size(); ++t) f[t] = (float)w[t];
-        pl->tapsets.push_back(f);
-        pl->tapset_r.push_back((int)(w.size() - 1) / 2);
-    };
-    add_taps(pl->base_sigma);
-    for (int i = 1; i <= S + 2; ++i) add_taps(pl->inc_sigma[i - 1]);
-    add_taps(p.brief_blur);
-    pl->brief_tapset = S + 3;
-    pl->brief_rb = (p.brief_blur > 0.0 && p.brief_n > 0) ? pl->tapset_r[S + 3] : -1;
-
-    for (int o = 0; o < pl->n_oct; ++o) {
-        const OctaveGeom &g = pl->oct[o];
-        for (int i = (o == 0 ? 0 : 1); i <= S + 2; ++i) {
-            BlurLaunch L{};
-            L.tapset = i;
-            L.r = pl->tapset_r[i];
-            L.dog = i > 0;
-            L.octave = o;
-            L.src_kind = i == 0 ? -1 : 0;
-            L.src_idx = i - 1;
-            L.dst_idx = i;
-            L.dog_idx = i - 1;
-            L.sub_octave = (i == S && o + 1 < pl->n_oct) ? o + 1 : -1;
-            L.fused = p.pyramid_mode == 1 || (p.pyramid_mode == 0 && (long long)g.n >= kFusedMinVoxels);
-            if (L.fused) {
-                BlurArgs &a = L.a;
-                a.nx = g.nx;
-                a.ny = g.ny;
-                a.nz = g.nz;
-                if (L.sub_octave >= 0) {
-                    a.mx = pl->oct[o + 1].nx;
-                    a.my = pl->oct[o + 1].ny;
-                    a.mz = pl->oct[o + 1].nz;
-                }
-                a.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
-                a.tiles_y = (g.ny + kBlurTY - 1) / kBlurTY;
-                a.L = choose_slab(g.nz, a.tiles_x * a.tiles_y, L.r);
-                a.slabs = (g.nz + a.L - 1) / a.L;
-                a.n_blocks = a.tiles_x * a.tiles_y * a.slabs;
-                for (int t = 0; t < kMaxTaps; ++t) a.w[t] = pl->tapsets[i][t];
-            }
-            pl->blur.push_back(L);
-        }
-    }
-    build_schedule(pl);
-    *out = pl;
-    return SIFT3D_OK;
+int sift3d_plan_create_batch(sift3d_ctx *ctx, int n_volumes, const int *dims, int kp_capacity, sift3d_plan **out)
+{
+    return make_plan(ctx, n_volumes, dims, kp_capacity, out);
 }
 
 int sift3d_plan_destroy(sift3d_plan *plan)
 {
     if (plan == nullptr) return SIFT3D_E_ARG;
+    if (plan->d_tables != nullptr) (void)hipFree(plan->d_tables);
     delete plan;
     return SIFT3D_OK;
 }
 
-int sift3d_plan_info(const sift3d_plan *plan, size_t *workspace_bytes, int *n_octaves)
+int sift3d_plan_info(const sift3d_plan *plan, size_t *workspace_bytes, int *n_volumes, size_t *input_elems)
 {
     if (plan == nullptr) return SIFT3D_E_ARG;
     if (workspace_bytes) *workspace_bytes = plan->ws_bytes;
-    if (n_octaves) *n_octaves = plan->n_oct;
+    if (n_volumes) *n_volumes = plan->n_vol;
+    if (input_elems) *input_elems = plan->in_elems;
     return SIFT3D_OK;
 }
 
-int sift3d_plan_octave_dims(const sift3d_plan *plan, int octave, int dims[3])
+int sift3d_plan_volume(const sift3d_plan *plan, int volume, int dims[3], size_t *input_offset, int *n_octaves)
 {
-    if (plan == nullptr || dims == nullptr || octave < 0 || octave >= plan->n_oct) return SIFT3D_E_ARG;
-    dims[0] = plan->oct[octave].nx;
-    dims[1] = plan->oct[octave].ny;
-    dims[2] = plan->oct[octave].nz;
+    if (plan == nullptr || volume < 0 || volume >= plan->n_vol) return SIFT3D_E_ARG;
+    const VolPlan &vp = plan->vols[volume];
+    if (dims) {
+        dims[0] = vp.nx;
+        dims[1] = vp.ny;
+        dims[2] = vp.nz;
+    }
+    if (input_offset) *input_offset = vp.in_off;
+    if (n_octaves) *n_octaves = (int)vp.oct.size();
     return SIFT3D_OK;
 }
 
-static float *raw_level(const sift3d_plan *pl, const void *ws, int o, int lev)
+int sift3d_plan_octave_dims(const sift3d_plan *plan, int volume, int octave, int dims[3])
 {
-    const OctaveGeom &g = pl->oct[o];
-    return reinterpret_cast<float *>(const_cast<char *>(static_cast<const char *>(ws)) + g.base +
-                                     (size_t)lev * g.level_bytes);
+    if (plan == nullptr || dims == nullptr || volume < 0 || volume >= plan->n_vol) return SIFT3D_E_ARG;
+    const VolPlan &vp = plan->vols[volume];
+    if (octave < 0 || octave >= (int)vp.oct.size()) return SIFT3D_E_ARG;
+    dims[0] = vp.oct[octave].nx;
+    dims[1] = vp.oct[octave].ny;
+    dims[2] = vp.oct[octave].nz;
+    return SIFT3D_OK;
 }
 
-static float *level_ptr(const sift3d_plan *pl, const void *ws, int o, int kind, int idx)
+int sift3d_level(const sift3d_plan *plan, void *d_ws, int volume, int octave, int kind, int idx, float **d_ptr)
 {
-    return raw_level(pl, ws, o, kind == 0 ? lev_G(idx) : lev_D(pl->S, idx));
-}
-
-int sift3d_level(const sift3d_plan *plan, void *d_ws, int octave, int kind, int idx, float **d_ptr)
-{
-    if (plan == nullptr || d_ws == nullptr || d_ptr == nullptr) return SIFT3D_E_ARG;
-    if (octave < 0 || octave >= plan->n_oct || kind < 0 || kind > 1) return SIFT3D_E_ARG;
+    if (plan == nullptr || d_ws == nullptr || d_ptr == nullptr || volume < 0 || volume >= plan->n_vol)
+        return SIFT3D_E_ARG;
+    const VolPlan &vp = plan->vols[volume];
+    if (octave < 0 || octave >= (int)vp.oct.size() || kind < 0 || kind > 1) return SIFT3D_E_ARG;
     if (idx < 0 || idx >= (kind == 0 ? plan->S + 3 : plan->S + 2)) return SIFT3D_E_ARG;
-    *d_ptr = level_ptr(plan, d_ws, octave, kind, idx);
+    *d_ptr = ws_float(d_ws, level_off(vp.oct[octave], kind == 0 ? lev_G(idx) : lev_D(plan->S, idx)));
     return SIFT3D_OK;
-}
-
-static int check_ws(const sift3d_plan *plan, const void *ws, size_t bytes)
-{
-    if (plan == nullptr || ws == nullptr) return SIFT3D_E_ARG;
-    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return SIFT3D_E_ARG;
-    if (bytes < plan->ws_bytes) return SIFT3D_E_WORKSPACE;
-    return SIFT3D_OK;
-}
-
-// Device pointers of a task's xy and z halves for one call.
-struct TaskPtrs {
-    const float *src;
-    float *t, *dst, *dog, *sub;
-    const OctaveGeom *g, *sub_g;
-    int r, tapset;
-};
-
-static TaskPtrs task_ptrs(const sift3d_plan *plan, const Task &k, const float *d_vol, const void *d_ws)
-{
-    TaskPtrs q{};
-    const int S = plan->S;
-    if (k.kind == 0) {
-        const BlurLaunch &L = plan->blur[k.pass];
-        q.src = L.src_kind < 0 ? d_vol : level_ptr(plan, d_ws, L.octave, 0, L.src_idx);
-        q.t = raw_level(plan, d_ws, L.octave, lev_T(S));
-        q.dst = level_ptr(plan, d_ws, L.octave, 0, L.dst_idx);
-        q.dog = L.dog ? level_ptr(plan, d_ws, L.octave, 1, L.dog_idx) : nullptr;
-        q.sub = L.sub_octave >= 0 ? level_ptr(plan, d_ws, L.sub_octave, 0, 0) : nullptr;
-        q.g = &plan->oct[L.octave];
-        q.sub_g = L.sub_octave >= 0 ? &plan->oct[L.sub_octave] : nullptr;
-        q.r = L.r;
-        q.tapset = L.tapset;
-    } else {
-        q.src = raw_level(plan, d_ws, k.octave, lev_G(k.s));
-        q.t = raw_level(plan, d_ws, k.octave, lev_Tb(S, k.s));
-        q.dst = raw_level(plan, d_ws, k.octave, lev_B(S, k.s));
-        q.dog = nullptr;
-        q.sub = nullptr;
-        q.g = &plan->oct[k.octave];
-        q.sub_g = nullptr;
-        q.r = plan->brief_rb;
-        q.tapset = plan->brief_tapset;
-    }
-    return q;
-}
-
-extern "C++" {
-// Tap-set slot of a launch (deduplicated, at most kMaxTapSets per launch).
-template <typename Args>
-static int tap_slot(const sift3d_plan *plan, Args &a, std::vector<int> &sets, int tapset)
-{
-    for (size_t i = 0; i < sets.size(); ++i)
-        if (sets[i] == tapset) return (int)i;
-    const int slot = (int)sets.size();
-    sets.push_back(tapset);
-    for (int t = 0; t < kMaxTaps; ++t) a.w[slot][t] = plan->tapsets[tapset][t];
-    return slot;
-}
-}  // extern "C++"
-
-static int run_step(const sift3d_plan *plan, int type, const std::vector<int> &tasks, const float *d_vol,
-                    void *d_ws, hipStream_t st)
-{
-    hipError_t e = hipSuccess;
-    if (type == 0) {
-        const BlurLaunch &L = plan->blur[plan->tasks[tasks[0]].pass];
-        BlurArgs a = L.a;
-        a.src = L.src_kind < 0 ? d_vol : level_ptr(plan, d_ws, L.octave, 0, L.src_idx);
-        a.dst = level_ptr(plan, d_ws, L.octave, 0, L.dst_idx);
-        a.dog = L.dog ? level_ptr(plan, d_ws, L.octave, 1, L.dog_idx) : nullptr;
-        a.sub = L.sub_octave >= 0 ? level_ptr(plan, d_ws, L.sub_octave, 0, 0) : nullptr;
-        e = launch_blur(a, L.r, L.dog, st);
-    } else if (type == 1) {
-        XYArgs a{};
-        std::vector<int> sets;
-        int j = 0;
-        for (int t : tasks) {
-            const TaskPtrs q = task_ptrs(plan, plan->tasks[t], d_vol, d_ws);
-            set_xy_job(a, j, *q.g);
-            a.job[j].src = q.src;
-            a.job[j].dst = q.t;
-            a.job[j].r = q.r;
-            a.job[j].taps = tap_slot(plan, a, sets, q.tapset);
-            ++j;
-        }
-        a.n_jobs = j;
-        a.n_blocks = a.job[j - 1].block0 + a.job[j - 1].tiles_x * a.job[j - 1].tiles_y * a.job[j - 1].nz;
-        e = launch_blur_xy(a, st);
-    } else {
-        ZArgs a{};
-        std::vector<int> sets;
-        int j = 0;
-        for (int t : tasks) {
-            const TaskPtrs q = task_ptrs(plan, plan->tasks[t], d_vol, d_ws);
-            set_z_job(a, j, *q.g, q.sub_g);
-            a.job[j].t = q.t;
-            a.job[j].center = q.src;
-            a.job[j].dst = q.dst;
-            a.job[j].dog = q.dog;
-            a.job[j].sub = q.sub;
-            a.job[j].r = q.r;
-            a.job[j].taps = tap_slot(plan, a, sets, q.tapset);
-            ++j;
-        }
-        a.n_jobs = j;
-        a.n_blocks = a.job[j - 1].block0 + a.job[j - 1].gx * a.job[j - 1].gy * a.job[j - 1].gz;
-        e = launch_blur_z(a, st);
-    }
-    return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }
 
 int sift3d_build_pyramid(const sift3d_plan *plan, const float *d_vol, void *d_ws, size_t ws_bytes, void *stream)
@@ -570,7 +689,7 @@ int sift3d_build_pyramid(const sift3d_plan *plan, const float *d_vol, void *d_ws
     if (rc != SIFT3D_OK) return rc;
     if (d_vol == nullptr) return SIFT3D_E_ARG;
     for (const Step &stp : plan->sched) {
-        rc = run_step(plan, stp.type, stp.tasks, d_vol, d_ws, static_cast<hipStream_t>(stream));
+        rc = run_step(plan, stp, d_vol, d_ws, static_cast<hipStream_t>(stream));
         if (rc != SIFT3D_OK) return rc;
     }
     return SIFT3D_OK;
@@ -583,21 +702,23 @@ int sift3d_pyramid_pass_count(const sift3d_plan *plan, int *n_passes)
     return SIFT3D_OK;
 }
 
-int sift3d_pyramid_pass_info(const sift3d_plan *plan, int pass, int info[5], size_t *bytes)
+int sift3d_pyramid_pass_info(const sift3d_plan *plan, int pass, int info[6], size_t *bytes)
 {
     if (plan == nullptr || pass < 0 || pass >= (int)plan->blur.size()) return SIFT3D_E_ARG;
     const BlurLaunch &L = plan->blur[pass];
+    const VolPlan &vp = plan->vols[L.vol];
     if (info != nullptr) {
         info[0] = L.octave;
         info[1] = L.dst_idx;
         info[2] = L.r;
         info[3] = L.sub_octave >= 0 ? 1 : 0;
         info[4] = L.fused ? 1 : 0;
+        info[5] = L.vol;
     }
     if (bytes != nullptr) {
-        const size_t n = plan->oct[L.octave].n;
+        const size_t n = vp.oct[L.octave].n;
         size_t b = 8 * n + (L.dog ? 4 * n : 0);
-        if (L.sub_octave >= 0) b += 4 * plan->oct[L.sub_octave].n;
+        if (L.sub_octave >= 0) b += 4 * vp.oct[L.sub_octave].n;
         *bytes = b;
     }
     return SIFT3D_OK;
@@ -614,12 +735,13 @@ int sift3d_pyramid_pass(const sift3d_plan *plan, int pass, const float *d_vol, v
     int t = -1;
     for (size_t k = 0; k < plan->tasks.size(); ++k)
         if (plan->tasks[k].kind == 0 && plan->tasks[k].pass == pass) t = (int)k;
-    const std::vector<int> one{t};
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (L.fused) return run_step(plan, 0, one, d_vol, d_ws, st);
-    rc = run_step(plan, 1, one, d_vol, d_ws, st);
+    if (L.fused) return run_step(plan, Step{0, {t}, 0, 1, 0, 0}, d_vol, d_ws, st);
+    const VolPlan &vp = plan->vols[L.vol];
+    const OctaveGeom &g = vp.oct[L.octave];
+    rc = run_step(plan, Step{1, {t}, plan->solo_xy[t], 1, xy_blocks(g), L.r}, d_vol, d_ws, st);
     if (rc != SIFT3D_OK) return rc;
-    return run_step(plan, 2, one, d_vol, d_ws, st);
+    return run_step(plan, Step{2, {t}, plan->solo_z[t], 1, z_blocks(g), L.r}, d_vol, d_ws, st);
 }
 
 int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_keypoint *d_kp, int kp_capacity,
@@ -629,48 +751,26 @@ int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_k
     if (rc != SIFT3D_OK) return rc;
     if (d_count == nullptr || kp_capacity < 0 || (kp_capacity > 0 && d_kp == nullptr)) return SIFT3D_E_ARG;
     const sift3d_params &p = plan->ctx->p;
-    DetectArgs a{};
-    for (int o = 0; o < plan->n_oct; ++o) {
-        const OctaveGeom &g = plan->oct[o];
-        DetOctave &d = a.oc[o];
-        d.D = level_ptr(plan, d_ws, o, 1, 0);
-        d.lstride = (long long)(g.level_bytes / sizeof(float));
-        d.nx = g.nx;
-        d.ny = g.ny;
-        d.nz = g.nz;
-        d.row_base = 0;
-        for (int q = 0; q < o; ++q)
-            d.row_base += (long long)plan->S * (plan->oct[q].nz - 2) * (plan->oct[q].ny - 2);
-        d.rows = (long long)plan->S * (g.nz - 2) * (g.ny - 2);
-        for (int s = 0; s <= plan->S; ++s) d.sigma[s] = (float)(scale_sigma(p, s) * std::ldexp(1.0, o));
-        d.words = (g.nx + 63) / 64;
-        d.tiles_x = d.words;
-        d.tiles_y = (g.ny - 2 + kDTY - 1) / kDTY;   // interior rows 1..ny-2
-        d.tiles_z = (g.nz - 2 + kDTZ - 1) / kDTZ;   // interior planes 1..nz-2
-        d.block0 = a.tile_blocks;
-        a.tile_blocks += d.tiles_x * d.tiles_y * d.tiles_z;
-    }
-    {
-        size_t moff = plan->masks_off;
-        for (int o = 0; o < plan->n_oct; ++o) {
-            a.oc[o].masks = reinterpret_cast<unsigned long long *>(static_cast<char *>(d_ws) + moff);
-            moff += align256((size_t)a.oc[o].rows * a.oc[o].words * sizeof(unsigned long long));
-        }
-    }
-    a.row_blocks = (int)((plan->total_rows + kRowBlock - 1) / kRowBlock);
-    a.n_oct = plan->n_oct;
+    char *ws = static_cast<char *>(d_ws);
+    DetLaunch a{};
+    a.units = plan->d_units;
+    a.vols = plan->d_vols;
+    a.n_units = (int)plan->units.size();
+    a.n_vol = plan->n_vol;
     a.S = plan->S;
     a.total_rows = plan->total_rows;
-    a.n_blocks = plan->det_blocks;
+    a.tile_blocks = plan->tile_blocks;
     a.thr = p.dog_threshold;
     a.votes = p.votes;
-    char *ws = static_cast<char *>(d_ws);
+    a.ws = ws;
     a.row_count = reinterpret_cast<int *>(ws + plan->row_count_off);
     a.block_sum = reinterpret_cast<int *>(ws + plan->block_sum_off);
     a.block_off = reinterpret_cast<int *>(ws + plan->block_off_off);
-    a.d_count = d_count;
+    a.counts = d_count;
     a.kp = d_kp;
     a.cap = kp_capacity;
+    if (a.n_units <= kInlineUnits)
+        for (int u = 0; u < a.n_units; ++u) a.inl[u] = plan->units[u];
     const hipError_t e = launch_detect(a, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }
@@ -684,27 +784,24 @@ int sift3d_describe(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes, 
     if (d_count == nullptr || kp_capacity < 0 || (kp_capacity > 0 && d_kp == nullptr)) return SIFT3D_E_ARG;
     const sift3d_params &p = plan->ctx->p;
     if (p.brief_n == 0) d_brief = nullptr, d_rrief = nullptr;
-    DescribeArgs a{};
-    for (int o = 0; o < plan->n_oct; ++o) {
-        const OctaveGeom &g = plan->oct[o];
-        a.oc[o].G = level_ptr(plan, d_ws, o, 0, 0);
-        a.oc[o].B = plan->brief_rb >= 0 ? raw_level(plan, d_ws, o, lev_B(plan->S, 1)) : level_ptr(plan, d_ws, o, 0, 1);
-        a.oc[o].lstride = (long long)(g.level_bytes / sizeof(float));
-        a.oc[o].nx = g.nx;
-        a.oc[o].ny = g.ny;
-        a.oc[o].nz = g.nz;
-    }
-    a.n_oct = plan->n_oct;
+    DescLaunch a{};
+    a.units = plan->d_units;
+    a.vols = plan->d_vols;
+    a.n_vol = plan->n_vol;
     a.S = plan->S;
     for (int s = 0; s <= plan->S; ++s) a.sift_R[s] = (int)std::ceil(p.siftrank_factor * scale_sigma(p, s));
+    a.ws = const_cast<char *>(static_cast<const char *>(d_ws));
     a.kp = d_kp;
-    a.d_count = d_count;
+    a.counts = d_count;
     a.cap = kp_capacity;
     a.siftrank = d_siftrank;
     a.brief = d_brief;
     a.rrief = d_rrief;
     a.brief_n = p.brief_n;
     a.pairs = plan->ctx->d_offsets;
+    a.n_units = (int)plan->units.size();
+    if (a.n_units <= kInlineUnits)
+        for (int u = 0; u < a.n_units; ++u) a.inl[u] = plan->units[u];
     const int grid = std::min(kp_capacity, 4096);
     const hipError_t e = launch_describe(a, grid, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
@@ -731,6 +828,7 @@ const char *sift3d_error_string(int code)
     case SIFT3D_E_WORKSPACE: return "workspace too small";
     case SIFT3D_E_HIP: return "HIP runtime error";
     case SIFT3D_E_UNSUPPORTED: return "parameter outside the supported range";
+    case SIFT3D_PENDING: return "request not finished";
     default: return "unknown error";
     }
 }

@@ -63,20 +63,24 @@ __device__ __forceinline__ void sift_column(const float *G, int nx, int ny, int 
 // plane dz = 0 adds half to each z half. The 64 bins are then summed over
 // columns with the column's x/y half weights (1, or 1/2 on the centre
 // planes), and ranked.
-__global__ void __launch_bounds__(kDescThreads) siftrank_kernel(const DescribeArgs a)
+template <bool INL>
+__global__ void __launch_bounds__(kDescThreads) siftrank_kernel(const DescLaunch a)
 {
     __shared__ double part[kDescThreads][17];
     __shared__ double hist[64];
-    const int count = min(*a.d_count, a.cap);
     const int tid = threadIdx.x;
-    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+    for (int v = 0; v < a.n_vol; ++v) {
+    const int count = min(a.counts[v], a.cap);
+    const DVol vol = a.vols[v];
+    for (int kk = blockIdx.x; kk < count; kk += gridDim.x) {
+        const size_t k = (size_t)v * a.cap + kk;
         const sift3d_keypoint kp = a.kp[k];
-        if (kp.octave < 0 || kp.octave >= a.n_oct || kp.scale < 1 || kp.scale > a.S) {
-            if (tid < 64) a.siftrank[(size_t)k * 64 + tid] = 0;  // not a keypoint of this plan
+        if (kp.octave < 0 || kp.octave >= vol.n_units || kp.scale < 1 || kp.scale > a.S) {
+            if (tid < 64) a.siftrank[k * 64 + tid] = 0;  // not a keypoint of this plan
             continue;
         }
-        const DescOctave &oc = a.oc[kp.octave];
-        const float *G = oc.G + oc.lstride * kp.scale;
+        const DUnit &oc = (INL ? a.inl[vol.unit0 + kp.octave] : a.units[vol.unit0 + kp.octave]);
+        const float *G = reinterpret_cast<const float *>(a.ws + oc.g0) + oc.lstride * kp.scale;
         const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
         const int R = a.sift_R[kp.scale];
         const int W = 2 * R + 1;
@@ -119,9 +123,10 @@ __global__ void __launch_bounds__(kDescThreads) siftrank_kernel(const DescribeAr
                 const double o = hist[e];
                 r += (int)(o < h) | ((int)(o == h) & (int)(e < tid));
             }
-            a.siftrank[(size_t)k * 64 + tid] = (uint8_t)r;
+            a.siftrank[k * 64 + tid] = (uint8_t)r;
         }
         __syncthreads();
+    }
     }
 }
 
@@ -131,23 +136,27 @@ __global__ void __launch_bounds__(kDescThreads) siftrank_kernel(const DescribeAr
 // keypoint: lane l owns pairs l, l+64, ...; d_i = B_s(p1) - B_s(p2) is the
 // exact double difference of the two samples; bit words come from ballots
 // and each rank from a comparison against all n differences in LDS.
-__global__ void __launch_bounds__(kDescThreads) brief_kernel(const DescribeArgs a)
+template <bool INL>
+__global__ void __launch_bounds__(kDescThreads) brief_kernel(const DescLaunch a)
 {
     constexpr int WAVES = kDescThreads / 64;
     __shared__ double dd[WAVES][kMaxPairs];
-    const int count = min(*a.d_count, a.cap);
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int n = a.brief_n, nw = n / 64;
+    for (int v = 0; v < a.n_vol; ++v) {
+    const int count = min(a.counts[v], a.cap);
+    const DVol vol = a.vols[v];
     for (int k0 = blockIdx.x * WAVES; k0 < count; k0 += gridDim.x * WAVES) {
-        const int k = k0 + wave;
-        const bool live = k < count;
+        const int kk = k0 + wave;
+        const bool live = kk < count;
+        const size_t k = (size_t)v * a.cap + kk;
         sift3d_keypoint kp{};
         if (live) kp = a.kp[k];
-        const bool valid = live && kp.octave >= 0 && kp.octave < a.n_oct && kp.scale >= 1 && kp.scale <= a.S;
+        const bool valid = live && kp.octave >= 0 && kp.octave < vol.n_units && kp.scale >= 1 && kp.scale <= a.S;
         double d[kMaxPairs / 64] = {0.0, 0.0, 0.0, 0.0};
         if (valid) {
-            const DescOctave &oc = a.oc[kp.octave];
-            const float *B = oc.B + oc.lstride * (kp.scale - 1);
+            const DUnit &oc = (INL ? a.inl[vol.unit0 + kp.octave] : a.units[vol.unit0 + kp.octave]);
+            const float *B = reinterpret_cast<const float *>(a.ws + oc.b1) + oc.lstride * (kp.scale - 1);
             const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
             const int32_t *off = a.pairs + (size_t)(kp.scale - 1) * n * 6;
             for (int q = 0; q < nw; ++q) {
@@ -182,27 +191,34 @@ __global__ void __launch_bounds__(kDescThreads) brief_kernel(const DescribeArgs 
             for (int q = 0; q < kMaxPairs / 64; ++q) {
                 if (q >= nw) break;
                 const unsigned long long m = __ballot(valid && d[q] > 0.0);
-                if (a.brief != nullptr && lane == 0) a.brief[(size_t)k * nw + q] = m;
-                if (a.rrief != nullptr) a.rrief[(size_t)k * n + lane + 64 * q] = (uint8_t)r[q];
+                if (a.brief != nullptr && lane == 0) a.brief[k * nw + q] = m;
+                if (a.rrief != nullptr) a.rrief[k * n + lane + 64 * q] = (uint8_t)r[q];
             }
         }
         __syncthreads();
+    }
     }
 }
 
 }  // namespace
 
-hipError_t launch_describe(const DescribeArgs &a, int grid, hipStream_t st)
+hipError_t launch_describe(const DescLaunch &a, int grid, hipStream_t st)
 {
     if (grid <= 0) return hipSuccess;
     if (a.siftrank != nullptr) {
-        hipLaunchKernelGGL(siftrank_kernel, dim3(grid), dim3(kDescThreads), 0, st, a);
+        if (a.n_units <= kInlineUnits)
+            hipLaunchKernelGGL(siftrank_kernel<true>, dim3(grid), dim3(kDescThreads), 0, st, a);
+        else
+            hipLaunchKernelGGL(siftrank_kernel<false>, dim3(grid), dim3(kDescThreads), 0, st, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if ((a.brief != nullptr || a.rrief != nullptr) && a.brief_n > 0) {
         const int g = (grid + kDescThreads / 64 - 1) / (kDescThreads / 64);
-        hipLaunchKernelGGL(brief_kernel, dim3(g), dim3(kDescThreads), 0, st, a);
+        if (a.n_units <= kInlineUnits)
+            hipLaunchKernelGGL(brief_kernel<true>, dim3(g), dim3(kDescThreads), 0, st, a);
+        else
+            hipLaunchKernelGGL(brief_kernel<false>, dim3(g), dim3(kDescThreads), 0, st, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

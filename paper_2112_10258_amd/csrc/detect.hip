@@ -4,41 +4,101 @@
 // D_{s+1}, the other 26 of D_s) of sign(D_s(v) - neighbour) reaches
 // +votes (peak) or -votes (valley).
 //
-// The candidate space of all octaves is cut into "rows": (octave, s, z, y)
-// over the interior x range, enumerated in canonical order. Three launches
-// turn the per-voxel test into a keypoint list in that order without a
-// sort and without atomics:
-//   count: one wavefront per row, wavefront ballots + popcount, per-row
-//          and per-block counts;
-//   scan:  one workgroup scans the block counts (exclusive) and writes the
-//          total to the device-side count;
-//   emit:  blocks with a non-zero count re-test their non-empty rows and
-//          write each keypoint at block offset + row prefix + ballot rank.
+// The candidate space of all volumes and octaves is cut into "rows": (volume,
+// octave, s, z, y) over the x range, enumerated in canonical order, each
+// volume starting on a block of kRowBlock rows. Launches turn the per-voxel
+// test into per-volume keypoint lists in that order without a sort and
+// without atomics:
+//   test:  per-row keypoint counts (and, on the strict path, bit masks);
+//   scan:  one workgroup scans the per-block counts (exclusive) and writes
+//          each volume's total;
+//   emit:  blocks with keypoints write each one at (block offset - the
+//          volume's first offset) + row prefix + rank within the row.
 #include "sift3d_internal.h"
 
 namespace s3d {
 namespace {
 
+template <typename F>
+__device__ __forceinline__ int last_le(int n, F key, long long v)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (key(mid) <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// INL: units from the inline copy in the arguments, else from the device table.
+template <bool INL>
+__device__ __forceinline__ const DUnit &unit_at(const DetLaunch &a, int i)
+{
+    return INL ? a.inl[i] : a.units[i];
+}
+
 struct RowPos {
-    int o, s, y, z;
+    int u, s, y, z;
+    bool valid;
 };
 
-__device__ __forceinline__ RowPos decode_row(const DetectArgs &a, long long g)
+// Unit and (s, z, y) of global row g; invalid for padding rows.
+template <bool INL>
+__device__ __forceinline__ RowPos decode_row(const DetLaunch &a, long long g)
 {
-    int o = 0;
-    for (int k = 1; k < a.n_oct; ++k)
-        if (g >= a.oc[k].row_base) o = k;
-    const DetOctave &oc = a.oc[o];
-    const long long r = g - oc.row_base;
-    const long long per_s = (long long)(oc.nz - 2) * (oc.ny - 2);
     RowPos p;
-    p.o = o;
+    p.u = last_le(a.n_units, [&](int i) { return unit_at<INL>(a, i).row_base; }, g);
+    const DUnit &un = unit_at<INL>(a, p.u);
+    const long long r = g - un.row_base;
+    p.valid = r >= 0 && r < un.rows;
+    if (!p.valid) {
+        p.s = p.y = p.z = 0;
+        return p;
+    }
+    const long long per_s = (long long)(un.nz - 2) * (un.ny - 2);
     p.s = 1 + (int)(r / per_s);
     const long long rem = r - (long long)(p.s - 1) * per_s;
-    p.z = 1 + (int)(rem / (oc.ny - 2));
-    p.y = 1 + (int)(rem - (long long)(p.z - 1) * (oc.ny - 2));
+    p.z = 1 + (int)(rem / (un.ny - 2));
+    p.y = 1 + (int)(rem - (long long)(p.z - 1) * (un.ny - 2));
     return p;
 }
+
+__device__ __forceinline__ const float *unit_D(const DetLaunch &a, const DUnit &un)
+{
+    return reinterpret_cast<const float *>(a.ws + un.g0) + un.lstride * (a.S + 3);
+}
+
+__device__ __forceinline__ void write_keypoint(const DetLaunch &a, const DUnit &un, int idx, int x, int y, int z,
+                                               int s, int pol, float v)
+{
+    sift3d_keypoint k;
+    k.x = x;
+    k.y = y;
+    k.z = z;
+    k.octave = (int16_t)un.octave;
+    k.scale = (int16_t)s;
+    k.polarity = (int8_t)pol;
+    k.pad[0] = k.pad[1] = k.pad[2] = 0;
+    k.dog = v;
+    const float f = (float)(1 << un.octave);
+    const float h = 0.5f * (f - 1.f);
+    k.xf = f * (float)x + h;
+    k.yf = f * (float)y + h;
+    k.zf = f * (float)z + h;
+    k.sigma = un.sigma[s];
+    a.kp[(size_t)un.vol * a.cap + idx] = k;
+}
+
+// Offset of the first keypoint of volume v in the global order.
+__device__ __forceinline__ int volume_base(const DetLaunch &a, int v)
+{
+    return a.block_off[a.vols[v].row_base / a.rows_per_block];
+}
+
+// ---------------------------------------------------------------- general path (votes < 80)
 
 // +1 peak, -1 valley, 0 otherwise. v = D_s at the voxel; c points at it in D_s.
 // Neighbours are read one 3x3 plane at a time; the test stops as soon as
@@ -75,45 +135,29 @@ __device__ __forceinline__ int extremum(const float *c, long long lstride, int n
 }
 
 // Count (EMIT = false) or write (EMIT = true) the keypoints of one row.
-template <bool EMIT>
-__device__ int process_row(const DetectArgs &a, long long g, int lane, int base)
+template <bool EMIT, bool INL>
+__device__ int process_row(const DetLaunch &a, long long g, int lane, int base)
 {
-    const RowPos rp = decode_row(a, g);
-    const DetOctave &oc = a.oc[rp.o];
-    const long long nxy = (long long)oc.nx * oc.ny;
-    const float *Ds = oc.D + oc.lstride * rp.s;
-    const long long row = (long long)rp.z * nxy + (long long)rp.y * oc.nx;
+    const RowPos rp = decode_row<INL>(a, g);
+    if (!rp.valid) return 0;
+    const DUnit &un = unit_at<INL>(a, rp.u);
+    const long long nxy = (long long)un.nx * un.ny;
+    const float *Ds = unit_D(a, un) + un.lstride * rp.s;
+    const long long row = (long long)rp.z * nxy + (long long)rp.y * un.nx;
     int total = 0;
-    for (int xb = 1; xb <= oc.nx - 2; xb += 64) {
+    for (int xb = 1; xb <= un.nx - 2; xb += 64) {
         const int x = xb + lane;
         int pol = 0;
         float v = 0.f;
-        if (x <= oc.nx - 2) {
+        if (x <= un.nx - 2) {
             v = Ds[row + x];
-            if (fabsf(v) > a.thr) pol = extremum(Ds + row + x, oc.lstride, oc.nx, nxy, v, a.votes);
+            if (fabsf(v) > a.thr) pol = extremum(Ds + row + x, un.lstride, un.nx, nxy, v, a.votes);
         }
         const unsigned long long m = __ballot(pol != 0);
         if constexpr (EMIT) {
             if (pol != 0) {
                 const int idx = base + total + __popcll(m & ((1ull << lane) - 1ull));
-                if (idx < a.cap) {
-                    sift3d_keypoint k;
-                    k.x = x;
-                    k.y = rp.y;
-                    k.z = rp.z;
-                    k.octave = (int16_t)rp.o;
-                    k.scale = (int16_t)rp.s;
-                    k.polarity = (int8_t)pol;
-                    k.pad[0] = k.pad[1] = k.pad[2] = 0;
-                    k.dog = v;
-                    const float f = (float)(1 << rp.o);
-                    const float h = 0.5f * (f - 1.f);
-                    k.xf = f * (float)x + h;
-                    k.yf = f * (float)rp.y + h;
-                    k.zf = f * (float)rp.z + h;
-                    k.sigma = oc.sigma[rp.s];
-                    a.kp[idx] = k;
-                }
+                if (idx < a.cap) write_keypoint(a, un, idx, x, rp.y, rp.z, rp.s, pol, v);
             }
         }
         total += __popcll(m);
@@ -121,7 +165,8 @@ __device__ int process_row(const DetectArgs &a, long long g, int lane, int base)
     return total;
 }
 
-__global__ void __launch_bounds__(kDetThreads) detect_count_kernel(const DetectArgs a)
+template <bool INL>
+__global__ void __launch_bounds__(kDetThreads) detect_count_kernel(const DetLaunch a)
 {
     __shared__ int wsum[kDetThreads / 64];
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -130,7 +175,7 @@ __global__ void __launch_bounds__(kDetThreads) detect_count_kernel(const DetectA
     for (int rr = 0; rr < kDetRowsPerWave; ++rr) {
         const long long g = row0 + rr;
         if (g >= a.total_rows) break;
-        const int c = process_row<false>(a, g, lane, 0);
+        const int c = process_row<false, INL>(a, g, lane, 0);
         if (lane == 0) a.row_count[g] = c;
         sum += c;
     }
@@ -143,7 +188,37 @@ __global__ void __launch_bounds__(kDetThreads) detect_count_kernel(const DetectA
     }
 }
 
-__global__ void __launch_bounds__(kScanThreads) detect_scan_kernel(const DetectArgs a)
+template <bool INL>
+__global__ void __launch_bounds__(kDetThreads) detect_emit_kernel(const DetLaunch a)
+{
+    __shared__ int roff[kDetRowsPerBlock];
+    if (a.block_sum[blockIdx.x] == 0) return;
+    const long long row0 = (long long)blockIdx.x * kDetRowsPerBlock;
+    const RowPos first = decode_row<INL>(a, row0);
+    const int vbase = volume_base(a, unit_at<INL>(a, first.u).vol);
+    if (a.block_off[blockIdx.x] - vbase >= a.cap) return;
+    if (threadIdx.x == 0) {
+        int run = a.block_off[blockIdx.x] - vbase;
+        for (int r = 0; r < kDetRowsPerBlock; ++r) {
+            roff[r] = run;
+            if (row0 + r < a.total_rows) run += a.row_count[row0 + r];
+        }
+    }
+    __syncthreads();
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int rr = 0; rr < kDetRowsPerWave; ++rr) {
+        const int r = wave * kDetRowsPerWave + rr;
+        const long long g = row0 + r;
+        if (g >= a.total_rows) break;
+        if (a.row_count[g] == 0) continue;
+        process_row<true, INL>(a, g, lane, roff[r]);
+    }
+}
+
+// ---------------------------------------------------------------- scan
+
+// Exclusive scan of the block counts (one workgroup) and per-volume totals.
+__global__ void __launch_bounds__(kScanThreads) detect_scan_kernel(const DetLaunch a)
 {
     __shared__ int part[kScanThreads];
     const int tid = threadIdx.x;
@@ -165,34 +240,16 @@ __global__ void __launch_bounds__(kScanThreads) detect_scan_kernel(const DetectA
         a.block_off[b] = run;
         run += a.block_sum[b];
     }
-    if (tid == kScanThreads - 1) *a.d_count = part[kScanThreads - 1];
-}
-
-__global__ void __launch_bounds__(kDetThreads) detect_emit_kernel(const DetectArgs a)
-{
-    __shared__ int roff[kDetRowsPerBlock];
-    if (a.block_sum[blockIdx.x] == 0) return;
-    if (a.block_off[blockIdx.x] >= a.cap) return;
-    const long long row0 = (long long)blockIdx.x * kDetRowsPerBlock;
-    if (threadIdx.x == 0) {
-        int run = a.block_off[blockIdx.x];
-        for (int r = 0; r < kDetRowsPerBlock; ++r) {
-            roff[r] = run;
-            if (row0 + r < a.total_rows) run += a.row_count[row0 + r];
-        }
-    }
-    __syncthreads();
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int rr = 0; rr < kDetRowsPerWave; ++rr) {
-        const int r = wave * kDetRowsPerWave + rr;
-        const long long g = row0 + r;
-        if (g >= a.total_rows) break;
-        if (a.row_count[g] == 0) continue;
-        process_row<true>(a, g, lane, roff[r]);
+    for (int v = tid; v < a.n_vol; v += kScanThreads) {
+        const long long f = a.vols[v].row_base / a.rows_per_block;
+        const long long l = v + 1 < a.n_vol ? a.vols[v + 1].row_base / a.rows_per_block : n;
+        int c = 0;
+        for (long long b = f; b < l; ++b) c += a.block_sum[b];
+        a.counts[v] = c;
     }
 }
 
-// ---------------------------------------------------------------- strict path
+// ---------------------------------------------------------------- strict path (votes == 80)
 // With votes == 80 the sum-of-signs test accepts v exactly when v is above
 // (peak) or below (valley) every one of its 80 neighbours, i.e. above the
 // maximum or below the minimum of them. For scale s that neighbour maximum
@@ -206,35 +263,36 @@ __global__ void __launch_bounds__(kDetThreads) detect_emit_kernel(const DetectAr
 // loaded before the current one is reduced. No LDS, no barriers. Ballots of
 // the flags are the 64-bit words of the per-row keypoint bit masks.
 template <int NL>
-__device__ __forceinline__ void load_plane_rows(const DetOctave &oc, int pz, int x, int xe, int y,
-                                                float (&v)[NL][3], float (&e)[NL][3])
+__device__ __forceinline__ void load_plane_rows(const float *D, long long lstride, int nx, int ny, int pz, int x,
+                                                int xe, int y, float (&v)[NL][3], float (&e)[NL][3])
 {
-    const long long nxy = (long long)oc.nx * oc.ny;
+    const long long nxy = (long long)nx * ny;
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-        const float *pl = oc.D + oc.lstride * l + pz * nxy;
+        const float *pl = D + lstride * l + pz * nxy;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-            const float *row = pl + (long long)min(max(y - 1 + r, 0), oc.ny - 1) * oc.nx;
+            const float *row = pl + (long long)min(max(y - 1 + r, 0), ny - 1) * nx;
             v[l][r] = row[x];
             e[l][r] = row[xe];
         }
     }
 }
 
-template <int S>
-__global__ void __launch_bounds__(256) detect_tile_kernel(const DetectArgs a)
+template <int S, bool INL>
+__global__ void __launch_bounds__(256) detect_tile_kernel(const DetLaunch a)
 {
     constexpr int NL = S + 2;
-    int o = 0;
-    while (o + 1 < a.n_oct && (int)blockIdx.x >= a.oc[o + 1].block0) ++o;
-    const DetOctave &oc = a.oc[o];
-    const int local = blockIdx.x - oc.block0;
-    const int txi = local % oc.tiles_x;
-    const int rest = local / oc.tiles_x;
-    const int tyi = rest % oc.tiles_y, tzi = rest / oc.tiles_y;
+    const int u = last_le(a.n_units, [&](int i) { return (long long)unit_at<INL>(a, i).tile_block0; }, blockIdx.x);
+    const DUnit &un = unit_at<INL>(a, u);
+    const float *D = unit_D(a, un);
+    unsigned long long *masks = reinterpret_cast<unsigned long long *>(a.ws + un.masks);
+    const int local = blockIdx.x - un.tile_block0;
+    const int txi = local % un.tiles_x;
+    const int rest = local / un.tiles_x;
+    const int tyi = rest % un.tiles_y, tzi = rest / un.tiles_y;
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
-    const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
+    const int nx = un.nx, ny = un.ny, nz = un.nz;
     const int x0 = txi * kDTX, y = 1 + tyi * kDTY + wy, z0 = 1 + tzi * kDTZ;
     if (y > ny - 2) return;                          // whole wavefront: no row here
     const int z1 = min(z0 + kDTZ, nz - 1);           // outputs z0 .. z1-1 (interior)
@@ -253,10 +311,10 @@ __global__ void __launch_bounds__(256) detect_tile_kernel(const DetectArgs a)
     for (int l = 0; l <= S; ++l) cen[l][0] = cen[l][1] = rx[l][0] = rx[l][1] = rn[l][0] = rn[l][1] = 0.f;
 
     float v[NL][3], e[NL][3], vn[NL][3], en[NL][3];
-    load_plane_rows<NL>(oc, z0 - 1, x, xe, y, v, e);
+    load_plane_rows<NL>(D, un.lstride, nx, ny, z0 - 1, x, xe, y, v, e);
     const int nplanes = (z1 - z0) + 2;
     for (int k = 0; k < nplanes; ++k) {
-        if (k + 1 < nplanes) load_plane_rows<NL>(oc, z0 + k, x, xe, y, vn, en);
+        if (k + 1 < nplanes) load_plane_rows<NL>(D, un.lstride, nx, ny, z0 + k, x, xe, y, vn, en);
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
             float hx[3], hn[3], left1 = 0.f, right1 = 0.f;
@@ -304,7 +362,7 @@ __global__ void __launch_bounds__(256) detect_tile_kernel(const DetectArgs a)
                 const unsigned long long bits = __ballot(flag);
                 if (lane == 0) {
                     const long long row = (long long)(s - 1) * (nz - 2) * (ny - 2) + row_z;
-                    oc.masks[row * oc.words + txi] = bits;
+                    masks[row * un.words + txi] = bits;
                 }
             }
         }
@@ -318,24 +376,21 @@ __global__ void __launch_bounds__(256) detect_tile_kernel(const DetectArgs a)
     }
 }
 
-__device__ __forceinline__ int row_octave(const DetectArgs &a, long long g)
-{
-    int o = 0;
-    for (int k = 1; k < a.n_oct; ++k)
-        if (g >= a.oc[k].row_base) o = k;
-    return o;
-}
-
 // Keypoints per row (popcount of its words) and per block of kRowBlock rows.
-__global__ void __launch_bounds__(kRowBlock) row_count_kernel(const DetectArgs a)
+template <bool INL>
+__global__ void __launch_bounds__(kRowBlock) row_count_kernel(const DetLaunch a)
 {
     __shared__ int wsum[kRowBlock / 64];
     const long long g = (long long)blockIdx.x * kRowBlock + threadIdx.x;
     int c = 0;
     if (g < a.total_rows) {
-        const DetOctave &oc = a.oc[row_octave(a, g)];
-        const unsigned long long *w = oc.masks + (g - oc.row_base) * oc.words;
-        for (int q = 0; q < oc.words; ++q) c += __popcll(w[q]);
+        const RowPos rp = decode_row<INL>(a, g);
+        if (rp.valid) {
+            const DUnit &un = unit_at<INL>(a, rp.u);
+            const unsigned long long *w =
+                reinterpret_cast<const unsigned long long *>(a.ws + un.masks) + (g - un.row_base) * un.words;
+            for (int q = 0; q < un.words; ++q) c += __popcll(w[q]);
+        }
         a.row_count[g] = c;
     }
     int t = c;
@@ -349,13 +404,18 @@ __global__ void __launch_bounds__(kRowBlock) row_count_kernel(const DetectArgs a
     }
 }
 
-// Keypoint records in canonical order: row offset = block offset + prefix
-// of the block's row counts; within a row, x ascending.
-__global__ void __launch_bounds__(kRowBlock) emit_rows_kernel(const DetectArgs a)
+// Keypoint records in canonical order: row offset = block offset - volume
+// offset + prefix of the block's row counts; within a row, x ascending.
+template <bool INL>
+__global__ void __launch_bounds__(kRowBlock) emit_rows_kernel(const DetLaunch a)
 {
     __shared__ int pre[kRowBlock];
-    if (a.block_sum[blockIdx.x] == 0 || a.block_off[blockIdx.x] >= a.cap) return;
-    const long long g = (long long)blockIdx.x * kRowBlock + threadIdx.x;
+    if (a.block_sum[blockIdx.x] == 0) return;
+    const long long row0 = (long long)blockIdx.x * kRowBlock;
+    const RowPos first = decode_row<INL>(a, row0);
+    const int vbase = volume_base(a, unit_at<INL>(a, first.u).vol);
+    if (a.block_off[blockIdx.x] - vbase >= a.cap) return;
+    const long long g = row0 + threadIdx.x;
     const int c = g < a.total_rows ? a.row_count[g] : 0;
     pre[threadIdx.x] = c;
     __syncthreads();
@@ -366,84 +426,80 @@ __global__ void __launch_bounds__(kRowBlock) emit_rows_kernel(const DetectArgs a
         __syncthreads();
     }
     if (c == 0) return;
-    int idx = a.block_off[blockIdx.x] + pre[threadIdx.x] - c;
-    const int o = row_octave(a, g);
-    const DetOctave &oc = a.oc[o];
-    const long long r = g - oc.row_base;
-    const long long per_s = (long long)(oc.nz - 2) * (oc.ny - 2);
-    const int s = 1 + (int)(r / per_s);
-    const long long rem = r - (long long)(s - 1) * per_s;
-    const int z = 1 + (int)(rem / (oc.ny - 2));
-    const int y = 1 + (int)(rem - (long long)(z - 1) * (oc.ny - 2));
-    const long long nxy = (long long)oc.nx * oc.ny;
-    const float *Ds = oc.D + oc.lstride * s;
-    const float f = (float)(1 << o);
-    const float h = 0.5f * (f - 1.f);
-    for (int q = 0; q < oc.words && idx < a.cap; ++q) {
-        unsigned long long w = oc.masks[r * oc.words + q];
+    int idx = a.block_off[blockIdx.x] - vbase + pre[threadIdx.x] - c;
+    const RowPos rp = decode_row<INL>(a, g);
+    const DUnit &un = unit_at<INL>(a, rp.u);
+    const long long r = g - un.row_base;
+    const long long nxy = (long long)un.nx * un.ny;
+    const float *Ds = unit_D(a, un) + un.lstride * rp.s;
+    const unsigned long long *mw = reinterpret_cast<const unsigned long long *>(a.ws + un.masks) + r * un.words;
+    for (int q = 0; q < un.words && idx < a.cap; ++q) {
+        unsigned long long w = mw[q];
         while (w != 0ull && idx < a.cap) {
             const int x = 64 * q + (__ffsll((long long)w) - 1);
             w &= w - 1ull;
-            const long long vi = (long long)z * nxy + (long long)y * oc.nx + x;
+            const long long vi = (long long)rp.z * nxy + (long long)rp.y * un.nx + x;
             const float v = Ds[vi];
             // a strict extremum differs from every neighbour: one decides peak or valley
             const bool peak = v > Ds[vi + 1];
-            sift3d_keypoint k;
-            k.x = x;
-            k.y = y;
-            k.z = z;
-            k.octave = (int16_t)o;
-            k.scale = (int16_t)s;
-            k.polarity = (int8_t)(peak ? 1 : -1);
-            k.pad[0] = k.pad[1] = k.pad[2] = 0;
-            k.dog = v;
-            k.xf = f * (float)x + h;
-            k.yf = f * (float)y + h;
-            k.zf = f * (float)z + h;
-            k.sigma = oc.sigma[s];
-            a.kp[idx++] = k;
+            write_keypoint(a, un, idx++, x, rp.y, rp.z, rp.s, peak ? 1 : -1, v);
         }
     }
 }
 
-template <int S>
-hipError_t launch_strict(const DetectArgs &a, hipStream_t st)
+template <int S, bool INL>
+hipError_t launch_strict(const DetLaunch &a, hipStream_t st)
 {
-    hipLaunchKernelGGL((detect_tile_kernel<S>), dim3(a.tile_blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((detect_tile_kernel<S, INL>), dim3(a.tile_blocks), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(row_count_kernel, dim3(a.row_blocks), dim3(kRowBlock), 0, st, a);
+    hipLaunchKernelGGL(row_count_kernel<INL>, dim3(a.n_blocks), dim3(kRowBlock), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    DetectArgs b = a;
-    b.n_blocks = a.row_blocks;
-    hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, b);
+    hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(emit_rows_kernel, dim3(a.row_blocks), dim3(kRowBlock), 0, st, a);
+    hipLaunchKernelGGL(emit_rows_kernel<INL>, dim3(a.n_blocks), dim3(kRowBlock), 0, st, a);
     return hipGetLastError();
+}
+
+template <bool INL>
+hipError_t launch_general(const DetLaunch &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(detect_count_kernel<INL>, dim3(a.n_blocks), dim3(kDetThreads), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(detect_emit_kernel<INL>, dim3(a.n_blocks), dim3(kDetThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+template <bool INL>
+hipError_t launch_strict_s(const DetLaunch &a, hipStream_t st)
+{
+    switch (a.S) {
+    case 1: return launch_strict<1, INL>(a, st);
+    case 2: return launch_strict<2, INL>(a, st);
+    case 3: return launch_strict<3, INL>(a, st);
+    case 4: return launch_strict<4, INL>(a, st);
+    case 5: return launch_strict<5, INL>(a, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-hipError_t launch_detect(const DetectArgs &a, hipStream_t st)
+hipError_t launch_detect(const DetLaunch &in, hipStream_t st)
 {
+    DetLaunch a = in;
+    const bool inl = a.n_units <= kInlineUnits;
     if (a.votes == 80) {
-        switch (a.S) {
-        case 1: return launch_strict<1>(a, st);
-        case 2: return launch_strict<2>(a, st);
-        case 3: return launch_strict<3>(a, st);
-        case 4: return launch_strict<4>(a, st);
-        case 5: return launch_strict<5>(a, st);
-        default: return hipErrorInvalidValue;
-        }
+        a.rows_per_block = kRowBlock;
+        a.n_blocks = (int)((a.total_rows + kRowBlock - 1) / kRowBlock);
+        return inl ? launch_strict_s<true>(a, st) : launch_strict_s<false>(a, st);
     }
-    hipLaunchKernelGGL(detect_count_kernel, dim3(a.n_blocks), dim3(kDetThreads), 0, st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(detect_emit_kernel, dim3(a.n_blocks), dim3(kDetThreads), 0, st, a);
-    return hipGetLastError();
+    a.rows_per_block = kDetRowsPerBlock;
+    a.n_blocks = (int)((a.total_rows + kDetRowsPerBlock - 1) / kDetRowsPerBlock);
+    return inl ? launch_general<true>(a, st) : launch_general<false>(a, st);
 }
 
 }  // namespace s3d

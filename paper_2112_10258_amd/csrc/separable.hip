@@ -35,16 +35,24 @@ __device__ __forceinline__ float sym_stencil(const float (&w)[2 * R + 1], F at)
     }
 }
 
-template <typename Args>
-__device__ __forceinline__ int find_job(const Args &a, int bid)
+// Job of a block: the last job whose first block is <= bid (jobs sorted by block0).
+template <typename J>
+__device__ __forceinline__ int find_job(const J *jobs, int n, int bid)
 {
-    int j = 0;
-    while (j + 1 < a.n_jobs && bid >= a.job[j + 1].block0) ++j;
-    return j;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block0 <= bid)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
 template <int R>
-__device__ __forceinline__ void xy_body(const float *__restrict__ wt, const XYJob &jb, int local, float *smem)
+__device__ __forceinline__ void xy_body(const float *__restrict__ wt, const float *__restrict__ vol,
+                                        float *__restrict__ out, const DXYJob &jb, int local, float *smem)
 {
     constexpr int TX = kXYTX, TY = kXYTY, NT = kXYThreads, M = 2 * R + 1;
     constexpr int NYo = TX * TY / NT;               // y outputs per thread
@@ -64,7 +72,7 @@ __device__ __forceinline__ void xy_body(const float *__restrict__ wt, const XYJo
     const int x0 = txi * TX, y0 = tyi * TY;
     const int nx = jb.nx, ny = jb.ny;
     const size_t plane = (size_t)z * nx * ny;
-    const float *src = jb.src + plane;
+    const float *src = vol + plane;
     const int tid = threadIdx.x;
 
     float w[M];
@@ -103,12 +111,14 @@ __device__ __forceinline__ void xy_body(const float *__restrict__ wt, const XYJo
     for (int k = 0; k < NYo; ++k) {
         const float v = sym_stencil<R>(w, [&](int t) { return col[k + t]; });
         const int gy = y0 + tyb + k;
-        if (gx < nx && gy < ny) jb.dst[plane + (size_t)gy * nx + gx] = v;
+        if (gx < nx && gy < ny) out[plane + (size_t)gy * nx + gx] = v;
     }
 }
 
 template <int R>
-__device__ __forceinline__ void z_body(const float *__restrict__ wt, const ZJob &jb, int local)
+__device__ __forceinline__ void z_body(const float *__restrict__ wt, const float *__restrict__ tin,
+                                       const float *__restrict__ center, float *__restrict__ dst,
+                                       float *__restrict__ dog, float *__restrict__ sub, const DZJob &jb, int local)
 {
     constexpr int ZS = kZPlanes, M = 2 * R + 1, WN = ZS + 2 * R;
     static_assert(ZS % 2 == 0, "sub-sampling pairs planes inside a thread");
@@ -129,7 +139,7 @@ __device__ __forceinline__ void z_body(const float *__restrict__ wt, const ZJob 
     for (int t = 0; t < M; ++t) w[t] = wt[t];
     float win[WN];
 #pragma unroll
-    for (int q = 0; q < WN; ++q) win[q] = jb.t[(size_t)clampi(z0 - R + q, 0, nz - 1) * nxy + col];
+    for (int q = 0; q < WN; ++q) win[q] = tin[(size_t)clampi(z0 - R + q, 0, nz - 1) * nxy + col];
     float g[ZS];
 #pragma unroll
     for (int k = 0; k < ZS; ++k) g[k] = sym_stencil<R>(w, [&](int t) { return win[k + t]; });
@@ -140,11 +150,11 @@ __device__ __forceinline__ void z_body(const float *__restrict__ wt, const ZJob 
         const int z = z0 + k;
         if (in_xy && z < nz) {
             const size_t i = (size_t)z * nxy + col;
-            jb.dst[i] = g[k];
-            if (jb.dog != nullptr) jb.dog[i] = jb.center[i] - g[k];
+            dst[i] = g[k];
+            if (dog != nullptr) dog[i] = center[i] - g[k];
         }
     }
-    if (jb.sub != nullptr) {
+    if (sub != nullptr) {
 #pragma unroll
         for (int k = 0; k < ZS; k += 2) {
             float s = g[k] + g[k + 1];
@@ -152,7 +162,7 @@ __device__ __forceinline__ void z_body(const float *__restrict__ wt, const ZJob 
             s += __shfl_xor(s, 32);  // y pair: same lane of the other half-wave
             const int X = x >> 1, Y = y >> 1, Z = (z0 + k) >> 1;
             if ((tx & 1) == 0 && (ty & 1) == 0 && X < jb.mx && Y < jb.my && Z < jb.mz)
-                jb.sub[((size_t)Z * jb.my + Y) * jb.mx + X] = s * 0.125f;
+                sub[((size_t)Z * jb.my + Y) * jb.mx + X] = s * 0.125f;
         }
     }
 }
@@ -177,25 +187,38 @@ __device__ __forceinline__ void z_body(const float *__restrict__ wt, const ZJob 
     case 16: BODY(16); break;  \
     default: break;
 
-__global__ void __launch_bounds__(kXYThreads) blur_xy_kernel(const XYArgs a)
+// INL: the jobs are read from the inline copy in the arguments (small
+// launches), else from the device table.
+template <bool INL>
+__global__ void __launch_bounds__(kXYThreads) blur_xy_kernel(const XYLaunch a)
 {
     extern __shared__ __align__(16) float smem[];
-    const int j = find_job(a, blockIdx.x);
-    const XYJob jb = a.job[j];
-    const float *wt = a.w[jb.taps];
+    const DXYJob jb = INL ? a.inl[find_job(a.inl, a.n_jobs, blockIdx.x)]
+                          : a.jobs[find_job(a.jobs, a.n_jobs, blockIdx.x)];
+    const float *wt = a.taps + (size_t)jb.taps * kMaxTaps;
+    const float *src = jb.src_input ? a.in + jb.src : reinterpret_cast<const float *>(a.ws + jb.src);
+    float *dst = reinterpret_cast<float *>(a.ws + jb.dst);
     const int local = blockIdx.x - jb.block0;
-#define S3D_XY(R) xy_body<R>(wt, jb, local, smem)
+#define S3D_XY(R) xy_body<R>(wt, src, dst, jb, local, smem)
     switch (jb.r) { S3D_RADIUS_CASES(S3D_XY) }
 #undef S3D_XY
 }
 
-__global__ void __launch_bounds__(kZThreads) blur_z_kernel(const ZArgs a)
+template <bool INL>
+__global__ void __launch_bounds__(kZThreads) blur_z_kernel(const ZLaunch a)
 {
-    const int j = find_job(a, blockIdx.x);
-    const ZJob jb = a.job[j];
-    const float *wt = a.w[jb.taps];
+    const DZJob jb = INL ? a.inl[find_job(a.inl, a.n_jobs, blockIdx.x)]
+                         : a.jobs[find_job(a.jobs, a.n_jobs, blockIdx.x)];
+    const float *wt = a.taps + (size_t)jb.taps * kMaxTaps;
+    const float *tin = reinterpret_cast<const float *>(a.ws + jb.t);
+    const float *center = jb.center < 0 ? nullptr
+                          : jb.center_input ? a.in + jb.center
+                                            : reinterpret_cast<const float *>(a.ws + jb.center);
+    float *dst = reinterpret_cast<float *>(a.ws + jb.dst);
+    float *dog = jb.dog < 0 ? nullptr : reinterpret_cast<float *>(a.ws + jb.dog);
+    float *sub = jb.sub < 0 ? nullptr : reinterpret_cast<float *>(a.ws + jb.sub);
     const int local = blockIdx.x - jb.block0;
-#define S3D_Z(R) z_body<R>(wt, jb, local)
+#define S3D_Z(R) z_body<R>(wt, tin, center, dst, dog, sub, jb, local)
     switch (jb.r) { S3D_RADIUS_CASES(S3D_Z) }
 #undef S3D_Z
 }
@@ -209,24 +232,24 @@ static size_t xy_lds_bytes(int r)
     return (size_t)(ah * aw + ah * kXYTX) * sizeof(float);
 }
 
-hipError_t launch_blur_xy(const XYArgs &a, hipStream_t st)
+hipError_t launch_blur_xy(const XYLaunch &a, int max_r, hipStream_t st)
 {
     if (a.n_blocks <= 0) return hipSuccess;
-    size_t lds = 0;
-    for (int j = 0; j < a.n_jobs; ++j) {
-        if (a.job[j].r < 0 || a.job[j].r > kMaxR) return hipErrorInvalidValue;
-        lds = lds > xy_lds_bytes(a.job[j].r) ? lds : xy_lds_bytes(a.job[j].r);
-    }
-    hipLaunchKernelGGL(blur_xy_kernel, dim3(a.n_blocks), dim3(kXYThreads), lds, st, a);
+    if (max_r < 0 || max_r > kMaxR) return hipErrorInvalidValue;
+    if (a.n_jobs <= kInlineJobs)
+        hipLaunchKernelGGL(blur_xy_kernel<true>, dim3(a.n_blocks), dim3(kXYThreads), xy_lds_bytes(max_r), st, a);
+    else
+        hipLaunchKernelGGL(blur_xy_kernel<false>, dim3(a.n_blocks), dim3(kXYThreads), xy_lds_bytes(max_r), st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_blur_z(const ZArgs &a, hipStream_t st)
+hipError_t launch_blur_z(const ZLaunch &a, hipStream_t st)
 {
     if (a.n_blocks <= 0) return hipSuccess;
-    for (int j = 0; j < a.n_jobs; ++j)
-        if (a.job[j].r < 0 || a.job[j].r > kMaxR) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(blur_z_kernel, dim3(a.n_blocks), dim3(kZThreads), 0, st, a);
+    if (a.n_jobs <= kInlineJobs)
+        hipLaunchKernelGGL(blur_z_kernel<true>, dim3(a.n_blocks), dim3(kZThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(blur_z_kernel<false>, dim3(a.n_blocks), dim3(kZThreads), 0, st, a);
     return hipGetLastError();
 }
 

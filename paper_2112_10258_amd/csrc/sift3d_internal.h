@@ -1,5 +1,14 @@
 // Internal declarations of the gfx950 3D SIFT-Rank library: plan geometry,
-// kernel argument blocks and the launchers implemented in the .hip files.
+// the device-side job tables and the launch argument blocks of the kernels.
+//
+// A plan covers one or several volumes. Everything a kernel needs to know
+// about its work (which level of which octave of which volume, its dims,
+// where its inputs and outputs live) sits in small tables that the plan
+// uploads once to device memory. Table entries hold offsets, not pointers:
+// workspace byte offsets, or element offsets into the packed input. Each
+// launch passes the call's base pointers and the kernels add them, so the
+// tables stay valid for any workspace and input buffer, and a launch can
+// cover any number of volumes.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +28,7 @@ constexpr int kMaxTaps = 2 * kMaxR + 1;
 constexpr int kMaxSiftR = 7;                // SIFT-Rank window half-width
 constexpr int kMaxBriefR = 6;               // pre-blur tap radius
 constexpr int kMaxPairs = 256;
+constexpr int kMaxVolumes = 4096;
 
 // Fused blur pass geometry (shared by host planning and the kernel).
 constexpr int kBlurTX = 32;                 // tile width in x (one output column per lane)
@@ -32,7 +42,6 @@ constexpr int kXYTY = 16;                   // xy tile height
 constexpr int kXYThreads = 256;
 constexpr int kZPlanes = 16;                // z outputs per thread
 constexpr int kZThreads = 256;              // 32 (x) x 8 (y) columns
-constexpr int kMaxJobs = 16;                // jobs per xy / z launch
 // Octaves with at least this many voxels use the fused streaming pass.
 constexpr long long kFusedMinVoxels = 24LL << 20;
 
@@ -44,9 +53,64 @@ constexpr int kScanThreads = 1024;
 // Strict-extremum path (votes == 80): one wavefront per (64 x, one y row,
 // kDTZ planes); 4 wavefronts (4 consecutive y rows) per block.
 constexpr int kDTX = 64, kDTY = 4, kDTZ = 16;
-constexpr int kRowBlock = 256;              // rows per count / emit block
+constexpr int kRowBlock = 256;              // rows per count / emit block; volumes start on a block
 
-// One launch of the fused blur -> DoG -> sub-sample pass.
+// ---------------------------------------------------------------- device tables
+
+// One job of an xy launch: the xy blur of one level of one octave.
+struct DXYJob {
+    long long src;        // workspace byte offset, or input element offset if src_input
+    long long dst;        // workspace byte offset
+    int src_input;
+    int nx, ny, nz;
+    int tiles_x, tiles_y;
+    int block0;           // first block of the job within its launch
+    int r, taps;          // tap radius, tap-set index
+    int pad_[3];
+};
+
+// One job of a z launch: the z blur of one level plus its DoG and sub-sample.
+struct DZJob {
+    long long t;          // xy-blurred input (workspace byte offset)
+    long long center;     // level the DoG subtracts from (see center_input), < 0: no DoG
+    long long dst;
+    long long dog;        // < 0: none
+    long long sub;        // < 0: none
+    int center_input;
+    int nx, ny, nz;
+    int mx, my, mz;
+    int gx, gy, gz;       // blocks per axis
+    int block0;
+    int r, taps;
+    int pad_[2];
+};
+
+// One octave of one volume, for detection and description.
+struct DUnit {
+    long long g0;         // workspace byte offset of G_0 (levels G, D, B follow at lstride)
+    long long b1;         // workspace byte offset of the BRIEF level of s = 1 (B_s at (s-1) lstride)
+    long long masks;      // workspace byte offset of the keypoint bit masks [rows][words]
+    long long row_base;   // first global detection row of the unit
+    long long rows;       // S * (nz-2) * (ny-2)
+    long long lstride;    // floats between consecutive levels
+    int nx, ny, nz, octave;
+    int vol, words;       // volume index; 64-bit mask words per row
+    int tiles_x, tiles_y, tiles_z;
+    int tile_block0;      // first block of the unit in the strict-detection launch
+    float sigma[kMaxScales + 1];  // input-space sigma per scale (index s)
+    int pad_[2];
+};
+
+// One volume of the plan.
+struct DVol {
+    long long row_base;   // first global detection row (a multiple of kRowBlock)
+    int unit0, n_units;   // its octaves in the unit table
+};
+
+// ---------------------------------------------------------------- launch arguments
+
+// One launch of the fused blur -> DoG -> sub-sample pass (one level of one
+// octave of one volume; pointers bound per call).
 struct BlurArgs {
     const float *src;     // G_{i-1} (or the input volume)
     float *dst;           // G_i
@@ -60,111 +124,79 @@ struct BlurArgs {
     float w[kMaxTaps];    // taps w[t + r], t = -r..r
 };
 
-constexpr int kMaxTapSets = 8;              // distinct tap sets per xy / z launch
+// Launches with few jobs also carry them inline (read through the scalar
+// cache from the argument segment instead of a dependent global load).
+constexpr int kInlineJobs = 8;
+constexpr int kInlineUnits = 12;
 
-// One job of an xy or z launch: one level of one volume. Jobs of one launch
-// may have different tap radii; each block dispatches on its job's radius.
-struct XYJob {
-    const float *src;
-    float *dst;
-    int nx, ny, nz;
-    int tiles_x, tiles_y;
-    int block0;           // first block of this job in the launch
-    int r;                // tap radius
-    int taps;             // index into XYArgs::w
+struct XYLaunch {
+    const DXYJob *jobs;   // this launch's jobs, block0 ascending
+    int n_jobs, n_blocks;
+    char *ws;
+    const float *in;      // packed input volumes
+    const float *taps;    // [n_tapsets][kMaxTaps]
+    DXYJob inl[kInlineJobs];  // copy of jobs[0..n_jobs) when n_jobs <= kInlineJobs
 };
 
-struct XYArgs {
-    XYJob job[kMaxJobs];
-    int n_jobs;
-    int n_blocks;
-    float w[kMaxTapSets][kMaxTaps];
+struct ZLaunch {
+    const DZJob *jobs;
+    int n_jobs, n_blocks;
+    char *ws;
+    const float *in;
+    const float *taps;
+    DZJob inl[kInlineJobs];
 };
 
-struct ZJob {
-    const float *t;       // xy-blurred input
-    const float *center;  // level the DoG subtracts from (when dog != nullptr)
-    float *dst;
-    float *dog;           // or nullptr
-    float *sub;           // or nullptr
-    int nx, ny, nz;
-    int mx, my, mz;
-    int gx, gy, gz;       // blocks per axis
-    int block0;
-    int r;
-    int taps;
-};
-
-struct ZArgs {
-    ZJob job[kMaxJobs];
-    int n_jobs;
-    int n_blocks;
-    float w[kMaxTapSets][kMaxTaps];
-};
-
-struct DetOctave {
-    const float *D;       // D_0 of the octave
-    long long lstride;    // floats between consecutive levels
-    int nx, ny, nz;
-    int pad_;
-    long long row_base;   // first global row of the octave
-    long long rows;       // S * (nz-2) * (ny-2)
-    float sigma[kMaxScales + 1];  // input-space sigma per scale (index s)
-    unsigned long long *masks;    // [rows][words] keypoint bits, x = 64 w + bit
-    int words;            // ceil(nx / 64)
-    int tiles_x, tiles_y, tiles_z;
-    int block0;           // first tile block of the octave
-};
-
-struct DetectArgs {
-    DetOctave oc[kMaxOctaves];
-    int n_oct;
-    int S;
-    long long total_rows;
-    int n_blocks;
+struct DetLaunch {
+    const DUnit *units;
+    const DVol *vols;
+    int n_units, n_vol, S;
+    long long total_rows;     // including the padding rows between volumes
+    int tile_blocks;          // blocks of the strict tile launch
+    int n_blocks;             // count / scan / emit blocks (rows_per_block rows each)
+    int rows_per_block;
     float thr;
     int votes;
-    int *row_count;       // [total_rows]
-    int *block_sum;       // [n_blocks]
-    int *block_off;       // [n_blocks]
-    int *d_count;         // total keypoints (device)
-    sift3d_keypoint *kp;
+    char *ws;
+    int *row_count;           // [total_rows]
+    int *block_sum;           // [n_blocks]
+    int *block_off;           // [n_blocks]
+    int *counts;              // [n_vol] keypoints found per volume (device)
+    sift3d_keypoint *kp;      // [n_vol][cap]
     int cap;
-    int tile_blocks;      // blocks of the tile launch (all octaves)
-    int row_blocks;       // blocks of kRowBlock rows
+    DUnit inl[kInlineUnits];  // copy of units[0..n_units) when n_units <= kInlineUnits
 };
 
-struct DescOctave {
-    const float *G;       // G_0 of the octave
-    const float *B;       // pre-blurred B_1 (B_s = B + (s-1) * lstride)
-    long long lstride;    // floats between consecutive levels
-    int nx, ny, nz, pad_;
-};
-
-struct DescribeArgs {
-    DescOctave oc[kMaxOctaves];
-    int n_oct;
-    int S;
-    int sift_R[kMaxScales + 1];        // per scale
-    const sift3d_keypoint *kp;
-    const int *d_count;
+struct DescLaunch {
+    const DUnit *units;
+    const DVol *vols;
+    int n_vol, S;
+    int sift_R[kMaxScales + 1];
+    char *ws;
+    const sift3d_keypoint *kp;    // [n_vol][cap]
+    const int *counts;            // [n_vol]
     int cap;
-    uint8_t *siftrank;
-    uint64_t *brief;
-    uint8_t *rrief;
+    uint8_t *siftrank;            // [n_vol][cap][64]
+    uint64_t *brief;              // [n_vol][cap][n/64]
+    uint8_t *rrief;               // [n_vol][cap][n]
     int brief_n;
-    const int32_t *pairs;              // [S][brief_n][2][3] (scale s at index s-1)
+    const int32_t *pairs;         // [S][brief_n][2][3] (scale s at index s-1)
+    int n_units;
+    DUnit inl[kInlineUnits];      // copy of units when n_units <= kInlineUnits
 };
+
+// ---------------------------------------------------------------- host plan
 
 struct OctaveGeom {
     int nx, ny, nz;
     size_t n;             // voxels
     size_t level_bytes;   // one level, padded to 256 bytes
-    size_t base;          // byte offset of G_0 in the workspace
+    size_t base;          // workspace byte offset of G_0
 };
 
-// One pyramid level: G_dst of `octave` from G_src (or the input volume).
+// One pyramid level: G_dst of `octave` of volume `vol` from G_src (or the input).
 struct BlurLaunch {
+    int vol;
     int r;
     bool dog;
     bool fused;           // fused streaming pass, else xy + z jobs
@@ -177,18 +209,27 @@ struct BlurLaunch {
 };
 
 // A unit of work of the pyramid schedule: a level pass (index into
-// sift3d_plan::blur) or the BRIEF pre-blur of G_s of one octave.
+// sift3d_plan::blur) or the BRIEF pre-blur of G_s of one octave of one volume.
 struct Task {
     int kind;             // 0 = level pass, 1 = pre-blur
     int pass;             // level pass index (kind 0)
-    int octave, s;        // pre-blur target (kind 1)
+    int vol, octave, s;   // pre-blur target (kind 1)
 };
 
 // One launch of the schedule: a fused pass, or the xy / z half of a set of
-// split tasks.
+// split tasks (their jobs are entries [first, first + count) of the device
+// job table of that kind).
 struct Step {
     int type;             // 0 = fused pass, 1 = xy launch, 2 = z launch
     std::vector<int> tasks;
+    int first, count, n_blocks, max_r;
+};
+
+struct VolPlan {
+    int nx, ny, nz;
+    size_t in_off;        // element offset in the packed input
+    std::vector<OctaveGeom> oct;
+    int unit0;
 };
 
 }  // namespace s3d
@@ -203,33 +244,44 @@ struct sift3d_ctx {
 
 struct sift3d_plan {
     sift3d_ctx *ctx;
-    int nx, ny, nz, cap;
-    int n_oct;
-    int S;
-    std::vector<s3d::OctaveGeom> oct;
-    size_t pyramid_bytes;
-    size_t row_count_off, block_sum_off, block_off_off, masks_off;
+    int n_vol, cap, S;
+    std::vector<s3d::VolPlan> vols;
+    size_t in_elems;                    // floats of the packed input
+    size_t row_count_off, block_sum_off, block_off_off;
     size_t ws_bytes;
     long long total_rows;
-    int det_blocks;
-    std::vector<s3d::BlurLaunch> blur;  // level passes in dependency order
+    int tile_blocks;
+    std::vector<s3d::BlurLaunch> blur;  // level passes of all volumes in dependency order
     int brief_rb;                       // pre-blur radius (-1: none, B_s = G_s)
     int brief_tapset;
+    double base_sigma;
+    std::vector<double> inc_sigma;      // G_1..G_{S+2}
     std::vector<std::vector<float>> tapsets;  // kMaxTaps floats each
     std::vector<int> tapset_r;
     std::vector<s3d::Task> tasks;
     std::vector<s3d::Step> sched;       // launches of sift3d_build_pyramid
-    double base_sigma;
-    std::vector<double> inc_sigma;      // G_1..G_{S+2}
+    std::vector<int> solo_xy, solo_z;   // per task: index of its single-job entry (-1: fused)
+    // host copies of the device tables
+    std::vector<s3d::DUnit> units;
+    std::vector<s3d::DVol> dvols;
+    std::vector<s3d::DXYJob> xyjobs;
+    std::vector<s3d::DZJob> zjobs;
+    // device tables (one allocation, owned by the plan)
+    void *d_tables;
+    s3d::DUnit *d_units;
+    s3d::DVol *d_vols;
+    s3d::DXYJob *d_xy;
+    s3d::DZJob *d_z;
+    float *d_taps;
 };
 
 namespace s3d {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_blur(const BlurArgs &a, int r, bool dog, hipStream_t st);
-hipError_t launch_detect(const DetectArgs &a, hipStream_t st);
-hipError_t launch_describe(const DescribeArgs &a, int grid, hipStream_t st);
-hipError_t launch_blur_xy(const XYArgs &a, hipStream_t st);
-hipError_t launch_blur_z(const ZArgs &a, hipStream_t st);
+hipError_t launch_blur_xy(const XYLaunch &a, int max_r, hipStream_t st);
+hipError_t launch_blur_z(const ZLaunch &a, hipStream_t st);
+hipError_t launch_detect(const DetLaunch &a, hipStream_t st);
+hipError_t launch_describe(const DescLaunch &a, int grid, hipStream_t st);
 
 // Workspace levels of an octave, in units of one padded level.
 inline int lev_G(int i) { return i; }

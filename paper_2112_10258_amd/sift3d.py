@@ -24,6 +24,7 @@ KEYPOINT_BYTES = 40
 assert KEYPOINT_DTYPE.itemsize == KEYPOINT_BYTES
 
 OK, E_ARG, E_TOO_SMALL, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -5, -6
+PENDING = 1
 
 
 class Params(ctypes.Structure):
@@ -40,6 +41,47 @@ class Params(ctypes.Structure):
         ("brief_blur", ctypes.c_double),
         ("siftrank_factor", ctypes.c_double),
         ("pyramid_mode", ctypes.c_int),
+    ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_size_t),
+        ("n_streams", ctypes.c_int),
+        ("max_inflight", ctypes.c_int),
+        ("kp_capacity", ctypes.c_int),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("hip_error", ctypes.c_int),
+        ("count", ctypes.c_int),
+        ("capacity", ctypes.c_int),
+        ("d_kp", ctypes.c_void_p),
+        ("d_siftrank", ctypes.c_void_p),
+        ("d_brief", ctypes.c_void_p),
+        ("d_rrief", ctypes.c_void_p),
+        ("stream", ctypes.c_int),
+        ("t_submit", ctypes.c_double),
+        ("t_start", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64),
+        ("in_flight", ctypes.c_int),
+        ("pending", ctypes.c_int),
+        ("allocated", ctypes.c_size_t),
+        ("peak_allocated", ctypes.c_size_t),
+        ("hbm_budget", ctypes.c_size_t),
+        ("slot_allocations", ctypes.c_int64),
+        ("slot_evictions", ctypes.c_int64),
     ]
 
 
@@ -72,10 +114,12 @@ def _load():
         "sift3d_destroy": (i, [_vp]),
         "sift3d_pair_offsets": (i, [P(Params), P(ctypes.c_double), i, i, P(ctypes.c_int32)]),
         "sift3d_plan_create": (i, [_vp, i, i, i, i, P(_vp)]),
+        "sift3d_plan_create_batch": (i, [_vp, i, P(i), i, P(_vp)]),
         "sift3d_plan_destroy": (i, [_vp]),
-        "sift3d_plan_info": (i, [_vp, P(sz), P(i)]),
-        "sift3d_plan_octave_dims": (i, [_vp, i, P(i)]),
-        "sift3d_level": (i, [_vp, _vp, i, i, i, P(_vp)]),
+        "sift3d_plan_info": (i, [_vp, P(sz), P(i), P(sz)]),
+        "sift3d_plan_volume": (i, [_vp, i, P(i), P(sz), P(i)]),
+        "sift3d_plan_octave_dims": (i, [_vp, i, i, P(i)]),
+        "sift3d_level": (i, [_vp, _vp, i, i, i, i, P(_vp)]),
         "sift3d_build_pyramid": (i, [_vp, _vp, _vp, sz, _vp]),
         "sift3d_detect": (i, [_vp, _vp, sz, _vp, i, _vp, _vp]),
         "sift3d_describe": (i, [_vp, _vp, sz, _vp, _vp, i, _vp, _vp, _vp, _vp]),
@@ -83,6 +127,16 @@ def _load():
         "sift3d_pyramid_pass_count": (i, [_vp, P(i)]),
         "sift3d_pyramid_pass_info": (i, [_vp, i, P(i), P(sz)]),
         "sift3d_pyramid_pass": (i, [_vp, i, _vp, _vp, sz, _vp]),
+        "sift3d_ctx_params": (i, [_vp, P(Params)]),
+        "sift3d_server_create": (i, [_vp, P(ServerConfig), P(_vp)]),
+        "sift3d_server_footprint": (i, [_vp, i, i, i, P(sz)]),
+        "sift3d_server_submit": (i, [_vp, _vp, i, i, i, P(ctypes.c_int64)]),
+        "sift3d_server_result": (i, [_vp, ctypes.c_int64, i, P(Result)]),
+        "sift3d_server_fetch": (i, [_vp, ctypes.c_int64, _vp, _vp, _vp, _vp]),
+        "sift3d_server_release": (i, [_vp, ctypes.c_int64]),
+        "sift3d_server_stats": (i, [_vp, P(ServerCounters)]),
+        "sift3d_server_clock": (ctypes.c_double, []),
+        "sift3d_server_destroy": (i, [_vp]),
         "sift3d_error_string": (ctypes.c_char_p, [i]),
         "sift3d_last_hip_error": (i, []),
     }
@@ -173,38 +227,72 @@ class Context:
 
 
 class Plan:
-    """Extraction plan for one (nx, ny, nz) shape and keypoint capacity."""
+    """Extraction plan for one volume shape, or for a batch of volumes.
 
-    def __init__(self, ctx: Context, shape_xyz, kp_capacity: int):
+    Plan(ctx, (nx, ny, nz), cap) plans one volume; Plan(ctx, [(nx, ny, nz), ...],
+    cap, batch=True) plans a batch processed together (inputs packed with
+    ``pack_volumes``).
+    """
+
+    def __init__(self, ctx: Context, shape_xyz, kp_capacity: int, batch: bool = False):
         lib = _load()
         self.ctx = ctx
-        self.shape_xyz = tuple(int(v) for v in shape_xyz)
         self.capacity = int(kp_capacity)
         h = _vp()
-        nx, ny, nz = self.shape_xyz
-        _check(lib.sift3d_plan_create(ctx.handle, nx, ny, nz, self.capacity, ctypes.byref(h)), "sift3d_plan_create")
+        if batch:
+            shapes = [tuple(int(v) for v in s) for s in shape_xyz]
+            dims = (ctypes.c_int * (3 * len(shapes)))(*[v for s in shapes for v in s])
+            _check(lib.sift3d_plan_create_batch(ctx.handle, len(shapes), dims, self.capacity, ctypes.byref(h)),
+                   "sift3d_plan_create_batch")
+        else:
+            nx, ny, nz = (int(v) for v in shape_xyz)
+            _check(lib.sift3d_plan_create(ctx.handle, nx, ny, nz, self.capacity, ctypes.byref(h)),
+                   "sift3d_plan_create")
         self.handle = h
         ws = ctypes.c_size_t()
-        no = ctypes.c_int()
-        _check(lib.sift3d_plan_info(h, ctypes.byref(ws), ctypes.byref(no)), "sift3d_plan_info")
+        nv = ctypes.c_int()
+        ne = ctypes.c_size_t()
+        _check(lib.sift3d_plan_info(h, ctypes.byref(ws), ctypes.byref(nv), ctypes.byref(ne)), "sift3d_plan_info")
         self.workspace_bytes = ws.value
-        self.n_octaves = no.value
+        self.n_volumes = nv.value
+        self.input_elems = ne.value
+        self.volumes = []
+        for v in range(self.n_volumes):
+            d = (ctypes.c_int * 3)()
+            off = ctypes.c_size_t()
+            no = ctypes.c_int()
+            _check(lib.sift3d_plan_volume(h, v, d, ctypes.byref(off), ctypes.byref(no)), "sift3d_plan_volume")
+            self.volumes.append({"shape_xyz": tuple(d), "offset": off.value, "n_octaves": no.value})
+        self.shape_xyz = self.volumes[0]["shape_xyz"]
+        self.n_octaves = self.volumes[0]["n_octaves"]
 
-    def octave_dims(self, o: int):
+    def octave_dims(self, o: int, volume: int = 0):
         d = (ctypes.c_int * 3)()
-        _check(_load().sift3d_plan_octave_dims(self.handle, o, d), "sift3d_plan_octave_dims")
+        _check(_load().sift3d_plan_octave_dims(self.handle, volume, o, d), "sift3d_plan_octave_dims")
         return tuple(d)
 
-    def level(self, ws, octave: int, kind: int, idx: int):
+    def level(self, ws, octave: int, kind: int, idx: int, volume: int = 0):
         """torch view [nz, ny, nx] float32 of a level inside the workspace tensor."""
         import torch
         p = _vp()
-        _check(_load().sift3d_level(self.handle, _vp(ws.data_ptr()), octave, kind, idx, ctypes.byref(p)),
+        _check(_load().sift3d_level(self.handle, _vp(ws.data_ptr()), volume, octave, kind, idx, ctypes.byref(p)),
                "sift3d_level")
-        nx, ny, nz = self.octave_dims(octave)
+        nx, ny, nz = self.octave_dims(octave, volume)
         off = p.value - ws.data_ptr()
         n = nx * ny * nz
         return ws[off:off + 4 * n].view(torch.float32).view(nz, ny, nx)
+
+    def pack_volumes(self, vols, device="cuda"):
+        """One device buffer holding the volumes at the plan's input offsets."""
+        import torch
+        buf = torch.zeros(max(self.input_elems, 1), dtype=torch.float32, device=device)
+        for v, vol in enumerate(vols):
+            info = self.volumes[v]
+            nx, ny, nz = info["shape_xyz"]
+            t = torch.as_tensor(np.ascontiguousarray(vol, dtype=np.float32)).reshape(-1)
+            assert t.numel() == nx * ny * nz
+            buf[info["offset"]:info["offset"] + t.numel()].copy_(t)
+        return buf
 
     def alloc_workspace(self, device="cuda"):
         import torch
@@ -215,16 +303,16 @@ class Plan:
                                             _vp(_stream(stream))), "sift3d_build_pyramid")
 
     def pyramid_passes(self):
-        """[(octave, level, radius, writes_sub, algorithmic_bytes, fused)] in dependency order."""
+        """[(octave, level, radius, writes_sub, algorithmic_bytes, fused, volume)] in dependency order."""
         lib = _load()
         n = ctypes.c_int()
         _check(lib.sift3d_pyramid_pass_count(self.handle, ctypes.byref(n)), "sift3d_pyramid_pass_count")
         out = []
         for i in range(n.value):
-            info = (ctypes.c_int * 5)()
+            info = (ctypes.c_int * 6)()
             b = ctypes.c_size_t()
             _check(lib.sift3d_pyramid_pass_info(self.handle, i, info, ctypes.byref(b)), "sift3d_pyramid_pass_info")
-            out.append((info[0], info[1], info[2], info[3], b.value, info[4]))
+            out.append((info[0], info[1], info[2], info[3], b.value, info[4], info[5]))
         return out
 
     def pyramid_pass(self, i, vol, ws, stream=None):
@@ -260,34 +348,118 @@ class Plan:
 
 
 class Buffers:
-    """Device buffers (torch) for one plan: workspace, keypoints, count, descriptors."""
+    """Device buffers (torch) for one plan: workspace, keypoints, counts, descriptors."""
 
     def __init__(self, plan: Plan, device="cuda"):
         import torch
-        cap = plan.capacity
+        cap = max(plan.capacity, 1)
+        nv = plan.n_volumes
         n = plan.ctx.params.brief_n
         self.ws = plan.alloc_workspace(device)
-        self.kp = torch.zeros(max(cap, 1) * KEYPOINT_BYTES, dtype=torch.uint8, device=device)
-        self.count = torch.zeros(1, dtype=torch.int32, device=device)
-        self.siftrank = torch.zeros(max(cap, 1), 64, dtype=torch.uint8, device=device)
-        self.brief = torch.zeros(max(cap, 1), max(n // 64, 1), dtype=torch.int64, device=device)
-        self.rrief = torch.zeros(max(cap, 1), max(n, 1), dtype=torch.uint8, device=device)
+        self.kp = torch.zeros(nv * cap * KEYPOINT_BYTES, dtype=torch.uint8, device=device)
+        self.count = torch.zeros(nv, dtype=torch.int32, device=device)
+        self.siftrank = torch.zeros(nv * cap, 64, dtype=torch.uint8, device=device)
+        self.brief = torch.zeros(nv * cap, max(n // 64, 1), dtype=torch.int64, device=device)
+        self.rrief = torch.zeros(nv * cap, max(n, 1), dtype=torch.uint8, device=device)
 
 
 def run_extract(plan: Plan, vol, buf: Buffers, stream=None):
     plan.extract(vol, buf.ws, buf.kp, buf.count, buf.siftrank, buf.brief, buf.rrief, stream=stream)
 
 
-def fetch_results(plan: Plan, buf: Buffers):
-    """Copy keypoints and descriptors to host numpy (synchronises)."""
-    count = int(buf.count.item())
+def fetch_results(plan: Plan, buf: Buffers, volume: int = 0):
+    """Copy one volume's keypoints and descriptors to host numpy (synchronises)."""
+    cap = max(plan.capacity, 1)
+    count = int(buf.count[volume].item())
     k = min(count, plan.capacity)
-    kp = buf.kp[: k * KEYPOINT_BYTES].cpu().numpy().view(KEYPOINT_DTYPE)
+    base = volume * cap
+    kp = buf.kp[base * KEYPOINT_BYTES:(base + k) * KEYPOINT_BYTES].cpu().numpy().view(KEYPOINT_DTYPE)
     n = plan.ctx.params.brief_n
     return {
         "count": count,
         "keypoints": kp,
-        "siftrank": buf.siftrank[:k].cpu().numpy(),
-        "brief": buf.brief[:k].cpu().numpy().view(np.uint64)[:, : n // 64],
-        "rrief": buf.rrief[:k].cpu().numpy()[:, :n],
+        "siftrank": buf.siftrank[base:base + k].cpu().numpy(),
+        "brief": buf.brief[base:base + k].cpu().numpy().view(np.uint64)[:, : n // 64],
+        "rrief": buf.rrief[base:base + k].cpu().numpy()[:, :n],
     }
+
+
+class Server:
+    """Continuous-batching request server (sift3d_server_*): submit device
+    volumes as they arrive, poll or wait for results, release their slots."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, n_streams: int = 4, max_inflight: int = 8,
+                 kp_capacity: int = 1 << 14):
+        lib = _load()
+        self.ctx = ctx
+        self.capacity = int(kp_capacity)
+        cfg = ServerConfig(int(hbm_budget), int(n_streams), int(max_inflight), int(kp_capacity))
+        h = ctypes.c_void_p()
+        _check(lib.sift3d_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "sift3d_server_create")
+        self.handle = h
+        self._inputs = {}
+
+    @staticmethod
+    def clock() -> float:
+        return _load().sift3d_server_clock()
+
+    def footprint(self, shape_xyz) -> int:
+        b = ctypes.c_size_t()
+        nx, ny, nz = (int(v) for v in shape_xyz)
+        _check(_load().sift3d_server_footprint(self.handle, nx, ny, nz, ctypes.byref(b)), "sift3d_server_footprint")
+        return b.value
+
+    def submit(self, vol) -> int:
+        """Queue one volume (a contiguous float32 [nz, ny, nx] CUDA tensor whose
+        producing work has completed); returns the ticket."""
+        nz, ny, nx = vol.shape
+        t = ctypes.c_int64()
+        _check(_load().sift3d_server_submit(self.handle, _ptr(vol), nx, ny, nz, ctypes.byref(t)),
+               "sift3d_server_submit")
+        self._inputs[t.value] = vol
+        return t.value
+
+    def result(self, ticket: int, wait: bool = True):
+        """Result struct of a ticket, or None if wait is False and it is not finished."""
+        r = Result()
+        rc = _load().sift3d_server_result(self.handle, int(ticket), 1 if wait else 0, ctypes.byref(r))
+        if rc == PENDING:
+            return None
+        _check(rc, "sift3d_server_result")
+        return r
+
+    def fetch(self, ticket: int):
+        """Host copies of a finished request's keypoints and descriptors."""
+        r = self.result(ticket, wait=True)
+        _check(r.status, "server request")
+        k = min(r.count, r.capacity)
+        n = self.ctx.params.brief_n
+        kp = np.zeros(k, dtype=KEYPOINT_DTYPE)
+        sr = np.zeros((k, 64), dtype=np.uint8)
+        br = np.zeros((k, max(n // 64, 1)), dtype=np.uint64)
+        rr = np.zeros((k, max(n, 1)), dtype=np.uint8)
+        _check(_load().sift3d_server_fetch(self.handle, int(ticket), kp.ctypes.data, sr.ctypes.data,
+                                           br.ctypes.data if n else None, rr.ctypes.data if n else None),
+               "sift3d_server_fetch")
+        return {"count": r.count, "keypoints": kp, "siftrank": sr, "brief": br[:, : n // 64], "rrief": rr[:, :n]}
+
+    def release(self, ticket: int):
+        _check(_load().sift3d_server_release(self.handle, int(ticket)), "sift3d_server_release")
+        self._inputs.pop(int(ticket), None)
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(_load().sift3d_server_stats(self.handle, ctypes.byref(c)), "sift3d_server_stats")
+        return {f: getattr(c, f) for f, _ in ServerCounters._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _load().sift3d_server_destroy(self.handle)
+            self.handle = None
+            self._inputs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -66,3 +66,38 @@ def test_bad_params_rejected():
     assert ei.value.code == -6
     with pytest.raises(S.Sift3dError):
         S.pair_offsets(S.default_params(), draws[:10], 1)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors have the sizes and field offsets the C compiler
+    gives the header's structs."""
+    import shutil
+    import subprocess
+
+    import paper_2112_10258_amd.sift3d as S
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    mirrors = {"sift3d_params": S.Params, "sift3d_server_config": S.ServerConfig,
+               "sift3d_result": S.Result, "sift3d_server_counters": S.ServerCounters}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sift3d.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append('printf("sift3d_keypoint %zu\\n", sizeof(sift3d_keypoint));')
+    for f in S.KEYPOINT_DTYPE.names:
+        lines.append(f'printf("sift3d_keypoint.{f} %zu\\n", offsetof(sift3d_keypoint, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True)
+               .stdout.splitlines())
+    for cname, py in mirrors.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+    assert int(got["sift3d_keypoint"]) == S.KEYPOINT_DTYPE.itemsize
+    for f in S.KEYPOINT_DTYPE.names:
+        assert int(got[f"sift3d_keypoint.{f}"]) == S.KEYPOINT_DTYPE.fields[f][1], f
