@@ -76,7 +76,7 @@ def read_traffic(workload):
     return None if w is None else w.get("hbm_bytes_per_launch")
 
 
-def batch_vs_plain(steps, stream):
+def batch_vs_plain(steps, stream, extra):
     """32 mixed-size volumes (each axis U{96..192}): one batch-plan call per step
     against 32 one-volume calls per step. Inputs resident in HBM."""
     import torch
@@ -86,7 +86,7 @@ def batch_vs_plain(steps, stream):
     vols = P.config3()
     shapes = [(v.shape[2], v.shape[1], v.shape[0]) for v in vols]
     cap = 1 << 14
-    ctx = S.Context(S.default_params(), P.pair_draws())
+    ctx = S.Context(S.default_params(**extra), P.pair_draws())
     bplan = S.Plan(ctx, shapes, cap, batch=True)
     bbuf = S.Buffers(bplan)
     packed = bplan.pack_volumes(vols)
@@ -128,6 +128,133 @@ def batch_vs_plain(steps, stream):
     }
 
 
+def _pct(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
+
+
+def serve_vs_plain(n_req, rate, pool_per_class, n_streams, max_inflight, budget_gb, stream, extra):
+    """The config-5 request stream through the server against a plain
+    one-request-at-a-time loop: saturated throughput (all requests queued at
+    once) and latency at the Poisson arrival rate. Volumes come from a pool of
+    pool_per_class distinct volumes per size class, resident in HBM."""
+    import threading
+
+    import torch
+
+    import paper_2112_10258_amd as S
+    from gen import phantoms as P
+    reqs = P.config5_requests(n_req, rate)
+    sizes = list(P.CONFIG5_SIZES)
+    pool = {}
+    t0 = time.perf_counter()
+    for c, sh in enumerate(sizes):
+        pool[sh] = [torch.from_numpy(P.noise_blob_volume(sh, 5000 + 100 * c + j)).cuda()
+                    for j in range(pool_per_class)]
+    torch.cuda.synchronize()
+    log(f"[bench] serve: pool of {pool_per_class} volumes per size class built in {time.perf_counter() - t0:.1f} s")
+    work = [(arr, sh, pool[sh][i % pool_per_class], i % pool_per_class) for i, (arr, sh, _) in enumerate(reqs)]
+    cap = 1 << 14
+    ctx = S.Context(S.default_params(**extra), P.pair_draws())
+
+    # plain path: one plan and buffer set per shape, one request per call
+    plans = {sh: S.Plan(ctx, sh, cap) for sh in sizes}
+    bufs = {sh: S.Buffers(plans[sh]) for sh in sizes}
+    plain_counts = {}
+    for sh in sizes:
+        for j in range(pool_per_class):
+            S.run_extract(plans[sh], pool[sh][j], bufs[sh], stream=stream)
+            torch.cuda.synchronize()
+            plain_counts[(sh, j)] = int(bufs[sh].count.item())
+
+    def plain_all():
+        for _, sh, dv, _ in work:
+            S.run_extract(plans[sh], dv, bufs[sh], stream=stream)
+
+    plain_all()
+    torch.cuda.synchronize()
+    ms_plain = time_calls(plain_all, 1, stream)
+
+    # plain loop at the arrival rate: each request runs when it has arrived and
+    # the previous one is done
+    lat_plain = []
+    t_begin = time.perf_counter()
+    for arr, sh, dv, _ in work:
+        while time.perf_counter() - t_begin < arr:
+            time.sleep(min(1e-4, max(0.0, arr - (time.perf_counter() - t_begin))))
+        S.run_extract(plans[sh], dv, bufs[sh], stream=stream)
+        stream.synchronize()
+        lat_plain.append(time.perf_counter() - t_begin - arr)
+    wall_plain = time.perf_counter() - t_begin
+    del bufs, plans
+    torch.cuda.empty_cache()
+
+    srv = S.Server(ctx, hbm_budget=int(budget_gb * (1 << 30)), n_streams=n_streams, max_inflight=max_inflight,
+                   kp_capacity=cap)
+    mismatch = 0
+
+    def run(items, paced):
+        """Submit items (at their arrival times if paced) from one thread while
+        this one collects and releases results in order."""
+        nonlocal mismatch
+        tickets, times = [], []
+        cv = threading.Condition()
+
+        def submitter():
+            t_begin = time.perf_counter()
+            for arr, _, dv, _ in items:
+                if paced:
+                    while time.perf_counter() - t_begin < arr:
+                        time.sleep(min(1e-4, max(0.0, arr - (time.perf_counter() - t_begin))))
+                t = srv.submit(dv)
+                with cv:
+                    tickets.append(t)
+                    cv.notify()
+
+        sub = threading.Thread(target=submitter)
+        t0 = time.perf_counter()
+        sub.start()
+        for k in range(len(items)):
+            with cv:
+                while len(tickets) <= k:
+                    cv.wait()
+                t = tickets[k]
+            r = srv.result(t)
+            if r.status != 0 or r.count != plain_counts[(items[k][1], items[k][3])]:
+                mismatch += 1
+            times.append((r.t_submit, r.t_start, r.t_done))
+            srv.release(t)
+        sub.join()
+        return times, time.perf_counter() - t0
+
+    run(work[:100], False)          # warm the plan and slot caches
+    mismatch = 0
+    times, _ = run(work, False)     # saturated: all requests queued at once
+    served_sat = len(work) / (max(t[2] for t in times) - min(t[0] for t in times))
+    times, wall_served = run(work, True)   # Poisson arrivals
+    lat_served = [d - s for s, _, d in times]
+    st = srv.stats()
+    srv.close()
+    del pool
+    torch.cuda.empty_cache()
+    plain_sat = len(work) * 1000.0 / ms_plain
+    return {
+        "workload": f"config5: {n_req} requests, Poisson {rate:g}/s, sizes {sizes} w.p. {list(P.CONFIG5_PROBS)}",
+        "volumes_pool": f"{pool_per_class} distinct volumes per size class (request i uses volume i mod {pool_per_class})",
+        "server": {"n_streams": n_streams, "max_inflight": max_inflight, "hbm_budget_gb": budget_gb,
+                   "peak_allocated_gb": round(st["peak_allocated"] / 2**30, 3),
+                   "slot_allocations": st["slot_allocations"], "slot_evictions": st["slot_evictions"]},
+        "saturated": {"served_volumes_per_s": round(served_sat, 1), "plain_volumes_per_s": round(plain_sat, 1),
+                      "served_vs_plain": round(served_sat / plain_sat, 3)},
+        "poisson": {"served_p50_ms": round(_pct(lat_served, 50) * 1e3, 3),
+                    "served_p99_ms": round(_pct(lat_served, 99) * 1e3, 3),
+                    "served_volumes_per_s": round(len(work) / wall_served, 1),
+                    "plain_p50_ms": round(_pct(lat_plain, 50) * 1e3, 3),
+                    "plain_p99_ms": round(_pct(lat_plain, 99) * 1e3, 3),
+                    "plain_volumes_per_s": round(len(work) / wall_plain, 1)},
+        "count_mismatches_vs_plain": mismatch,
+    }
+
+
 def cpu_baseline(vol, kw, budget_s):
     import oracle as O
     from gen import phantoms as P
@@ -156,6 +283,15 @@ def main():
     ap.add_argument("--pass-reps", type=int, default=20)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--pyramid-mode", type=int, default=None, choices=[0, 1, 2],
+                    help="0 = by octave size, 1 = fused streaming passes, 2 = xy + z launches")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-pool", type=int, default=4)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-inflight", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); volumes are independent, "
@@ -168,6 +304,8 @@ def main():
     from gen import phantoms as P
 
     desc, kw = WORKLOADS[args.workload]
+    extra = {} if args.pyramid_mode is None else {"pyramid_mode": args.pyramid_mode}
+    kw = dict(kw, **extra)
     log(f"[bench] workload {args.workload}: {desc}")
     vol = make_volume(args.workload)
     nz, ny, nx = vol.shape
@@ -237,8 +375,14 @@ def main():
     if not args.no_batch:
         del buf
         torch.cuda.empty_cache()
-        batch = batch_vs_plain(args.batch_steps, stream)
+        batch = batch_vs_plain(args.batch_steps, stream, extra)
         log(f"[bench] batch: {batch}")
+
+    serve = None
+    if not args.no_serve:
+        serve = serve_vs_plain(args.serve_requests, args.serve_rate, args.serve_pool, args.serve_streams,
+                               args.serve_inflight, args.serve_budget_gb, stream, extra)
+        log(f"[bench] serve: {serve}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -270,6 +414,7 @@ def main():
                       "brief_rrief": round(st_br, 4)},
         "roofline": roofline,
         "batch": batch,
+        "serve": serve,
         "cpu_baseline": cpu,
         "paper_context": "paper: 1.4 s CPU, 0.2 s GPU per 145x174x145 volume (~3000 keypoints, hardware unnamed)",
     }

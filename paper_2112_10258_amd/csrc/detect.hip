@@ -240,12 +240,24 @@ __global__ void __launch_bounds__(kScanThreads) detect_scan_kernel(const DetLaun
         a.block_off[b] = run;
         run += a.block_sum[b];
     }
+    // keypoints of volume v = prefix(first block of v+1) - prefix(first block of v),
+    // with prefix(b) the exclusive sum of block_sum[0..b): the thread-level
+    // partials in LDS plus at most `per` block sums
+    auto prefix = [&](long long b) -> int {
+        if (b >= n) return part[kScanThreads - 1];
+        const int t = (int)(b / per);
+        int r = t ? part[t - 1] : 0;
+        for (long long q = (long long)t * per; q < b; ++q) r += a.block_sum[q];
+        return r;
+    };
     for (int v = tid; v < a.n_vol; v += kScanThreads) {
+        if (per == 0) {
+            a.counts[v] = 0;
+            continue;
+        }
         const long long f = a.vols[v].row_base / a.rows_per_block;
         const long long l = v + 1 < a.n_vol ? a.vols[v + 1].row_base / a.rows_per_block : n;
-        int c = 0;
-        for (long long b = f; b < l; ++b) c += a.block_sum[b];
-        a.counts[v] = c;
+        a.counts[v] = prefix(l) - prefix(f);
     }
 }
 
