@@ -53,27 +53,113 @@ def time_calls(fn, reps, stream):
     return s.elapsed_time(e) / reps
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pyramid_pass_hbm_traffic.json")
+COPY_BYTES = 1 << 30
+
+
 def kernel_source_hash():
+    """Hash of the pyramid kernel sources and their shared header."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2112_10258_amd", "csrc", "pyramid.hip"), "rb") as f:
-        h.update(f.read())
+    for f in ("pyramid.hip", "separable.hip", "sift3d_internal.h"):
+        with open(os.path.join(ROOT, "paper_2112_10258_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def read_traffic(workload):
-    """Per-launch HBM bytes of the blur pass from the committed counter summary,
-    or None if absent or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "blur_level_kernel_pmc.json")
-    if not os.path.exists(path):
+    """Measured bytes beyond L2 per octave-0 level pass from the committed
+    counter summary, or None if absent or taken on a different kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
         return None
     try:
-        d = json.load(open(path))
+        d = json.load(open(PMC_SUMMARY))
     except ValueError:
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     w = d.get("workloads", {}).get(workload)
     return None if w is None else w.get("hbm_bytes_per_launch")
+
+
+def octave0_grids(shape_xyz):
+    """Grid sizes (threads) of a solo octave-0 level pass: fused, xy, z."""
+    nx, ny, nz = shape_xyz
+    cdiv = lambda a, b: (a + b - 1) // b  # noqa: E731
+    return {"xy": cdiv(nx, 64) * cdiv(ny, 16) * nz * 256, "z": cdiv(nx, 32) * cdiv(ny, 8) * cdiv(nz, 16) * 256}
+
+
+def summarize_pmc(fetch_dir, write_dir, workloads, out_path):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of two rocprofv3 --pmc runs
+    of this script (with --copy-calibration) -> bytes per octave-0 level pass,
+    scaled by what the same counters read for a 1 GiB device copy."""
+    import csv
+    import glob
+
+    def rows(d, counter):
+        fs = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not fs:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        out = []
+        for f in fs:
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") == counter:
+                    out.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"]),
+                                int(r.get("Dispatch_Id", 0))))
+        return out
+
+    fr, wr = rows(fetch_dir, "FETCH_SIZE"), rows(write_dir, "WRITE_SIZE")
+
+    def copy_kib(rs):
+        c = [v for k, g, v, _ in rs if ("copy" in k.lower() or "elementwise" in k.lower()) and v * 1024 > COPY_BYTES / 2]
+        if not c:
+            raise SystemExit("copy calibration dispatch not found")
+        return float(np.median(c))
+
+    cf, cw = copy_kib(fr), copy_kib(wr)
+    f_factor, w_factor = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
+    calib = {"bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
+             "fetch_factor": round(f_factor, 4), "write_factor": round(w_factor, 4)}
+    out = {"what": "bytes beyond L2 (TCC FETCH_SIZE + WRITE_SIZE) per octave-0 level pass, "
+                   "scaled by the counters' reading on a plain 1 GiB device copy",
+           "kernel_source_sha256_16": kernel_source_hash(), "workloads": {}}
+    if os.path.exists(out_path):
+        try:
+            old = json.load(open(out_path))
+            if old.get("kernel_source_sha256_16") == out["kernel_source_sha256_16"]:
+                out["workloads"] = old.get("workloads", {})
+        except ValueError:
+            pass
+    for wl, shape in workloads.items():
+        grids = octave0_grids(shape)
+        res = {}
+        for kname, key in (("blur_level_kernel", None), ("blur_xy_kernel", "xy"), ("blur_z_kernel", "z")):
+            sel_f = [v for k, g, v, _ in fr if k.startswith(kname) and (key is None or g == grids[key])]
+            sel_w = [v for k, g, v, _ in wr if k.startswith(kname) and (key is None or g == grids[key])]
+            if key is None and sel_f:
+                # fused passes: the octave-0 ones are the largest dispatches
+                top = max(g for k, g, _, _ in fr if k.startswith(kname))
+                sel_f = [v for k, g, v, _ in fr if k.startswith(kname) and g == top]
+                sel_w = [v for k, g, v, _ in wr if k.startswith(kname) and g == top]
+            if sel_f and sel_w:
+                res[kname] = {"dispatches": len(sel_f),
+                              "fetch_bytes": float(np.mean(sel_f)) * 1024 * f_factor,
+                              "write_bytes": float(np.mean(sel_w)) * 1024 * w_factor}
+        if "blur_level_kernel" in res:
+            k = res["blur_level_kernel"]
+            tot = k["fetch_bytes"] + k["write_bytes"]
+            kern = "blur_level_kernel"
+        elif "blur_xy_kernel" in res and "blur_z_kernel" in res:
+            tot = sum(res[k]["fetch_bytes"] + res[k]["write_bytes"] for k in ("blur_xy_kernel", "blur_z_kernel"))
+            kern = "blur_xy_kernel + blur_z_kernel"
+        else:
+            continue
+        out["workloads"][wl] = {"kernel": kern, "shape_xyz": list(shape), "per_kernel": res,
+                                "hbm_bytes_per_launch": int(tot), "copy_calibration": calib,
+                                "fetch_dir": fetch_dir, "write_dir": write_dir}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out, indent=1))
 
 
 def batch_vs_plain(steps, stream, extra):
@@ -284,6 +370,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB on the device a few times (reference dispatch for counter runs)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic summary from two rocprofv3 --pmc runs and exit (no GPU)")
     ap.add_argument("--pyramid-mode", type=int, default=None, choices=[0, 1, 2],
                     help="0 = by octave size, 1 = fused streaming passes, 2 = xy + z launches")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -293,6 +383,11 @@ def main():
     ap.add_argument("--serve-inflight", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     args = ap.parse_args()
+    if args.summarize_pmc:
+        shapes = {"config2": (145, 174, 145), "config4": (512, 512, 384)}
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], {args.workload: shapes[args.workload]},
+                      PMC_SUMMARY)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); volumes are independent, "
               "a multi-GPU run would be N copies of this one", file=sys.stderr)
@@ -302,6 +397,15 @@ def main():
 
     import paper_2112_10258_amd as S
     from gen import phantoms as P
+
+    if args.copy_calibration:
+        a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
 
     desc, kw = WORKLOADS[args.workload]
     extra = {} if args.pyramid_mode is None else {"pyramid_mode": args.pyramid_mode}

@@ -93,9 +93,20 @@ void pair_offsets(const sift3d_params &p, const double *draws, int s, int32_t *o
         }
 }
 
+// Planes per xy block: 4 while that still leaves >= 1024 blocks for the
+// octave (4 per CU), fewer on small octaves.
+int xy_planes(const OctaveGeom &g)
+{
+    const int tiles = ((g.nx + kXYTX - 1) / kXYTX) * ((g.ny + kXYTY - 1) / kXYTY);
+    int P = 4;
+    while (P > 1 && tiles * ((g.nz + P - 1) / P) < 1024) P /= 2;
+    return P;
+}
+
 int xy_blocks(const OctaveGeom &g)
 {
-    return ((g.nx + kXYTX - 1) / kXYTX) * ((g.ny + kXYTY - 1) / kXYTY) * g.nz;
+    const int P = xy_planes(g);
+    return ((g.nx + kXYTX - 1) / kXYTX) * ((g.ny + kXYTY - 1) / kXYTY) * ((g.nz + P - 1) / P);
 }
 
 int z_blocks(const OctaveGeom &g)
@@ -158,6 +169,7 @@ void task_jobs(const sift3d_plan *pl, const Task &k, DXYJob &xy, DZJob &z)
     xy.nz = z.nz = g->nz;
     xy.tiles_x = (g->nx + kXYTX - 1) / kXYTX;
     xy.tiles_y = (g->ny + kXYTY - 1) / kXYTY;
+    xy.planes = xy_planes(*g);
     z.mx = sub ? sub->nx : 0;
     z.my = sub ? sub->ny : 0;
     z.mz = sub ? sub->nz : 0;
@@ -528,7 +540,7 @@ int run_step(const sift3d_plan *plan, const Step &stp, const float *d_in, void *
         a.taps = plan->d_taps;
         if (stp.count <= kInlineJobs)
             for (int j = 0; j < stp.count; ++j) a.inl[j] = plan->zjobs[stp.first + j];
-        e = launch_blur_z(a, st);
+        e = launch_blur_z(a, stp.max_r, st);
     }
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }
@@ -802,7 +814,8 @@ int sift3d_describe(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes, 
     a.n_units = (int)plan->units.size();
     if (a.n_units <= kInlineUnits)
         for (int u = 0; u < a.n_units; ++u) a.inl[u] = plan->units[u];
-    const int grid = std::min(kp_capacity, 4096);
+    // two workgroups per CU are resident (LDS and registers); blocks loop over the keypoints
+    const int grid = (int)std::min<long long>((long long)kp_capacity * plan->n_vol, 1024);
     const hipError_t e = launch_describe(a, grid, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }

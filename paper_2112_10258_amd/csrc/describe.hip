@@ -1,8 +1,10 @@
 // Keypoint descriptors on gfx950: upright 3D SIFT-Rank (Section 2: 2x2x2
 // spatial x 8 orientation bins, normalised by ranking) and the BRIEF /
-// RRIEF descriptors (Section 3.2.3). One workgroup (4 wavefronts) per
-// keypoint; workgroups loop over the keypoint list, whose length is read
-// from device memory, so the launch never waits on the host.
+// RRIEF descriptors (Section 3.2.3), in one launch. One workgroup (4
+// wavefronts) per keypoint; workgroups loop over the keypoint lists, whose
+// lengths are read from device memory, so the launch never waits on the
+// host. The keypoints of all volumes of a plan are dealt to the workgroups
+// as one flat sequence.
 //
 // Floating-point sums are accumulated in double precision in a fixed order
 // (no atomics), so results are bit-reproducible run to run.
@@ -58,64 +60,131 @@ __device__ __forceinline__ void sift_column(const float *G, int nx, int ny, int 
     }
 }
 
-// SIFT-Rank. Each lane owns one (dx, dy) column of the (2R+1)^3 window and
-// walks dz, accumulating |g| per (z half, orientation octant); the centre
-// plane dz = 0 adds half to each z half. The 64 bins are then summed over
-// columns with the column's x/y half weights (1, or 1/2 on the centre
-// planes), and ranked.
-template <bool INL>
-__global__ void __launch_bounds__(kDescThreads) siftrank_kernel(const DescLaunch a)
+// Class of an offset along x or y: 0 for d < 0, 1 for d == 0, 2 for d > 0,
+// and the weight a class gives spatial half b (0: d < 0 side, 1: d > 0
+// side): the centre plane splits half/half.
+__device__ __forceinline__ double half_weight(int cls, int b)
 {
-    __shared__ double part[kDescThreads][17];
+    return cls == 1 ? 0.5 : ((cls == 2) == (b == 1) ? 1.0 : 0.0);
+}
+
+// First keypoint of volume v that block b handles when the keypoints of all
+// volumes are dealt round-robin to the blocks in one flat sequence (base =
+// keypoints of the volumes before v).
+__device__ __forceinline__ int first_of_block(int b, long long base, int grid)
+{
+    const long long r = ((long long)b - base) % grid;
+    return (int)(r < 0 ? r + grid : r);
+}
+
+// One workgroup per keypoint, both descriptor families.
+//
+// SIFT-Rank. Each of the first (2R+1)^2 threads owns one (dx, dy) column of
+// the (2R+1)^3 window and walks dz, accumulating |g| per (z half,
+// orientation octant); the centre plane dz = 0 adds half to each z half.
+// The column sums are then added up within each of the 9 (sign dx, sign dy)
+// classes (144 threads, fixed order), and each of the 64 bins combines the 9
+// class sums with their x/y half weights, and is ranked.
+//
+// BRIEF / RRIEF. B_s is G_s already blurred by the sigma_b pre-blur (a
+// whole-level separable pass with the same clamp-to-edge rule, so B_s at a
+// voxel equals the pre-blur stencil evaluated there). Thread i owns pair i:
+// d_i = B_s(p1) - B_s(p2) is the exact double difference of the two samples,
+// its bit comes from a ballot and its rank from a comparison against all n
+// differences in LDS.
+template <bool INL>
+__global__ void __launch_bounds__(kDescThreads) describe_kernel(const DescLaunch a)
+{
+    constexpr int kCols = (2 * kMaxSiftR + 1) * (2 * kMaxSiftR + 1);
+    static_assert(kCols <= kDescThreads, "one thread per window column");
+    __shared__ double part[kCols][17];
+    __shared__ double cls[9][16];
     __shared__ double hist[64];
-    const int tid = threadIdx.x;
+    __shared__ __align__(16) double dd[kMaxPairs];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = a.brief_n, nw = n / 64;
+    const bool do_sr = a.siftrank != nullptr;
+    const bool do_br = (a.brief != nullptr || a.rrief != nullptr) && n > 0;
+    long long base = 0;
     for (int v = 0; v < a.n_vol; ++v) {
     const int count = min(a.counts[v], a.cap);
     const DVol vol = a.vols[v];
-    for (int kk = blockIdx.x; kk < count; kk += gridDim.x) {
+    for (int kk = first_of_block(blockIdx.x, base, gridDim.x); kk < count; kk += gridDim.x) {
         const size_t k = (size_t)v * a.cap + kk;
         const sift3d_keypoint kp = a.kp[k];
         if (kp.octave < 0 || kp.octave >= vol.n_units || kp.scale < 1 || kp.scale > a.S) {
-            if (tid < 64) a.siftrank[k * 64 + tid] = 0;  // not a keypoint of this plan
+            // not a keypoint of this plan
+            if (do_sr && tid < 64) a.siftrank[k * 64 + tid] = 0;
+            if (a.rrief != nullptr && tid < n) a.rrief[k * n + tid] = 0;
+            if (a.brief != nullptr && tid < nw) a.brief[k * nw + tid] = 0;
             continue;
         }
         const DUnit &oc = (INL ? a.inl[vol.unit0 + kp.octave] : a.units[vol.unit0 + kp.octave]);
-        const float *G = reinterpret_cast<const float *>(a.ws + oc.g0) + oc.lstride * kp.scale;
         const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
-        const int R = a.sift_R[kp.scale];
-        const int W = 2 * R + 1;
-        double acc[16];
+
+        // BRIEF samples first: their loads overlap the SIFT-Rank work
+        double d = 0.0;
+        if (do_br && tid < n) {
+            const float *B = reinterpret_cast<const float *>(a.ws + oc.b1) + oc.lstride * (kp.scale - 1);
+            const int32_t *o = a.pairs + ((size_t)(kp.scale - 1) * n + tid) * 6;
+            const int x1 = clampi(kp.x + o[0], 0, nx - 1), y1 = clampi(kp.y + o[1], 0, ny - 1);
+            const int z1 = clampi(kp.z + o[2], 0, nz - 1);
+            const int x2 = clampi(kp.x + o[3], 0, nx - 1), y2 = clampi(kp.y + o[4], 0, ny - 1);
+            const int z2 = clampi(kp.z + o[5], 0, nz - 1);
+            const float b1 = B[((size_t)z1 * ny + y1) * nx + x1];
+            const float b2 = B[((size_t)z2 * ny + y2) * nx + x2];
+            d = (double)b1 - (double)b2;
+            dd[tid] = d;
+        }
+
+        if (do_sr) {
+            const float *G = reinterpret_cast<const float *>(a.ws + oc.g0) + oc.lstride * kp.scale;
+            const int R = a.sift_R[kp.scale];
+            const int W = 2 * R + 1;
+            if (tid < W * W) {
+                double acc[16];
 #pragma unroll
-        for (int b = 0; b < 16; ++b) acc[b] = 0.0;
-        if (tid < W * W) {
-            const int dx = tid % W - R, dy = tid / W - R;
-            switch (R) {
-            case 1: sift_column<1>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-            case 2: sift_column<2>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-            case 3: sift_column<3>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-            case 4: sift_column<4>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-            case 5: sift_column<5>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-            case 6: sift_column<6>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-            default: sift_column<7>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+                for (int b = 0; b < 16; ++b) acc[b] = 0.0;
+                const int dy = tid / W - R, dx = tid - (tid / W) * W - R;
+                switch (R) {
+                case 1: sift_column<1>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+                case 2: sift_column<2>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+                case 3: sift_column<3>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+                case 4: sift_column<4>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+                case 5: sift_column<5>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+                case 6: sift_column<6>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+                default: sift_column<7>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
+                }
+#pragma unroll
+                for (int b = 0; b < 16; ++b) part[tid][b] = acc[b];
+            }
+            __syncthreads();
+            if (tid < 144) {
+                // class q = (cy, cx), value j: columns with dx, dy in the class ranges
+                const int q = tid >> 4, j = tid & 15;
+                const int cy = q / 3, cx = q - cy * 3;
+                const int y0 = cy == 0 ? 0 : (cy == 1 ? R : R + 1), y1 = cy == 0 ? R : (cy == 1 ? R + 1 : W);
+                const int x0 = cx == 0 ? 0 : (cx == 1 ? R : R + 1), x1 = cx == 0 ? R : (cx == 1 ? R + 1 : W);
+                double sum = 0.0;
+                for (int yy = y0; yy < y1; ++yy)
+                    for (int xx = x0; xx < x1; ++xx) sum += part[yy * W + xx][j];
+                cls[q][j] = sum;
+            }
+            __syncthreads();
+            if (tid < 64) {
+                const int bs = tid >> 3, bo = tid & 7;
+                const int bx = bs & 1, by = (bs >> 1) & 1, bz = bs >> 2;
+                double h = 0.0;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    const int cy = q / 3, cx = q - cy * 3;
+                    h += (half_weight(cx, bx) * half_weight(cy, by)) * cls[q][8 * bz + bo];
+                }
+                hist[tid] = h;
             }
         }
-#pragma unroll
-        for (int b = 0; b < 16; ++b) part[tid][b] = acc[b];
         __syncthreads();
-        if (tid < 64) {
-            const int bs = tid >> 3, bo = tid & 7;
-            const int bx = bs & 1, by = (bs >> 1) & 1, bz = bs >> 2;
-            double h = 0.0;
-            for (int c = 0; c < W * W; ++c) {
-                const int dx = c % W - R, dy = c / W - R;
-                const double wx = dx == 0 ? 0.5 : ((dx > 0) == (bx == 1) ? 1.0 : 0.0);
-                const double wy = dy == 0 ? 0.5 : ((dy > 0) == (by == 1) ? 1.0 : 0.0);
-                h += (wx * wy) * part[c][8 * bz + bo];
-            }
-            hist[tid] = h;
-        }
-        __syncthreads();
-        if (tid < 64) {
+        if (do_sr && tid < 64) {
             const double h = hist[tid];
             int r = 0;
 #pragma unroll 8
@@ -125,78 +194,24 @@ __global__ void __launch_bounds__(kDescThreads) siftrank_kernel(const DescLaunch
             }
             a.siftrank[k * 64 + tid] = (uint8_t)r;
         }
-        __syncthreads();
-    }
-    }
-}
-
-// BRIEF / RRIEF. B_s is G_s already blurred by the sigma_b pre-blur (a
-// whole-level separable pass with the same clamp-to-edge rule, so B_s at a
-// voxel equals the pre-blur stencil evaluated there). One wavefront per
-// keypoint: lane l owns pairs l, l+64, ...; d_i = B_s(p1) - B_s(p2) is the
-// exact double difference of the two samples; bit words come from ballots
-// and each rank from a comparison against all n differences in LDS.
-template <bool INL>
-__global__ void __launch_bounds__(kDescThreads) brief_kernel(const DescLaunch a)
-{
-    constexpr int WAVES = kDescThreads / 64;
-    __shared__ double dd[WAVES][kMaxPairs];
-    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-    const int n = a.brief_n, nw = n / 64;
-    for (int v = 0; v < a.n_vol; ++v) {
-    const int count = min(a.counts[v], a.cap);
-    const DVol vol = a.vols[v];
-    for (int k0 = blockIdx.x * WAVES; k0 < count; k0 += gridDim.x * WAVES) {
-        const int kk = k0 + wave;
-        const bool live = kk < count;
-        const size_t k = (size_t)v * a.cap + kk;
-        sift3d_keypoint kp{};
-        if (live) kp = a.kp[k];
-        const bool valid = live && kp.octave >= 0 && kp.octave < vol.n_units && kp.scale >= 1 && kp.scale <= a.S;
-        double d[kMaxPairs / 64] = {0.0, 0.0, 0.0, 0.0};
-        if (valid) {
-            const DUnit &oc = (INL ? a.inl[vol.unit0 + kp.octave] : a.units[vol.unit0 + kp.octave]);
-            const float *B = reinterpret_cast<const float *>(a.ws + oc.b1) + oc.lstride * (kp.scale - 1);
-            const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
-            const int32_t *off = a.pairs + (size_t)(kp.scale - 1) * n * 6;
-            for (int q = 0; q < nw; ++q) {
-                const int32_t *o = off + (size_t)(lane + 64 * q) * 6;
-                const int x1 = clampi(kp.x + o[0], 0, nx - 1), y1 = clampi(kp.y + o[1], 0, ny - 1);
-                const int z1 = clampi(kp.z + o[2], 0, nz - 1);
-                const int x2 = clampi(kp.x + o[3], 0, nx - 1), y2 = clampi(kp.y + o[4], 0, ny - 1);
-                const int z2 = clampi(kp.z + o[5], 0, nz - 1);
-                const float b1 = B[((size_t)z1 * ny + y1) * nx + x1];
-                const float b2 = B[((size_t)z2 * ny + y2) * nx + x2];
-                d[q] = (double)b1 - (double)b2;
-                dd[wave][lane + 64 * q] = d[q];
-            }
-        }
-        __syncthreads();
-        if (live) {
-            int r[kMaxPairs / 64] = {0, 0, 0, 0};
-            if (valid && a.rrief != nullptr) {
+        if (do_br && tid < n) {
+            if (a.rrief != nullptr) {
                 // rank of d_i among the n: #{j : d_j < d_i or (d_j == d_i and j < i)}
-                for (int j0 = 0; j0 < n; j0 += 8) {
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int jj = j0 + u;
-                        const double o = dd[wave][jj];
-#pragma unroll
-                        for (int q = 0; q < kMaxPairs / 64; ++q)  // branch-free; q >= nw is unused
-                            r[q] += (int)(o < d[q]) | ((int)(o == d[q]) & (int)(jj < lane + 64 * q));
-                    }
+                int r = 0;
+                const double2 *d2 = reinterpret_cast<const double2 *>(dd);
+                for (int j = 0; j < n / 2; ++j) {
+                    const double2 o = d2[j];
+                    r += (int)(o.x < d) | ((int)(o.x == d) & (int)(2 * j < tid));
+                    r += (int)(o.y < d) | ((int)(o.y == d) & (int)(2 * j + 1 < tid));
                 }
+                a.rrief[k * n + tid] = (uint8_t)r;
             }
-#pragma unroll
-            for (int q = 0; q < kMaxPairs / 64; ++q) {
-                if (q >= nw) break;
-                const unsigned long long m = __ballot(valid && d[q] > 0.0);
-                if (a.brief != nullptr && lane == 0) a.brief[k * nw + q] = m;
-                if (a.rrief != nullptr) a.rrief[k * n + lane + 64 * q] = (uint8_t)r[q];
-            }
+            const unsigned long long m = __ballot(d > 0.0);
+            if (a.brief != nullptr && lane == 0) a.brief[k * nw + wave] = m;
         }
         __syncthreads();
     }
+    base += count;
     }
 }
 
@@ -205,24 +220,13 @@ __global__ void __launch_bounds__(kDescThreads) brief_kernel(const DescLaunch a)
 hipError_t launch_describe(const DescLaunch &a, int grid, hipStream_t st)
 {
     if (grid <= 0) return hipSuccess;
-    if (a.siftrank != nullptr) {
-        if (a.n_units <= kInlineUnits)
-            hipLaunchKernelGGL(siftrank_kernel<true>, dim3(grid), dim3(kDescThreads), 0, st, a);
-        else
-            hipLaunchKernelGGL(siftrank_kernel<false>, dim3(grid), dim3(kDescThreads), 0, st, a);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if ((a.brief != nullptr || a.rrief != nullptr) && a.brief_n > 0) {
-        const int g = (grid + kDescThreads / 64 - 1) / (kDescThreads / 64);
-        if (a.n_units <= kInlineUnits)
-            hipLaunchKernelGGL(brief_kernel<true>, dim3(g), dim3(kDescThreads), 0, st, a);
-        else
-            hipLaunchKernelGGL(brief_kernel<false>, dim3(g), dim3(kDescThreads), 0, st, a);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    if (a.siftrank == nullptr && (a.brief == nullptr && a.rrief == nullptr)) return hipSuccess;
+    if (a.brief_n < 0 || a.brief_n > kDescThreads || a.brief_n % 64 != 0) return hipErrorInvalidValue;
+    if (a.n_units <= kInlineUnits)
+        hipLaunchKernelGGL(describe_kernel<true>, dim3(grid), dim3(kDescThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(describe_kernel<false>, dim3(grid), dim3(kDescThreads), 0, st, a);
+    return hipGetLastError();
 }
 
 }  // namespace s3d

@@ -66,7 +66,8 @@ struct DXYJob {
     int tiles_x, tiles_y;
     int block0;           // first block of the job within its launch
     int r, taps;          // tap radius, tap-set index
-    int pad_[3];
+    int planes;           // consecutive planes per block
+    int pad_[2];
 };
 
 // One job of a z launch: the z blur of one level plus its DoG and sub-sample.
@@ -279,7 +280,7 @@ namespace s3d {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_blur(const BlurArgs &a, int r, bool dog, hipStream_t st);
 hipError_t launch_blur_xy(const XYLaunch &a, int max_r, hipStream_t st);
-hipError_t launch_blur_z(const ZLaunch &a, hipStream_t st);
+hipError_t launch_blur_z(const ZLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_detect(const DetLaunch &a, hipStream_t st);
 hipError_t launch_describe(const DescLaunch &a, int grid, hipStream_t st);
 
