@@ -85,7 +85,11 @@ def octave0_grids(shape_xyz):
     """Grid sizes (threads) of a solo octave-0 level pass: fused, xy, z."""
     nx, ny, nz = shape_xyz
     cdiv = lambda a, b: (a + b - 1) // b  # noqa: E731
-    return {"xy": cdiv(nx, 64) * cdiv(ny, 16) * nz * 256, "z": cdiv(nx, 32) * cdiv(ny, 8) * cdiv(nz, 16) * 256}
+    tiles = cdiv(nx, 64) * cdiv(ny, 16)
+    planes = 4   # planes per xy block, as the plan picks them
+    while planes > 1 and tiles * cdiv(nz, planes) < 1024:
+        planes //= 2
+    return {"xy": tiles * cdiv(nz, planes) * 256, "z": cdiv(nx, 32) * cdiv(ny, 8) * cdiv(nz, 16) * 256}
 
 
 def summarize_pmc(fetch_dir, write_dir, workloads, out_path):
@@ -103,7 +107,8 @@ def summarize_pmc(fetch_dir, write_dir, workloads, out_path):
         for f in fs:
             for r in csv.DictReader(open(f)):
                 if r.get("Counter_Name") == counter:
-                    out.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"]),
+                    name = r["Kernel_Name"].replace("void ", "").replace("s3d::(anonymous namespace)::", "")
+                    out.append((name, int(r["Grid_Size"]), float(r["Counter_Value"]),
                                 int(r.get("Dispatch_Id", 0))))
         return out
 
