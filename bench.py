@@ -462,14 +462,19 @@ def main():
 
     # roofline of the blur/DoG pass: octave-0 incremental passes (G_1..G_{S+2})
     sel = [i for i, p in enumerate(passes) if p[0] == 0 and p[1] > 0]
-    fused = bool(passes[sel[0]][5])
+    fused_lv = [f"G_{passes[i][1]}" for i in sel if passes[i][5]]
+    split_lv = [f"G_{passes[i][1]}" for i in sel if not passes[i][5]]
+    kparts = []
+    if fused_lv:
+        kparts.append("blur_level_kernel (" + ", ".join(fused_lv) + ")")
+    if split_lv:
+        kparts.append("blur_xy_kernel + blur_z_kernel (" + ", ".join(split_lv) + ")")
     bytes_per_launch = sum(passes[i][4] for i in sel) / len(sel)
     dur_ms = sum(pass_ms[i] for i in sel) / len(sel)
     achieved = bytes_per_launch / (dur_ms * 1e-3) / 1e9
     traffic = read_traffic(args.workload)
     roofline = {
-        "kernel": ("blur_level_kernel" if fused else "blur_xy_kernel + blur_z_kernel")
-                  + " (octave-0 pyramid level passes G_1..G_5: blur + DoG + sub-sample)",
+        "kernel": " + ".join(kparts) + ": octave-0 pyramid level passes (blur + DoG + sub-sample)",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,

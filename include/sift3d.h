@@ -58,8 +58,12 @@ typedef struct sift3d_params {
     double brief_blur;      /* [0.95] patch pre-blur sigma_b (0 = none), <= 2.0  */
     double siftrank_factor; /* [2.0] SIFT-Rank half-width R = ceil(f * sigma_s), R <= 7 */
     int pyramid_mode;       /* [0] 0 = by size (fused streaming pass for octaves of
-                               >= 24M voxels, xy + z launches below), 1 = always
-                               fused, 2 = always xy + z; results agree to rounding */
+                               >= 24M voxels, and for levels of radius <= 8 in
+                               octaves of >= 2M voxels; xy + z launches for the
+                               rest), 1 = always
+                               fused, 2 = always xy + z; results agree to rounding.
+                               Levels whose tap radius exceeds 10 always run as
+                               xy + z launches */
 } sift3d_params;
 
 /*

@@ -65,13 +65,14 @@ int check_params(const sift3d_params *p)
     return SIFT3D_OK;
 }
 
-// Output planes per slab: few enough slabs that the z halo (2R planes per
-// slab) stays cheap, enough blocks to occupy the 256 compute units.
-int choose_slab(int nz, int tiles, int r)
+// Output planes per slab: enough blocks to fill every resident slot of the
+// device once (CUs x the fused pass's workgroups per CU at this radius, set
+// by its registers and LDS), no more, so that the z halo (2R planes per
+// slab) stays cheap.
+int choose_slab(int nz, int tiles, int r, int slots)
 {
-    const int target_blocks = 1024;
     const int min_l = std::max(8, 2 * r);
-    int slabs = std::max(1, (target_blocks + tiles - 1) / tiles);
+    int slabs = std::max(1, (slots + tiles - 1) / tiles);
     int L = (nz + slabs - 1) / slabs;
     L = std::max(L, min_l);
     L = (L + 1) & ~1;
@@ -459,7 +460,10 @@ int make_plan(sift3d_ctx *ctx, int n, const int *dims, int kp_capacity, sift3d_p
                 L.dst_idx = i;
                 L.dog_idx = i - 1;
                 L.sub_octave = (i == S && o + 1 < no) ? o + 1 : -1;
-                L.fused = p.pyramid_mode == 1 || (p.pyramid_mode == 0 && (long long)g.n >= kFusedMinVoxels);
+                // the fused pass is compiled for radii up to kMaxFusedR; larger ones run split
+                const bool by_size = (long long)g.n >= kFusedMinVoxels ||
+                                     ((long long)g.n >= kFusedMidVoxels && L.r <= kFusedMidMaxR);
+                L.fused = L.r <= kMaxFusedR && (p.pyramid_mode == 1 || (p.pyramid_mode == 0 && by_size));
                 if (L.fused) {
                     BlurArgs &a = L.a;
                     a.nx = g.nx;
@@ -472,7 +476,8 @@ int make_plan(sift3d_ctx *ctx, int n, const int *dims, int kp_capacity, sift3d_p
                     }
                     a.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
                     a.tiles_y = (g.ny + kBlurTY - 1) / kBlurTY;
-                    a.L = choose_slab(g.nz, a.tiles_x * a.tiles_y, L.r);
+                    const int per_cu = std::max(1, fused_blocks_per_cu(L.r, L.dog));
+                    a.L = choose_slab(g.nz, a.tiles_x * a.tiles_y, L.r, ctx->n_cu * per_cu);
                     a.slabs = (g.nz + a.L - 1) / a.L;
                     a.n_blocks = a.tiles_x * a.tiles_y * a.slabs;
                     for (int t = 0; t < kMaxTaps; ++t) a.w[t] = pl->tapsets[i][t];
@@ -579,6 +584,7 @@ int sift3d_create(const sift3d_params *p, const double *pair_draws, int n_draws,
     c->p = *p;
     c->d_offsets = nullptr;
     hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e);

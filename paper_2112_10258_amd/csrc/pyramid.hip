@@ -11,9 +11,12 @@
 // halo tile is staged in LDS (coalesced row loads, clamp-to-edge), blurred
 // along x into a second LDS tile, then along y into registers. The z pass
 // keeps the last 2R+1 y-blurred values of each output column in a
-// per-thread register ring; the ring slot is a compile-time constant in
-// each of the 2R+1 unrolled phases, so the ring never leaves registers.
+// per-thread register ring. The plane loop is unrolled by 2R+1, so each
+// step writes and reads ring slots that are compile-time constants: the
+// ring stays in fixed registers with no copies between steps.
 #include "sift3d_internal.h"
+
+#include <type_traits>
 
 namespace s3d {
 namespace {
@@ -47,36 +50,14 @@ __device__ __forceinline__ float sym_stencil(const float (&w)[2 * R + 1], F at)
     }
 }
 
-template <int R, int NY, bool DOG, int P>
-__device__ __forceinline__ void ring_step(float (&ring)[NY][2 * R + 1], float (&cen)[NY][2 * R + 1],
-                                          const float (&yv)[NY], const float (&cv)[NY],
-                                          const float (&w)[2 * R + 1], float (&zo)[NY], float (&co)[NY])
+// f(std::integral_constant<int, P>) for P = I .. N-1: every P is a
+// compile-time constant inside f, whatever the unroller's size limits.
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
 {
-    constexpr int M = 2 * R + 1;
-#pragma unroll
-    for (int j = 0; j < NY; ++j) {
-        ring[j][P] = yv[j];
-        if constexpr (DOG) cen[j][P] = cv[j];
-    }
-    // slot (P + 1 + t) % M holds input plane (current - 2R + t)
-#pragma unroll
-    for (int j = 0; j < NY; ++j) {
-        zo[j] = sym_stencil<R>(w, [&](int t) { return ring[j][(P + 1 + t) % M]; });
-        if constexpr (DOG) co[j] = cen[j][(P + 1 + R) % M];  // input plane (current - R)
-    }
-}
-
-template <int R, int NY, bool DOG, int P = 0>
-__device__ __forceinline__ void ring_dispatch(int phase, float (&ring)[NY][2 * R + 1],
-                                              float (&cen)[NY][2 * R + 1], const float (&yv)[NY],
-                                              const float (&cv)[NY], const float (&w)[2 * R + 1],
-                                              float (&zo)[NY], float (&co)[NY])
-{
-    if constexpr (P < 2 * R + 1) {
-        if (phase == P)
-            ring_step<R, NY, DOG, P>(ring, cen, yv, cv, w, zo, co);
-        else
-            ring_dispatch<R, NY, DOG, P + 1>(phase, ring, cen, yv, cv, w, zo, co);
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
     }
 }
 
@@ -93,8 +74,13 @@ __global__ void __launch_bounds__(kBlurThreads) blur_level_kernel(const BlurArgs
     constexpr int XQ = TX / 4;                      // x-pass items per row (4 outputs each)
     constexpr int XIN = 4 + ((2 * R + 3) & ~3);     // x-pass inputs per item, multiple of 4
     static_assert(NY == 2, "sub-sampling pairs rows inside a thread");
-    __shared__ __align__(16) float A[AH * AW];
+    // staging tile plus one dummy slot per unused staging lane (branch-free writes)
+    __shared__ __align__(16) float A[AH * AW + KL * NT - AE];
     __shared__ __align__(16) float B[AH * TX];
+    // centre values (G_{i-1} at the thread's output voxels) of the last R+1
+    // input planes: private to each thread, kept in LDS because the slot
+    // index is not a compile-time constant
+    __shared__ float C[DOG ? (R + 1) * NY * NT : 1];
 
     const int tid = threadIdx.x;
     const int logical = xcd_remap(blockIdx.x, a.n_blocks);
@@ -109,17 +95,18 @@ __global__ void __launch_bounds__(kBlurThreads) blur_level_kernel(const BlurArgs
     const size_t nxy = (size_t)nx * ny;
 
     // Per-thread staging slots: the same in-plane offsets for every plane.
-    int goff[KL], loff[KL];
+    unsigned goff[KL];
+    int loff[KL];
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
         const int idx = tid + k * NT;
         if (idx < AE) {
             const int r = idx / AWL, c = idx - r * AWL;
-            goff[k] = clampi(y0 - R + r, 0, ny - 1) * nx + clampi(x0 - R + c, 0, nx - 1);
+            goff[k] = (unsigned)(clampi(y0 - R + r, 0, ny - 1) * nx + clampi(x0 - R + c, 0, nx - 1));
             loff[k] = r * AW + c;
         } else {
             goff[k] = 0;
-            loff[k] = -1;
+            loff[k] = AH * AW + (idx - AE);
         }
     }
     float pre[KL];
@@ -135,86 +122,103 @@ __global__ void __launch_bounds__(kBlurThreads) blur_level_kernel(const BlurArgs
 
     const int tx = tid % TX;
     const int tyb = (tid / TX) * NY;
-    const int gx = x0 + tx;
-    float ring[NY][M], cen[NY][M];
+    const int gx = x0 + tx, gy0 = y0 + tyb;
+    const bool ok0 = gx < nx && gy0 < ny, ok1 = gx < nx && gy0 + 1 < ny;
+    const unsigned o0 = (unsigned)(min(gy0, ny - 1) * nx + min(gx, nx - 1));
+    const unsigned o1 = (unsigned)(min(gy0 + 1, ny - 1) * nx + min(gx, nx - 1));
+    float ring[NY][M];
 #pragma unroll
     for (int j = 0; j < NY; ++j)
 #pragma unroll
-        for (int t = 0; t < M; ++t) ring[j][t] = cen[j][t] = 0.f;
+        for (int t = 0; t < M; ++t) ring[j][t] = 0.f;
     float subacc = 0.f;
+    int cslot = 0;                                  // C slot of the current step (it mod R+1)
 
+    // Input plane z0 - R + it is staged at step it; output plane z0 + it - 2R
+    // completes at step it. The plane loop is unrolled by the ring length so
+    // that every ring slot is a fixed register.
     const int nplanes = (z1 - z0) + 2 * R;
-    int phase = 0;
     load_plane(z0 - R);
-    for (int it = 0; it < nplanes; ++it) {
+    for (int base = 0; base < nplanes; base += M) {
+        static_for<0, M>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            const int it = base + p;
+            if (it >= nplanes) return;
 #pragma unroll
-        for (int k = 0; k < KL; ++k)
-            if (loff[k] >= 0) A[loff[k]] = pre[k];
-        __syncthreads();
-        if (it + 1 < nplanes) load_plane(z0 - R + it + 1);
-
-        float cv[NY];
-#pragma unroll
-        for (int j = 0; j < NY; ++j) cv[j] = DOG ? A[(R + tyb + j) * AW + R + tx] : 0.f;
-
-        // x pass: 4 consecutive outputs per item from one LDS strip
-        for (int item = tid; item < AH * XQ; item += NT) {
-            const int r = item / XQ, xb = (item - r * XQ) * 4;
-            float in[XIN];
-            const float4 *s4 = reinterpret_cast<const float4 *>(&A[r * AW + xb]);
-#pragma unroll
-            for (int q = 0; q < XIN / 4; ++q) {
-                const float4 v = s4[q];
-                in[4 * q + 0] = v.x;
-                in[4 * q + 1] = v.y;
-                in[4 * q + 2] = v.z;
-                in[4 * q + 3] = v.w;
-            }
-            float o[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) o[q] = sym_stencil<R>(w, [&](int t) { return in[q + t]; });
-            *reinterpret_cast<float4 *>(&B[r * TX + xb]) = make_float4(o[0], o[1], o[2], o[3]);
-        }
-        __syncthreads();
-
-        // y pass: NY consecutive outputs of column tx
-        float yv[NY];
-        {
-            float col[NY + 2 * R];
-#pragma unroll
-            for (int q = 0; q < NY + 2 * R; ++q) col[q] = B[(tyb + q) * TX + tx];
-#pragma unroll
-            for (int j = 0; j < NY; ++j) yv[j] = sym_stencil<R>(w, [&](int t) { return col[j + t]; });
-        }
-
-        // z pass from the register ring
-        float zo[NY], co[NY];
-        ring_dispatch<R, NY, DOG>(phase, ring, cen, yv, cv, w, zo, co);
-        phase = (phase + 1 == M) ? 0 : phase + 1;
-
-        if (it >= 2 * R) {
+            for (int k = 0; k < KL; ++k) A[loff[k]] = pre[k];
+            __syncthreads();
+            if (it + 1 < nplanes) load_plane(z0 - R + it + 1);
             const int oz = z0 + it - 2 * R;
+            float cv0 = 0.f, cv1 = 0.f;
+            if constexpr (DOG) {
+                // D_{i-1} needs G_{i-1} at the output voxel: keep this plane's centre
+                // values, and take those of the plane staged R steps ago (slot cslot+1)
+                const int rslot = cslot == R ? 0 : cslot + 1;
+                C[(cslot * NY + 0) * NT + tid] = A[(R + tyb) * AW + R + tx];
+                C[(cslot * NY + 1) * NT + tid] = A[(R + tyb + 1) * AW + R + tx];
+                if (it >= 2 * R) {
+                    cv0 = C[(rslot * NY + 0) * NT + tid];
+                    cv1 = C[(rslot * NY + 1) * NT + tid];
+                }
+                cslot = rslot;
+            }
+
+            // x pass: 4 consecutive outputs per item from one LDS strip
+            for (int item = tid; item < AH * XQ; item += NT) {
+                const int r = item / XQ, xb = (item - r * XQ) * 4;
+                float in[XIN];
+                const float4 *s4 = reinterpret_cast<const float4 *>(&A[r * AW + xb]);
 #pragma unroll
-            for (int j = 0; j < NY; ++j) {
-                const int gy = y0 + tyb + j;
-                if (gx < nx && gy < ny) {
-                    const size_t i = (size_t)oz * nxy + (size_t)gy * nx + gx;
-                    a.dst[i] = zo[j];
-                    if constexpr (DOG) a.dog[i] = co[j] - zo[j];
+                for (int q = 0; q < XIN / 4; ++q) {
+                    const float4 v = s4[q];
+                    in[4 * q + 0] = v.x;
+                    in[4 * q + 1] = v.y;
+                    in[4 * q + 2] = v.z;
+                    in[4 * q + 3] = v.w;
+                }
+                float o[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) o[q] = sym_stencil<R>(w, [&](int t) { return in[q + t]; });
+                *reinterpret_cast<float4 *>(&B[r * TX + xb]) = make_float4(o[0], o[1], o[2], o[3]);
+            }
+            __syncthreads();
+
+            // y pass: NY consecutive outputs of column tx, into ring slot p
+            {
+                float col[NY + 2 * R];
+#pragma unroll
+                for (int q = 0; q < NY + 2 * R; ++q) col[q] = B[(tyb + q) * TX + tx];
+#pragma unroll
+                for (int j = 0; j < NY; ++j) ring[j][p] = sym_stencil<R>(w, [&](int t) { return col[j + t]; });
+            }
+
+            if (it >= 2 * R) {
+                // z pass: slot (p + 1 + t) % M holds input plane (it - 2R + t)
+                float zo[NY];
+#pragma unroll
+                for (int j = 0; j < NY; ++j)
+                    zo[j] = sym_stencil<R>(w, [&](int t) { return ring[j][(p + 1 + t) % M]; });
+                float *d = a.dst + (size_t)oz * nxy;
+                if (ok0) d[o0] = zo[0];
+                if (ok1) d[o1] = zo[1];
+                if constexpr (DOG) {
+                    float *e = a.dog + (size_t)oz * nxy;
+                    if (ok0) e[o0] = cv0 - zo[0];
+                    if (ok1) e[o1] = cv1 - zo[1];
+                }
+                if (a.sub != nullptr) {
+                    const float s2 = zo[0] + zo[1];
+                    const float s4 = s2 + __shfl_xor(s2, 1);
+                    if ((oz & 1) == 0) {
+                        subacc = s4;
+                    } else {
+                        const int X = gx >> 1, Y = gy0 >> 1, Z = oz >> 1;
+                        if ((tx & 1) == 0 && X < a.mx && Y < a.my && Z < a.mz)
+                            a.sub[((size_t)Z * a.my + Y) * a.mx + X] = (subacc + s4) * 0.125f;
+                    }
                 }
             }
-            if (a.sub != nullptr) {
-                const float s2 = zo[0] + zo[1];
-                const float s4 = s2 + __shfl_xor(s2, 1);
-                if ((oz & 1) == 0) {
-                    subacc = s4;
-                } else {
-                    const int X = gx >> 1, Y = (y0 + tyb) >> 1, Z = oz >> 1;
-                    if ((tx & 1) == 0 && X < a.mx && Y < a.my && Z < a.mz)
-                        a.sub[((size_t)Z * a.my + Y) * a.mx + X] = (subacc + s4) * 0.125f;
-                }
-            }
-        }
+        });
     }
 }
 
@@ -232,6 +236,7 @@ hipError_t launch_r(const BlurArgs &a, bool dog, hipStream_t st)
 
 hipError_t launch_blur(const BlurArgs &a, int r, bool dog, hipStream_t st)
 {
+    static_assert(kMaxFusedR == 10, "one case per fused radius");
     switch (r) {
     case 0: return launch_r<0>(a, dog, st);
     case 1: return launch_r<1>(a, dog, st);
@@ -244,14 +249,28 @@ hipError_t launch_blur(const BlurArgs &a, int r, bool dog, hipStream_t st)
     case 8: return launch_r<8>(a, dog, st);
     case 9: return launch_r<9>(a, dog, st);
     case 10: return launch_r<10>(a, dog, st);
-    case 11: return launch_r<11>(a, dog, st);
-    case 12: return launch_r<12>(a, dog, st);
-    case 13: return launch_r<13>(a, dog, st);
-    case 14: return launch_r<14>(a, dog, st);
-    case 15: return launch_r<15>(a, dog, st);
-    case 16: return launch_r<16>(a, dog, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+// Workgroups of the fused pass at radius r that one CU holds at once
+// (registers and LDS), 0 on error.
+int fused_blocks_per_cu(int r, bool dog)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define S3D_OCC(R)                                                                                               \
+    case R:                                                                                                      \
+        e = dog ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, true>, kBlurThreads, 0) \
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, false>, kBlurThreads, 0); \
+        break;
+    switch (r) {
+        S3D_OCC(0) S3D_OCC(1) S3D_OCC(2) S3D_OCC(3) S3D_OCC(4) S3D_OCC(5) S3D_OCC(6) S3D_OCC(7) S3D_OCC(8)
+        S3D_OCC(9) S3D_OCC(10)
+    default: break;
+    }
+#undef S3D_OCC
+    return e == hipSuccess ? n : 0;
 }
 
 }  // namespace s3d

@@ -42,8 +42,14 @@ constexpr int kXYTY = 16;                   // xy tile height
 constexpr int kXYThreads = 256;
 constexpr int kZPlanes = 16;                // z outputs per thread
 constexpr int kZThreads = 256;              // 32 (x) x 8 (y) columns
-// Octaves with at least this many voxels use the fused streaming pass.
+// Octaves with at least this many voxels use the fused streaming pass; from
+// kFusedMidVoxels on, so do the levels with radius <= kFusedMidMaxR (there
+// the fused pass beats the xy + z pair even while the octave sits in the
+// last-level cache).
 constexpr long long kFusedMinVoxels = 24LL << 20;
+constexpr long long kFusedMidVoxels = 2LL << 20;
+constexpr int kFusedMidMaxR = 8;
+constexpr int kMaxFusedR = 10;              // largest tap radius of the fused pass
 
 // Detection geometry.
 constexpr int kDetThreads = 256;            // 4 waves
@@ -238,6 +244,7 @@ struct VolPlan {
 struct sift3d_ctx {
     sift3d_params p;
     int device;
+    int n_cu;                           // compute units of the device
     std::vector<double> draws;          // [brief_n][2][3]
     std::vector<int32_t> offsets;       // [S][brief_n][2][3]
     int32_t *d_offsets;                 // device copy
@@ -279,6 +286,7 @@ struct sift3d_plan {
 namespace s3d {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_blur(const BlurArgs &a, int r, bool dog, hipStream_t st);
+int fused_blocks_per_cu(int r, bool dog);
 hipError_t launch_blur_xy(const XYLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_blur_z(const ZLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_detect(const DetLaunch &a, hipStream_t st);
