@@ -65,14 +65,12 @@ int check_params(const sift3d_params *p)
     return SIFT3D_OK;
 }
 
-// Output planes per slab: enough blocks to fill every resident slot of the
-// device once (CUs x the fused pass's workgroups per CU at this radius, set
-// by its registers and LDS), no more, so that the z halo (2R planes per
-// slab) stays cheap.
-int choose_slab(int nz, int tiles, int r, int slots)
+// Output planes per slab when a fused launch splits each job's depth into
+// `slabs` slabs: at least 2R (and 8) planes so that the z halo (2R planes
+// per slab) stays cheap, even.
+int slab_planes(int nz, int slabs, int r)
 {
     const int min_l = std::max(8, 2 * r);
-    int slabs = std::max(1, (slots + tiles - 1) / tiles);
     int L = (nz + slabs - 1) / slabs;
     L = std::max(L, min_l);
     L = (L + 1) & ~1;
@@ -179,6 +177,54 @@ void task_jobs(const sift3d_plan *pl, const Task &k, DXYJob &xy, DZJob &z)
     z.gz = (g->nz + kZPlanes - 1) / kZPlanes;
 }
 
+// The fused job of a level-pass task, its depth split into `slabs` slabs
+// (block0 left for the caller).
+DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs)
+{
+    const int S = pl->S;
+    const BlurLaunch &L = pl->blur[k.pass];
+    const VolPlan &vp = pl->vols[L.vol];
+    const OctaveGeom &g = vp.oct[L.octave];
+    DFJob f{};
+    if (L.src_kind < 0) {
+        f.src = (long long)vp.in_off;
+        f.src_input = 1;
+    } else {
+        f.src = (long long)level_off(g, lev_G(L.src_idx));
+    }
+    f.dst = (long long)level_off(g, lev_G(L.dst_idx));
+    f.dog = L.dog ? (long long)level_off(g, lev_D(S, L.dog_idx)) : -1;
+    if (L.sub_octave >= 0) {
+        const OctaveGeom &m = vp.oct[L.sub_octave];
+        f.sub = (long long)level_off(m, lev_G(0));
+        f.mx = m.nx;
+        f.my = m.ny;
+        f.mz = m.nz;
+    } else {
+        f.sub = -1;
+    }
+    f.nx = g.nx;
+    f.ny = g.ny;
+    f.nz = g.nz;
+    f.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
+    f.tiles_y = (g.ny + kBlurTY - 1) / kBlurTY;
+    f.L = slab_planes(g.nz, slabs, L.r);
+    f.slabs = (g.nz + f.L - 1) / f.L;
+    f.taps = L.tapset;
+    return f;
+}
+
+// Slabs per job for a fused launch over jobs with `tiles` (x, y) tiles in
+// total: enough blocks to fill every resident slot of the device once (CUs x
+// the fused pass's workgroups per CU at this radius, from its registers and
+// LDS), no more.
+int fused_slabs(const sift3d_plan *pl, long long tiles, int r, bool dog)
+{
+    const int per_cu = std::max(1, fused_blocks_per_cu(r, dog));
+    const long long slots = (long long)pl->ctx->n_cu * per_cu;
+    return (int)std::max<long long>(1, (slots + tiles - 1) / tiles);
+}
+
 // List scheduler over all volumes: alternating xy and z launches, each
 // holding every split task whose inputs are ready; fused passes are
 // launches of their own. Fills the job tables (schedule entries first, then
@@ -190,6 +236,7 @@ void build_schedule(sift3d_plan *pl)
     pl->sched.clear();
     pl->xyjobs.clear();
     pl->zjobs.clear();
+    pl->fjobs.clear();
     for (size_t b = 0; b < pl->blur.size(); ++b)
         pl->tasks.push_back(Task{0, (int)b, pl->blur[b].vol, pl->blur[b].octave, 0});
     if (pl->brief_rb >= 0)
@@ -216,7 +263,7 @@ void build_schedule(sift3d_plan *pl)
     auto is_fused = [&](int t) { return pl->tasks[t].kind == 0 && pl->blur[pl->tasks[t].pass].fused; };
     auto emit = [&](int type, const std::vector<int> &ts) {
         if (ts.empty()) return;
-        Step st{type, ts, 0, (int)ts.size(), 0, 0};
+        Step st{type, ts, 0, (int)ts.size(), 0, 0, false};
         st.first = type == 1 ? (int)pl->xyjobs.size() : (int)pl->zjobs.size();
         int blocks = 0;
         for (int t : ts) {
@@ -239,16 +286,46 @@ void build_schedule(sift3d_plan *pl)
         st.n_blocks = blocks;
         pl->sched.push_back(st);
     };
+    // one fused launch per (radius, DoG) group of ready fused tasks
+    auto emit_fused = [&](const std::vector<int> &ts) {
+        std::vector<int> left = ts;
+        while (!left.empty()) {
+            const BlurLaunch &L0 = pl->blur[pl->tasks[left[0]].pass];
+            std::vector<int> grp, rest;
+            for (int t : left) {
+                const BlurLaunch &L = pl->blur[pl->tasks[t].pass];
+                (L.r == L0.r && L.dog == L0.dog ? grp : rest).push_back(t);
+            }
+            long long tiles = 0;
+            for (int t : grp) {
+                const BlurLaunch &L = pl->blur[pl->tasks[t].pass];
+                const OctaveGeom &g = pl->vols[L.vol].oct[L.octave];
+                tiles += (long long)((g.nx + kBlurTX - 1) / kBlurTX) * ((g.ny + kBlurTY - 1) / kBlurTY);
+            }
+            const int slabs = fused_slabs(pl, tiles, L0.r, L0.dog);
+            Step st{0, grp, (int)pl->fjobs.size(), (int)grp.size(), 0, L0.r, L0.dog};
+            for (int t : grp) {
+                DFJob f = fused_job(pl, pl->tasks[t], slabs);
+                f.block0 = st.n_blocks;
+                st.n_blocks += f.tiles_x * f.tiles_y * f.slabs;
+                pl->fjobs.push_back(f);
+            }
+            pl->sched.push_back(st);
+            left.swap(rest);
+        }
+    };
     int remaining = nt;
     while (remaining > 0) {
         bool progress = false;
+        std::vector<int> fs;
         for (int t = 0; t < nt; ++t)
-            if (!done[t] && is_fused(t) && ready(t)) {
-                pl->sched.push_back(Step{0, {t}, 0, 1, 0, 0});
-                done[t] = 1;
-                --remaining;
-                progress = true;
-            }
+            if (!done[t] && is_fused(t) && ready(t)) fs.push_back(t);
+        emit_fused(fs);
+        for (int t : fs) {
+            done[t] = 1;
+            --remaining;
+            progress = true;
+        }
         std::vector<int> xs;
         for (int t = 0; t < nt; ++t)
             if (!done[t] && !xy_done[t] && !is_fused(t) && ready(t)) xs.push_back(t);
@@ -268,8 +345,18 @@ void build_schedule(sift3d_plan *pl)
     // single-job entries
     pl->solo_xy.assign(nt, -1);
     pl->solo_z.assign(nt, -1);
+    pl->solo_f.assign(nt, -1);
     for (int t = 0; t < nt; ++t) {
-        if (is_fused(t)) continue;
+        if (is_fused(t)) {
+            const BlurLaunch &L = pl->blur[pl->tasks[t].pass];
+            const OctaveGeom &g = pl->vols[L.vol].oct[L.octave];
+            const long long tiles = (long long)((g.nx + kBlurTX - 1) / kBlurTX) * ((g.ny + kBlurTY - 1) / kBlurTY);
+            DFJob f = fused_job(pl, pl->tasks[t], fused_slabs(pl, tiles, L.r, L.dog));
+            f.block0 = 0;
+            pl->solo_f[t] = (int)pl->fjobs.size();
+            pl->fjobs.push_back(f);
+            continue;
+        }
         DXYJob xy;
         DZJob z;
         task_jobs(pl, pl->tasks[t], xy, z);
@@ -289,8 +376,9 @@ int upload_tables(sift3d_plan *pl)
     const size_t b_vols = al(pl->dvols.size() * sizeof(DVol));
     const size_t b_xy = al(std::max<size_t>(1, pl->xyjobs.size()) * sizeof(DXYJob));
     const size_t b_z = al(std::max<size_t>(1, pl->zjobs.size()) * sizeof(DZJob));
+    const size_t b_f = al(std::max<size_t>(1, pl->fjobs.size()) * sizeof(DFJob));
     const size_t b_taps = al(pl->tapsets.size() * kMaxTaps * sizeof(float));
-    const size_t total = b_units + b_vols + b_xy + b_z + b_taps;
+    const size_t total = b_units + b_vols + b_xy + b_z + b_f + b_taps;
     std::vector<char> host(total, 0);
     size_t off = 0;
     std::memcpy(host.data() + off, pl->units.data(), pl->units.size() * sizeof(DUnit));
@@ -301,6 +389,8 @@ int upload_tables(sift3d_plan *pl)
     off += b_xy;
     std::memcpy(host.data() + off, pl->zjobs.data(), pl->zjobs.size() * sizeof(DZJob));
     off += b_z;
+    std::memcpy(host.data() + off, pl->fjobs.data(), pl->fjobs.size() * sizeof(DFJob));
+    off += b_f;
     for (size_t i = 0; i < pl->tapsets.size(); ++i)
         std::memcpy(host.data() + off + i * kMaxTaps * sizeof(float), pl->tapsets[i].data(), kMaxTaps * sizeof(float));
     hipError_t e = hipMalloc(&pl->d_tables, total);
@@ -315,7 +405,8 @@ int upload_tables(sift3d_plan *pl)
     pl->d_vols = reinterpret_cast<DVol *>(d + b_units);
     pl->d_xy = reinterpret_cast<DXYJob *>(d + b_units + b_vols);
     pl->d_z = reinterpret_cast<DZJob *>(d + b_units + b_vols + b_xy);
-    pl->d_taps = reinterpret_cast<float *>(d + b_units + b_vols + b_xy + b_z);
+    pl->d_f = reinterpret_cast<DFJob *>(d + b_units + b_vols + b_xy + b_z);
+    pl->d_taps = reinterpret_cast<float *>(d + b_units + b_vols + b_xy + b_z + b_f);
     return SIFT3D_OK;
 }
 
@@ -464,24 +555,6 @@ int make_plan(sift3d_ctx *ctx, int n, const int *dims, int kp_capacity, sift3d_p
                 const bool by_size = (long long)g.n >= kFusedMinVoxels ||
                                      ((long long)g.n >= kFusedMidVoxels && L.r <= kFusedMidMaxR);
                 L.fused = L.r <= kMaxFusedR && (p.pyramid_mode == 1 || (p.pyramid_mode == 0 && by_size));
-                if (L.fused) {
-                    BlurArgs &a = L.a;
-                    a.nx = g.nx;
-                    a.ny = g.ny;
-                    a.nz = g.nz;
-                    if (L.sub_octave >= 0) {
-                        a.mx = vp.oct[o + 1].nx;
-                        a.my = vp.oct[o + 1].ny;
-                        a.mz = vp.oct[o + 1].nz;
-                    }
-                    a.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
-                    a.tiles_y = (g.ny + kBlurTY - 1) / kBlurTY;
-                    const int per_cu = std::max(1, fused_blocks_per_cu(L.r, L.dog));
-                    a.L = choose_slab(g.nz, a.tiles_x * a.tiles_y, L.r, ctx->n_cu * per_cu);
-                    a.slabs = (g.nz + a.L - 1) / a.L;
-                    a.n_blocks = a.tiles_x * a.tiles_y * a.slabs;
-                    for (int t = 0; t < kMaxTaps; ++t) a.w[t] = pl->tapsets[i][t];
-                }
                 pl->blur.push_back(L);
             }
         }
@@ -515,15 +588,16 @@ int run_step(const sift3d_plan *plan, const Step &stp, const float *d_in, void *
     hipError_t e = hipSuccess;
     char *ws = static_cast<char *>(d_ws);
     if (stp.type == 0) {
-        const BlurLaunch &L = plan->blur[plan->tasks[stp.tasks[0]].pass];
-        const VolPlan &vp = plan->vols[L.vol];
-        const OctaveGeom &g = vp.oct[L.octave];
-        BlurArgs a = L.a;
-        a.src = L.src_kind < 0 ? d_in + vp.in_off : ws_float(ws, level_off(g, lev_G(L.src_idx)));
-        a.dst = ws_float(ws, level_off(g, lev_G(L.dst_idx)));
-        a.dog = L.dog ? ws_float(ws, level_off(g, lev_D(plan->S, L.dog_idx))) : nullptr;
-        a.sub = L.sub_octave >= 0 ? ws_float(ws, level_off(vp.oct[L.sub_octave], lev_G(0))) : nullptr;
-        e = launch_blur(a, L.r, L.dog, st);
+        FusedLaunch a{};
+        a.jobs = plan->d_f + stp.first;
+        a.n_jobs = stp.count;
+        a.n_blocks = stp.n_blocks;
+        a.ws = ws;
+        a.in = d_in;
+        a.taps = plan->d_taps;
+        if (stp.count <= kInlineJobs)
+            for (int j = 0; j < stp.count; ++j) a.inl[j] = plan->fjobs[stp.first + j];
+        e = launch_blur(a, stp.max_r, stp.dog, st);
     } else if (stp.type == 1) {
         XYLaunch a{};
         a.jobs = plan->d_xy + stp.first;
@@ -754,12 +828,16 @@ int sift3d_pyramid_pass(const sift3d_plan *plan, int pass, const float *d_vol, v
     for (size_t k = 0; k < plan->tasks.size(); ++k)
         if (plan->tasks[k].kind == 0 && plan->tasks[k].pass == pass) t = (int)k;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (L.fused) return run_step(plan, Step{0, {t}, 0, 1, 0, 0}, d_vol, d_ws, st);
+    if (L.fused) {
+        const DFJob &f = plan->fjobs[plan->solo_f[t]];
+        return run_step(plan, Step{0, {t}, plan->solo_f[t], 1, f.tiles_x * f.tiles_y * f.slabs, L.r, L.dog}, d_vol,
+                        d_ws, st);
+    }
     const VolPlan &vp = plan->vols[L.vol];
     const OctaveGeom &g = vp.oct[L.octave];
-    rc = run_step(plan, Step{1, {t}, plan->solo_xy[t], 1, xy_blocks(g), L.r}, d_vol, d_ws, st);
+    rc = run_step(plan, Step{1, {t}, plan->solo_xy[t], 1, xy_blocks(g), L.r, false}, d_vol, d_ws, st);
     if (rc != SIFT3D_OK) return rc;
-    return run_step(plan, Step{2, {t}, plan->solo_z[t], 1, z_blocks(g), L.r}, d_vol, d_ws, st);
+    return run_step(plan, Step{2, {t}, plan->solo_z[t], 1, z_blocks(g), L.r, false}, d_vol, d_ws, st);
 }
 
 int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_keypoint *d_kp, int kp_capacity,

@@ -61,8 +61,24 @@ __device__ __forceinline__ void static_for(F &&f)
     }
 }
 
-template <int R, bool DOG>
-__global__ void __launch_bounds__(kBlurThreads) blur_level_kernel(const BlurArgs a)
+// Job of a block: the last job whose first block is <= bid (jobs sorted by block0).
+__device__ __forceinline__ int find_fjob(const DFJob *jobs, int n, int bid)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block0 <= bid)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// INL: the jobs are read from the inline copy in the arguments (small
+// launches), else from the device table.
+template <int R, bool DOG, bool INL>
+__global__ void __launch_bounds__(kBlurThreads) blur_level_kernel(const FusedLaunch fl)
 {
     constexpr int TX = kBlurTX, TY = kBlurTY, NY = kBlurNY, NT = kBlurThreads;
     constexpr int M = 2 * R + 1;
@@ -83,15 +99,23 @@ __global__ void __launch_bounds__(kBlurThreads) blur_level_kernel(const BlurArgs
     __shared__ float C[DOG ? (R + 1) * NY * NT : 1];
 
     const int tid = threadIdx.x;
-    const int logical = xcd_remap(blockIdx.x, a.n_blocks);
-    const int ntile = a.tiles_x * a.tiles_y;
-    const int slab = logical / ntile;
-    const int t2 = logical - slab * ntile;
-    const int tyi = t2 / a.tiles_x;
-    const int txi = t2 - tyi * a.tiles_x;
-    const int x0 = txi * TX, y0 = tyi * TY, z0 = slab * a.L;
-    const int z1 = min(z0 + a.L, a.nz);
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int logical = xcd_remap(blockIdx.x, fl.n_blocks);
+    const DFJob jb = INL ? fl.inl[find_fjob(fl.inl, fl.n_jobs, logical)]
+                         : fl.jobs[find_fjob(fl.jobs, fl.n_jobs, logical)];
+    const float *const src = jb.src_input ? fl.in + jb.src : reinterpret_cast<const float *>(fl.ws + jb.src);
+    float *const dst = reinterpret_cast<float *>(fl.ws + jb.dst);
+    float *const dogp = DOG ? reinterpret_cast<float *>(fl.ws + jb.dog) : nullptr;
+    float *const subp = jb.sub < 0 ? nullptr : reinterpret_cast<float *>(fl.ws + jb.sub);
+    const float *const wt = fl.taps + (size_t)jb.taps * kMaxTaps;
+    const int local = logical - jb.block0;
+    const int ntile = jb.tiles_x * jb.tiles_y;
+    const int slab = local / ntile;
+    const int t2 = local - slab * ntile;
+    const int tyi = t2 / jb.tiles_x;
+    const int txi = t2 - tyi * jb.tiles_x;
+    const int x0 = txi * TX, y0 = tyi * TY, z0 = slab * jb.L;
+    const int z1 = min(z0 + jb.L, jb.nz);
+    const int nx = jb.nx, ny = jb.ny, nz = jb.nz;
     const size_t nxy = (size_t)nx * ny;
 
     // Per-thread staging slots: the same in-plane offsets for every plane.
@@ -111,14 +135,14 @@ __global__ void __launch_bounds__(kBlurThreads) blur_level_kernel(const BlurArgs
     }
     float pre[KL];
     auto load_plane = [&](int zi) {
-        const float *p = a.src + (size_t)clampi(zi, 0, nz - 1) * nxy;
+        const float *p = src + (size_t)clampi(zi, 0, nz - 1) * nxy;
 #pragma unroll
         for (int k = 0; k < KL; ++k) pre[k] = p[goff[k]];
     };
 
     float w[M];
 #pragma unroll
-    for (int t = 0; t < M; ++t) w[t] = a.w[t];
+    for (int t = 0; t < M; ++t) w[t] = wt[t];
 
     const int tx = tid % TX;
     const int tyb = (tid / TX) * NY;
@@ -198,23 +222,23 @@ __global__ void __launch_bounds__(kBlurThreads) blur_level_kernel(const BlurArgs
 #pragma unroll
                 for (int j = 0; j < NY; ++j)
                     zo[j] = sym_stencil<R>(w, [&](int t) { return ring[j][(p + 1 + t) % M]; });
-                float *d = a.dst + (size_t)oz * nxy;
+                float *d = dst + (size_t)oz * nxy;
                 if (ok0) d[o0] = zo[0];
                 if (ok1) d[o1] = zo[1];
                 if constexpr (DOG) {
-                    float *e = a.dog + (size_t)oz * nxy;
+                    float *e = dogp + (size_t)oz * nxy;
                     if (ok0) e[o0] = cv0 - zo[0];
                     if (ok1) e[o1] = cv1 - zo[1];
                 }
-                if (a.sub != nullptr) {
+                if (subp != nullptr) {
                     const float s2 = zo[0] + zo[1];
                     const float s4 = s2 + __shfl_xor(s2, 1);
                     if ((oz & 1) == 0) {
                         subacc = s4;
                     } else {
                         const int X = gx >> 1, Y = gy0 >> 1, Z = oz >> 1;
-                        if ((tx & 1) == 0 && X < a.mx && Y < a.my && Z < a.mz)
-                            a.sub[((size_t)Z * a.my + Y) * a.mx + X] = (subacc + s4) * 0.125f;
+                        if ((tx & 1) == 0 && X < jb.mx && Y < jb.my && Z < jb.mz)
+                            subp[((size_t)Z * jb.my + Y) * jb.mx + X] = (subacc + s4) * 0.125f;
                     }
                 }
             }
@@ -223,20 +247,27 @@ __global__ void __launch_bounds__(kBlurThreads) blur_level_kernel(const BlurArgs
 }
 
 template <int R>
-hipError_t launch_r(const BlurArgs &a, bool dog, hipStream_t st)
+hipError_t launch_r(const FusedLaunch &a, bool dog, hipStream_t st)
 {
-    if (dog)
-        hipLaunchKernelGGL((blur_level_kernel<R, true>), dim3(a.n_blocks), dim3(kBlurThreads), 0, st, a);
+    const dim3 g(a.n_blocks), b(kBlurThreads);
+    const bool inl = a.n_jobs <= kInlineJobs;
+    if (dog && inl)
+        hipLaunchKernelGGL((blur_level_kernel<R, true, true>), g, b, 0, st, a);
+    else if (dog)
+        hipLaunchKernelGGL((blur_level_kernel<R, true, false>), g, b, 0, st, a);
+    else if (inl)
+        hipLaunchKernelGGL((blur_level_kernel<R, false, true>), g, b, 0, st, a);
     else
-        hipLaunchKernelGGL((blur_level_kernel<R, false>), dim3(a.n_blocks), dim3(kBlurThreads), 0, st, a);
+        hipLaunchKernelGGL((blur_level_kernel<R, false, false>), g, b, 0, st, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_blur(const BlurArgs &a, int r, bool dog, hipStream_t st)
+hipError_t launch_blur(const FusedLaunch &a, int r, bool dog, hipStream_t st)
 {
     static_assert(kMaxFusedR == 10, "one case per fused radius");
+    if (a.n_blocks <= 0) return hipSuccess;
     switch (r) {
     case 0: return launch_r<0>(a, dog, st);
     case 1: return launch_r<1>(a, dog, st);
@@ -261,8 +292,8 @@ int fused_blocks_per_cu(int r, bool dog)
     hipError_t e = hipErrorInvalidValue;
 #define S3D_OCC(R)                                                                                               \
     case R:                                                                                                      \
-        e = dog ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, true>, kBlurThreads, 0) \
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, false>, kBlurThreads, 0); \
+        e = dog ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, true, true>, kBlurThreads, 0) \
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, false, true>, kBlurThreads, 0); \
         break;
     switch (r) {
         S3D_OCC(0) S3D_OCC(1) S3D_OCC(2) S3D_OCC(3) S3D_OCC(4) S3D_OCC(5) S3D_OCC(6) S3D_OCC(7) S3D_OCC(8)

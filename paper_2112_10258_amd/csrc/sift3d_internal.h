@@ -116,25 +116,36 @@ struct DVol {
 
 // ---------------------------------------------------------------- launch arguments
 
-// One launch of the fused blur -> DoG -> sub-sample pass (one level of one
-// octave of one volume; pointers bound per call).
-struct BlurArgs {
-    const float *src;     // G_{i-1} (or the input volume)
-    float *dst;           // G_i
-    float *dog;           // D_{i-1} = src - dst, or nullptr
-    float *sub;           // 2x2x2 mean of dst into the next octave's G_0, or nullptr
+// One job of a fused blur -> DoG -> sub-sample launch: one level of one
+// octave of one volume, streamed as tiles x slabs workgroups.
+struct DFJob {
+    long long src;        // workspace byte offset, or input element offset if src_input
+    long long dst;        // workspace byte offset of G_i
+    long long dog;        // D_{i-1} (< 0: none)
+    long long sub;        // next octave's G_0 (< 0: none)
+    int src_input;
     int nx, ny, nz;
     int mx, my, mz;       // dims of `sub`
     int L;                // output planes per slab (even)
     int tiles_x, tiles_y, slabs;
-    int n_blocks;         // tiles_x * tiles_y * slabs
-    float w[kMaxTaps];    // taps w[t + r], t = -r..r
+    int block0;           // first block of the job within its launch
+    int taps;             // tap-set index
+    int pad_[3];
 };
 
 // Launches with few jobs also carry them inline (read through the scalar
 // cache from the argument segment instead of a dependent global load).
 constexpr int kInlineJobs = 8;
 constexpr int kInlineUnits = 12;
+
+struct FusedLaunch {
+    const DFJob *jobs;    // this launch's jobs, block0 ascending; all share R and the DoG flag
+    int n_jobs, n_blocks;
+    char *ws;
+    const float *in;      // packed input volumes
+    const float *taps;    // [n_tapsets][kMaxTaps]
+    DFJob inl[kInlineJobs];
+};
 
 struct XYLaunch {
     const DXYJob *jobs;   // this launch's jobs, block0 ascending
@@ -207,7 +218,6 @@ struct BlurLaunch {
     int r;
     bool dog;
     bool fused;           // fused streaming pass, else xy + z jobs
-    BlurArgs a;           // fused geometry (pointers bound per call)
     int tapset;           // index into sift3d_plan::tapsets
     int src_kind;         // -1 = input volume, 0 = G level of the octave
     int src_idx, dst_idx, dog_idx;
@@ -227,9 +237,10 @@ struct Task {
 // split tasks (their jobs are entries [first, first + count) of the device
 // job table of that kind).
 struct Step {
-    int type;             // 0 = fused pass, 1 = xy launch, 2 = z launch
+    int type;             // 0 = fused launch, 1 = xy launch, 2 = z launch
     std::vector<int> tasks;
     int first, count, n_blocks, max_r;
+    bool dog;             // fused launches: jobs write a DoG level
 };
 
 struct VolPlan {
@@ -269,23 +280,26 @@ struct sift3d_plan {
     std::vector<s3d::Task> tasks;
     std::vector<s3d::Step> sched;       // launches of sift3d_build_pyramid
     std::vector<int> solo_xy, solo_z;   // per task: index of its single-job entry (-1: fused)
+    std::vector<int> solo_f;            // per task: index of its single-job fused entry (-1: split)
     // host copies of the device tables
     std::vector<s3d::DUnit> units;
     std::vector<s3d::DVol> dvols;
     std::vector<s3d::DXYJob> xyjobs;
     std::vector<s3d::DZJob> zjobs;
+    std::vector<s3d::DFJob> fjobs;
     // device tables (one allocation, owned by the plan)
     void *d_tables;
     s3d::DUnit *d_units;
     s3d::DVol *d_vols;
     s3d::DXYJob *d_xy;
     s3d::DZJob *d_z;
+    s3d::DFJob *d_f;
     float *d_taps;
 };
 
 namespace s3d {
 // Launchers (return hipError_t of the launch).
-hipError_t launch_blur(const BlurArgs &a, int r, bool dog, hipStream_t st);
+hipError_t launch_blur(const FusedLaunch &a, int r, bool dog, hipStream_t st);
 int fused_blocks_per_cu(int r, bool dog);
 hipError_t launch_blur_xy(const XYLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_blur_z(const ZLaunch &a, int max_r, hipStream_t st);

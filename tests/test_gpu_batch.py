@@ -31,20 +31,23 @@ def _run_plain(vol, cap, **kw):
     return res
 
 
-@pytest.mark.parametrize("cap", [4096, 7])
-def test_batch_equals_plain(cap):
+@pytest.mark.parametrize("cap,mode", [(4096, 0), (7, 0), (4096, 1)])
+def test_batch_equals_plain(cap, mode):
+    """mode 1 puts every level on the fused pass: one fused launch per level
+    covers all volumes (a job table with per-volume slabs)."""
     import torch
     import paper_2112_10258_amd as S
     vols = _vols()
-    print(f"[batch] shapes={SHAPES} cap={cap}", flush=True)
-    ctx = S.Context(S.default_params(**PARAMS), P.pair_draws())
+    params = dict(PARAMS, pyramid_mode=mode)
+    print(f"[batch] shapes={SHAPES} cap={cap} mode={mode}", flush=True)
+    ctx = S.Context(S.default_params(**params), P.pair_draws())
     plan = S.Plan(ctx, [(v.shape[2], v.shape[1], v.shape[0]) for v in vols], cap, batch=True)
     assert plan.n_volumes == len(vols)
     buf = S.Buffers(plan)
     S.run_extract(plan, plan.pack_volumes(vols), buf)
     torch.cuda.synchronize()
     for v, vol in enumerate(vols):
-        ref = _run_plain(vol, cap, **PARAMS)
+        ref = _run_plain(vol, cap, **params)
         got = S.fetch_results(plan, buf, v)
         assert got["count"] == ref["count"], v
         assert got["keypoints"].tobytes() == ref["keypoints"].tobytes(), v
