@@ -17,37 +17,37 @@ constexpr int kDescThreads = 256;
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
-// One (dx, dy) column of the SIFT-Rank window: all loads of the column are
-// issued first (4 per sample for the x/y differences, the column itself for
-// z), then |g| is accumulated per (z half, orientation octant) in double.
+// Side of the cube of G_s a SIFT-Rank window reads: the (2R+1)^3 samples
+// and their central-difference neighbours.
+constexpr int kSiftTile = 2 * kMaxSiftR + 3;
+
+// One (dx, dy) column of the SIFT-Rank window, read from the staged cube T
+// (T[k][j][i] = G_s at clamp(corner + (i, j, k)), corner = keypoint - R - 1):
+// the sample q = clamp(v + d) and its neighbours clamp(q +- 1) always fall
+// inside the cube, so each is one LDS read. |g| is accumulated per (z half,
+// orientation octant) in double.
 template <int R>
-__device__ __forceinline__ void sift_column(const float *G, int nx, int ny, int nz, int cx, int cy, int cz,
-                                            double (&acc)[16])
+__device__ __forceinline__ void sift_column(const float *T, int nx, int ny, int nz, int kx, int ky, int kz, int dx,
+                                            int dy, double (&acc)[16])
 {
-    constexpr int W = 2 * R + 1;
-    const int qx = clampi(cx, 0, nx - 1), qy = clampi(cy, 0, ny - 1);
-    const int xm = clampi(qx - 1, 0, nx - 1), xp = clampi(qx + 1, 0, nx - 1);
-    const int ym = clampi(qy - 1, 0, ny - 1), yp = clampi(qy + 1, 0, ny - 1);
-    const size_t nxy = (size_t)nx * ny;
-    float fxp[W], fxm[W], fyp[W], fym[W], fzp[W], fzm[W];
-#pragma unroll
-    for (int i = 0; i < W; ++i) {
-        const int qz = clampi(cz + i - R, 0, nz - 1);
-        const int zm = clampi(qz - 1, 0, nz - 1), zp = clampi(qz + 1, 0, nz - 1);
-        const size_t rc = (size_t)qz * nxy + (size_t)qy * nx;
-        fxp[i] = G[rc + xp];
-        fxm[i] = G[rc + xm];
-        fyp[i] = G[(size_t)qz * nxy + (size_t)yp * nx + qx];
-        fym[i] = G[(size_t)qz * nxy + (size_t)ym * nx + qx];
-        fzp[i] = G[(size_t)zp * nxy + (size_t)qy * nx + qx];
-        fzm[i] = G[(size_t)zm * nxy + (size_t)qy * nx + qx];
-    }
+    constexpr int W = 2 * R + 1, TW = 2 * R + 3;
+    const int cx = kx - R - 1, cy = ky - R - 1, cz = kz - R - 1;
+    const int qx = clampi(kx + dx, 0, nx - 1), qy = clampi(ky + dy, 0, ny - 1);
+    const int lx = qx - cx, ly = qy - cy;
+    const int lxm = clampi(qx - 1, 0, nx - 1) - cx, lxp = clampi(qx + 1, 0, nx - 1) - cx;
+    const int lym = clampi(qy - 1, 0, ny - 1) - cy, lyp = clampi(qy + 1, 0, ny - 1) - cy;
 #pragma unroll
     for (int i = 0; i < W; ++i) {
         const int dz = i - R;
-        const double gx = 0.5 * ((double)fxp[i] - (double)fxm[i]);
-        const double gy = 0.5 * ((double)fyp[i] - (double)fym[i]);
-        const double gz = 0.5 * ((double)fzp[i] - (double)fzm[i]);
+        const int qz = clampi(kz + dz, 0, nz - 1);
+        const int lz = qz - cz, lzm = clampi(qz - 1, 0, nz - 1) - cz, lzp = clampi(qz + 1, 0, nz - 1) - cz;
+        const float *row = T + (lz * TW + ly) * TW;
+        const float fxp = row[lxp], fxm = row[lxm];
+        const float fyp = T[(lz * TW + lyp) * TW + lx], fym = T[(lz * TW + lym) * TW + lx];
+        const float fzp = T[(lzp * TW + ly) * TW + lx], fzm = T[(lzm * TW + ly) * TW + lx];
+        const double gx = 0.5 * ((double)fxp - (double)fxm);
+        const double gy = 0.5 * ((double)fyp - (double)fym);
+        const double gz = 0.5 * ((double)fzp - (double)fzm);
         const double m = sqrt(gx * gx + gy * gy + gz * gz);
         const int bo = (gx > 0.0) + 2 * (gy > 0.0) + 4 * (gz > 0.0);
         const double w0 = dz < 0 ? m : (dz == 0 ? 0.5 * m : 0.0);
@@ -57,6 +57,29 @@ __device__ __forceinline__ void sift_column(const float *G, int nx, int ny, int 
             acc[b] += bo == b ? w0 : 0.0;
             acc[8 + b] += bo == b ? w1 : 0.0;
         }
+    }
+}
+
+// Stage G_s over clamp(keypoint - R - 1 .. keypoint + R + 1) per axis into
+// T, then accumulate this thread's (dx, dy) column (threads < (2R+1)^2).
+// Called by the whole workgroup (it contains a barrier).
+template <int R>
+__device__ __forceinline__ void sift_window(const float *G, float *T, int nx, int ny, int nz, int kx, int ky, int kz,
+                                            int tid, double (&acc)[16])
+{
+    constexpr int W = 2 * R + 1, TW = 2 * R + 3;
+    const int cx = kx - R - 1, cy = ky - R - 1, cz = kz - R - 1;
+    const size_t nxy = (size_t)nx * ny;
+    for (int idx = tid; idx < TW * TW * TW; idx += kDescThreads) {
+        const int i = idx % TW, jk = idx / TW;
+        const int j = jk % TW, k = jk / TW;
+        const int gx = clampi(cx + i, 0, nx - 1), gy = clampi(cy + j, 0, ny - 1), gz = clampi(cz + k, 0, nz - 1);
+        T[idx] = G[(size_t)gz * nxy + (size_t)gy * nx + gx];
+    }
+    __syncthreads();
+    if (tid < W * W) {
+        const int dy = tid / W - R, dx = tid - (tid / W) * W - R;
+        sift_column<R>(T, nx, ny, nz, kx, ky, kz, dx, dy, acc);
     }
 }
 
@@ -93,11 +116,16 @@ __device__ __forceinline__ int first_of_block(int b, long long base, int grid)
 // its bit comes from a ballot and its rank from a comparison against all n
 // differences in LDS.
 template <bool INL>
-__global__ void __launch_bounds__(kDescThreads) describe_kernel(const DescLaunch a)
+__global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLaunch a)
 {
     constexpr int kCols = (2 * kMaxSiftR + 1) * (2 * kMaxSiftR + 1);
     static_assert(kCols <= kDescThreads, "one thread per window column");
-    __shared__ double part[kCols][17];
+    constexpr int kTileFloats = kSiftTile * kSiftTile * kSiftTile;
+    constexpr int kPartBytes = kCols * 17 * (int)sizeof(double);
+    // the staged cube and the per-column sums share LDS (a barrier separates them)
+    __shared__ __align__(16) char scratch[kPartBytes > kTileFloats * 4 ? kPartBytes : kTileFloats * 4];
+    float *const T = reinterpret_cast<float *>(scratch);
+    double(*const part)[17] = reinterpret_cast<double(*)[17]>(scratch);
     __shared__ double cls[9][16];
     __shared__ double hist[64];
     __shared__ __align__(16) double dd[kMaxPairs];
@@ -141,20 +169,20 @@ __global__ void __launch_bounds__(kDescThreads) describe_kernel(const DescLaunch
             const float *G = reinterpret_cast<const float *>(a.ws + oc.g0) + oc.lstride * kp.scale;
             const int R = a.sift_R[kp.scale];
             const int W = 2 * R + 1;
-            if (tid < W * W) {
-                double acc[16];
+            double acc[16];
 #pragma unroll
-                for (int b = 0; b < 16; ++b) acc[b] = 0.0;
-                const int dy = tid / W - R, dx = tid - (tid / W) * W - R;
-                switch (R) {
-                case 1: sift_column<1>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-                case 2: sift_column<2>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-                case 3: sift_column<3>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-                case 4: sift_column<4>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-                case 5: sift_column<5>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-                case 6: sift_column<6>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-                default: sift_column<7>(G, nx, ny, nz, kp.x + dx, kp.y + dy, kp.z, acc); break;
-                }
+            for (int b = 0; b < 16; ++b) acc[b] = 0.0;
+            switch (R) {
+            case 1: sift_window<1>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+            case 2: sift_window<2>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+            case 3: sift_window<3>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+            case 4: sift_window<4>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+            case 5: sift_window<5>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+            case 6: sift_window<6>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+            default: sift_window<7>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+            }
+            __syncthreads();   // the column sums overwrite the staged cube
+            if (tid < W * W) {
 #pragma unroll
                 for (int b = 0; b < 16; ++b) part[tid][b] = acc[b];
             }
