@@ -177,15 +177,41 @@ void task_jobs(const sift3d_plan *pl, const Task &k, DXYJob &xy, DZJob &z)
     z.gz = (g->nz + kZPlanes - 1) / kZPlanes;
 }
 
+// Whether a level of an octave of n voxels blurred with radius r runs on
+// the fused pass (compiled for radii up to kMaxFusedR; larger ones run split).
+bool fused_choice(const sift3d_params &p, long long n, int r)
+{
+    if (r > kMaxFusedR || p.pyramid_mode == 2) return false;
+    if (p.pyramid_mode == 1) return true;
+    return n >= kFusedMinVoxels || (n >= kFusedMidVoxels && r <= kFusedMidMaxR);
+}
+
 // The fused job of a level-pass task, its depth split into `slabs` slabs
 // (block0 left for the caller).
 DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs)
 {
     const int S = pl->S;
+    DFJob f{};
+    if (k.kind == 1) {
+        // BRIEF pre-blur: G_s -> B_s, no DoG, no sub-sample
+        const OctaveGeom &g = pl->vols[k.vol].oct[k.octave];
+        f.src = (long long)level_off(g, lev_G(k.s));
+        f.dst = (long long)level_off(g, lev_B(S, k.s));
+        f.dog = -1;
+        f.sub = -1;
+        f.nx = g.nx;
+        f.ny = g.ny;
+        f.nz = g.nz;
+        f.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
+        f.tiles_y = (g.ny + kBlurTY - 1) / kBlurTY;
+        f.L = slab_planes(g.nz, slabs, pl->brief_rb);
+        f.slabs = (g.nz + f.L - 1) / f.L;
+        f.taps = pl->brief_tapset;
+        return f;
+    }
     const BlurLaunch &L = pl->blur[k.pass];
     const VolPlan &vp = pl->vols[L.vol];
     const OctaveGeom &g = vp.oct[L.octave];
-    DFJob f{};
     if (L.src_kind < 0) {
         f.src = (long long)vp.in_off;
         f.src_input = 1;
@@ -260,7 +286,19 @@ void build_schedule(sift3d_plan *pl)
         if (L.src_idx == 0 && L.octave > 0) return pass_done(L.vol, L.octave - 1, S);  // G_0 from the sub-sample
         return pass_done(L.vol, L.octave, L.src_idx);
     };
-    auto is_fused = [&](int t) { return pl->tasks[t].kind == 0 && pl->blur[pl->tasks[t].pass].fused; };
+    auto task_r = [&](int t) { return pl->tasks[t].kind == 0 ? pl->blur[pl->tasks[t].pass].r : pl->brief_rb; };
+    auto task_dog = [&](int t) { return pl->tasks[t].kind == 0 && pl->blur[pl->tasks[t].pass].dog; };
+    auto task_geom = [&](int t) -> const OctaveGeom & {
+        const Task &k = pl->tasks[t];
+        return pl->vols[k.vol].oct[k.kind == 0 ? pl->blur[k.pass].octave : k.octave];
+    };
+    // pre-blurs go on the fused pass by the same rule as the level passes
+    const sift3d_params &pp = pl->ctx->p;
+    auto is_fused = [&](int t) {
+        const Task &k = pl->tasks[t];
+        if (k.kind == 0) return pl->blur[k.pass].fused;
+        return fused_choice(pp, (long long)task_geom(t).n, pl->brief_rb);
+    };
     auto emit = [&](int type, const std::vector<int> &ts) {
         if (ts.empty()) return;
         Step st{type, ts, 0, (int)ts.size(), 0, 0, false};
@@ -290,20 +328,17 @@ void build_schedule(sift3d_plan *pl)
     auto emit_fused = [&](const std::vector<int> &ts) {
         std::vector<int> left = ts;
         while (!left.empty()) {
-            const BlurLaunch &L0 = pl->blur[pl->tasks[left[0]].pass];
+            const int r0 = task_r(left[0]);
+            const bool dog0 = task_dog(left[0]);
             std::vector<int> grp, rest;
-            for (int t : left) {
-                const BlurLaunch &L = pl->blur[pl->tasks[t].pass];
-                (L.r == L0.r && L.dog == L0.dog ? grp : rest).push_back(t);
-            }
+            for (int t : left) (task_r(t) == r0 && task_dog(t) == dog0 ? grp : rest).push_back(t);
             long long tiles = 0;
             for (int t : grp) {
-                const BlurLaunch &L = pl->blur[pl->tasks[t].pass];
-                const OctaveGeom &g = pl->vols[L.vol].oct[L.octave];
+                const OctaveGeom &g = task_geom(t);
                 tiles += (long long)((g.nx + kBlurTX - 1) / kBlurTX) * ((g.ny + kBlurTY - 1) / kBlurTY);
             }
-            const int slabs = fused_slabs(pl, tiles, L0.r, L0.dog);
-            Step st{0, grp, (int)pl->fjobs.size(), (int)grp.size(), 0, L0.r, L0.dog};
+            const int slabs = fused_slabs(pl, tiles, r0, dog0);
+            Step st{0, grp, (int)pl->fjobs.size(), (int)grp.size(), 0, r0, dog0};
             for (int t : grp) {
                 DFJob f = fused_job(pl, pl->tasks[t], slabs);
                 f.block0 = st.n_blocks;
@@ -347,6 +382,7 @@ void build_schedule(sift3d_plan *pl)
     pl->solo_z.assign(nt, -1);
     pl->solo_f.assign(nt, -1);
     for (int t = 0; t < nt; ++t) {
+        if (pl->tasks[t].kind == 1 && is_fused(t)) continue;  // pre-blurs have no single-pass entry
         if (is_fused(t)) {
             const BlurLaunch &L = pl->blur[pl->tasks[t].pass];
             const OctaveGeom &g = pl->vols[L.vol].oct[L.octave];
@@ -551,10 +587,7 @@ int make_plan(sift3d_ctx *ctx, int n, const int *dims, int kp_capacity, sift3d_p
                 L.dst_idx = i;
                 L.dog_idx = i - 1;
                 L.sub_octave = (i == S && o + 1 < no) ? o + 1 : -1;
-                // the fused pass is compiled for radii up to kMaxFusedR; larger ones run split
-                const bool by_size = (long long)g.n >= kFusedMinVoxels ||
-                                     ((long long)g.n >= kFusedMidVoxels && L.r <= kFusedMidMaxR);
-                L.fused = L.r <= kMaxFusedR && (p.pyramid_mode == 1 || (p.pyramid_mode == 0 && by_size));
+                L.fused = fused_choice(p, (long long)g.n, L.r);
                 pl->blur.push_back(L);
             }
         }
