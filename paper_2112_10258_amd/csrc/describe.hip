@@ -50,12 +50,21 @@ __device__ __forceinline__ void sift_column(const float *T, int nx, int ny, int 
         const double gz = 0.5 * ((double)fzp - (double)fzm);
         const double m = sqrt(gx * gx + gy * gy + gz * gz);
         const int bo = (gx > 0.0) + 2 * (gy > 0.0) + 4 * (gz > 0.0);
-        const double w0 = dz < 0 ? m : (dz == 0 ? 0.5 * m : 0.0);
-        const double w1 = dz > 0 ? m : (dz == 0 ? 0.5 * m : 0.0);
+        // dz is a compile-time constant here: a sample feeds only its z half
+        // (both halves, with half weight, on the centre plane)
+        if (dz < 0) {
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            acc[b] += bo == b ? w0 : 0.0;
-            acc[8 + b] += bo == b ? w1 : 0.0;
+            for (int b = 0; b < 8; ++b) acc[b] += bo == b ? m : 0.0;
+        } else if (dz > 0) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) acc[8 + b] += bo == b ? m : 0.0;
+        } else {
+            const double h = 0.5 * m;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                acc[b] += bo == b ? h : 0.0;
+                acc[8 + b] += bo == b ? h : 0.0;
+            }
         }
     }
 }
@@ -113,8 +122,8 @@ __device__ __forceinline__ int first_of_block(int b, long long base, int grid)
 // whole-level separable pass with the same clamp-to-edge rule, so B_s at a
 // voxel equals the pre-blur stencil evaluated there). Thread i owns pair i:
 // d_i = B_s(p1) - B_s(p2) is the exact double difference of the two samples,
-// its bit comes from a ballot and its rank from a comparison against all n
-// differences in LDS.
+// its bit comes from a ballot and its rank from a bitonic sort of the
+// (d_i, i) pairs in LDS.
 template <bool INL>
 __global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLaunch a)
 {
@@ -128,7 +137,8 @@ __global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLau
     double(*const part)[17] = reinterpret_cast<double(*)[17]>(scratch);
     __shared__ double cls[9][16];
     __shared__ double hist[64];
-    __shared__ __align__(16) double dd[kMaxPairs];
+    __shared__ double sk[kMaxPairs];    // RRIEF sort keys (difference, pair index)
+    __shared__ int si[kMaxPairs];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = a.brief_n, nw = n / 64;
     const bool do_sr = a.siftrank != nullptr;
@@ -162,7 +172,6 @@ __global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLau
             const float b1 = B[((size_t)z1 * ny + y1) * nx + x1];
             const float b2 = B[((size_t)z2 * ny + y2) * nx + x2];
             d = (double)b1 - (double)b2;
-            dd[tid] = d;
         }
 
         if (do_sr) {
@@ -223,19 +232,38 @@ __global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLau
             a.siftrank[k * 64 + tid] = (uint8_t)r;
         }
         if (do_br && tid < n) {
-            if (a.rrief != nullptr) {
-                // rank of d_i among the n: #{j : d_j < d_i or (d_j == d_i and j < i)}
-                int r = 0;
-                const double2 *d2 = reinterpret_cast<const double2 *>(dd);
-                for (int j = 0; j < n / 2; ++j) {
-                    const double2 o = d2[j];
-                    r += (int)(o.x < d) | ((int)(o.x == d) & (int)(2 * j < tid));
-                    r += (int)(o.y < d) | ((int)(o.y == d) & (int)(2 * j + 1 < tid));
-                }
-                a.rrief[k * n + tid] = (uint8_t)r;
-            }
             const unsigned long long m = __ballot(d > 0.0);
             if (a.brief != nullptr && lane == 0) a.brief[k * nw + wave] = m;
+        }
+        if (do_br && a.rrief != nullptr) {
+            // rank of d_i among the n: #{j : d_j < d_i or (d_j == d_i and j < i)},
+            // i.e. the position of (d_i, i) in ascending lexicographic order, by a
+            // bitonic sort of the (difference, index) pairs (n padded to 256 with
+            // +inf keys, which sort after every finite difference)
+            sk[tid] = tid < n ? d : __builtin_inf();
+            si[tid] = tid;
+            __syncthreads();
+#pragma unroll 1
+            for (int kk2 = 2; kk2 <= kMaxPairs; kk2 <<= 1) {
+#pragma unroll 1
+                for (int j = kk2 >> 1; j > 0; j >>= 1) {
+                    const int p = tid ^ j;
+                    if (p > tid) {
+                        const double ka = sk[tid], kb = sk[p];
+                        const int ia = si[tid], ib = si[p];
+                        const bool gt = ka > kb || (ka == kb && ia > ib);
+                        if (gt == ((tid & kk2) == 0)) {
+                            sk[tid] = kb;
+                            sk[p] = ka;
+                            si[tid] = ib;
+                            si[p] = ia;
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            const int i = si[tid];
+            if (i < n) a.rrief[k * n + i] = (uint8_t)tid;
         }
         __syncthreads();
     }
