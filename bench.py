@@ -223,7 +223,7 @@ def _pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
 
 
-def serve_vs_plain(n_req, rate, pool_per_class, n_streams, max_inflight, budget_gb, stream, extra):
+def serve_vs_plain(n_req, rate, pool_per_class, n_streams, max_inflight, max_batch, budget_gb, stream, extra):
     """The config-5 request stream through the server against a plain
     one-request-at-a-time loop: saturated throughput (all requests queued at
     once) and latency at the Poisson arrival rate. Volumes come from a pool of
@@ -280,7 +280,7 @@ def serve_vs_plain(n_req, rate, pool_per_class, n_streams, max_inflight, budget_
     torch.cuda.empty_cache()
 
     srv = S.Server(ctx, hbm_budget=int(budget_gb * (1 << 30)), n_streams=n_streams, max_inflight=max_inflight,
-                   kp_capacity=cap)
+                   kp_capacity=cap, max_batch=max_batch)
     mismatch = 0
 
     def run(items, paced):
@@ -331,7 +331,9 @@ def serve_vs_plain(n_req, rate, pool_per_class, n_streams, max_inflight, budget_
     return {
         "workload": f"config5: {n_req} requests, Poisson {rate:g}/s, sizes {sizes} w.p. {list(P.CONFIG5_PROBS)}",
         "volumes_pool": f"{pool_per_class} distinct volumes per size class (request i uses volume i mod {pool_per_class})",
-        "server": {"n_streams": n_streams, "max_inflight": max_inflight, "hbm_budget_gb": budget_gb,
+        "server": {"n_streams": n_streams, "max_inflight": max_inflight, "max_batch": max_batch,
+                   "hbm_budget_gb": budget_gb, "groups": st["groups"],
+                   "mean_group_size": round(st["grouped_requests"] / max(st["groups"], 1), 2),
                    "peak_allocated_gb": round(st["peak_allocated"] / 2**30, 3),
                    "slot_allocations": st["slot_allocations"], "slot_evictions": st["slot_evictions"]},
         "saturated": {"served_volumes_per_s": round(served_sat, 1), "plain_volumes_per_s": round(plain_sat, 1),
@@ -386,6 +388,7 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=4)
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-inflight", type=int, default=8)
+    ap.add_argument("--serve-batch", type=int, default=8, help="largest group of same-shape requests")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     args = ap.parse_args()
     if args.summarize_pmc:
@@ -495,7 +498,7 @@ def main():
     serve = None
     if not args.no_serve:
         serve = serve_vs_plain(args.serve_requests, args.serve_rate, args.serve_pool, args.serve_streams,
-                               args.serve_inflight, args.serve_budget_gb, stream, extra)
+                               args.serve_inflight, args.serve_batch, args.serve_budget_gb, stream, extra)
         log(f"[bench] serve: {serve}")
 
     cpu = None

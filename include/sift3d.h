@@ -239,25 +239,30 @@ int sift3d_extract(const sift3d_plan *plan, const float *d_vol, void *d_ws, size
  * Request server: continuous batching of independent extractions on one GPU
  * (the per-volume work of sift3d_extract, for volumes that arrive over
  * time). A scheduler thread owned by the server admits requests in arrival
- * order while (a) fewer than max_inflight are on the device and (b) a slot
- * of the request's shape is idle or can be allocated within hbm_budget
- * bytes (idle slots of other shapes are freed, least recently used first,
- * to make room). A slot is one device allocation holding the pyramid
- * workspace and the keypoint and descriptor buffers of one request; slots
- * and plans are cached per shape. Admitted requests are spread over
- * n_streams non-blocking streams (default priority) so that several run on
- * the device at once. Each request runs the same kernels as sift3d_extract
- * on its own slot, so its result is the same alone and among others.
- * The server owns its slots, plans, streams and thread; the context must
- * outlive it.
+ * order. The request at the head of the queue is admitted together with up
+ * to max_batch - 1 later waiting requests of the same shape (the group size
+ * rounded down to a power of two), as one batch extraction: each launch
+ * covers every volume of the group. A group is admitted while (a) fewer than
+ * max_inflight groups are on the device and (b) a slot of its (shape, size)
+ * is idle or can be allocated within hbm_budget bytes (idle slots of other
+ * kinds are freed, least recently used first, to make room; a group that
+ * still does not fit is halved before it waits). A slot is one device
+ * allocation holding the packed input, the batch workspace and the keypoint
+ * and descriptor buffers of the group; slots and plans are cached per
+ * (shape, size). Groups are spread over n_streams non-blocking streams
+ * (default priority) so that several run on the device at once. A batch
+ * plan gives each volume the same results as a one-volume plan, so every
+ * result is the same alone and among others. The server owns its slots,
+ * plans, streams and thread; the context must outlive it.
  */
 typedef struct sift3d_server sift3d_server;
 
 typedef struct sift3d_server_config {
     size_t hbm_budget;  /* device bytes that slots may occupy in total (> 0)  */
     int n_streams;      /* 1..8                                             */
-    int max_inflight;   /* requests on the device at once, 1..256           */
+    int max_inflight;   /* groups on the device at once, 1..256             */
     int kp_capacity;    /* keypoint and descriptor rows per request, >= 1    */
+    int max_batch;      /* requests per group, 1..64 (1 = no grouping)        */
 } sift3d_server_config;
 
 /* Result of one request; device pointers stay valid until its release. */
@@ -277,15 +282,16 @@ typedef struct sift3d_result {
 
 typedef struct sift3d_server_counters {
     int64_t submitted, completed, failed;
-    int in_flight, pending;
+    int in_flight, pending;                          /* requests */
     size_t allocated, peak_allocated, hbm_budget;   /* slot bytes */
     int64_t slot_allocations, slot_evictions;
+    int64_t groups, grouped_requests;               /* groups launched, requests in them */
 } sift3d_server_counters;
 
 /* Create a server on the current HIP device and start its scheduler thread. */
 int sift3d_server_create(sift3d_ctx *ctx, const sift3d_server_config *cfg, sift3d_server **out);
 
-/* Device bytes of the slot a request of this shape occupies (plans it). */
+/* Device bytes of the slot a lone request of this shape occupies (plans it). */
 int sift3d_server_footprint(sift3d_server *srv, int nx, int ny, int nz, size_t *bytes);
 
 /*

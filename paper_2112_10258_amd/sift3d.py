@@ -50,6 +50,7 @@ class ServerConfig(ctypes.Structure):
         ("n_streams", ctypes.c_int),
         ("max_inflight", ctypes.c_int),
         ("kp_capacity", ctypes.c_int),
+        ("max_batch", ctypes.c_int),
     ]
 
 
@@ -82,6 +83,8 @@ class ServerCounters(ctypes.Structure):
         ("hbm_budget", ctypes.c_size_t),
         ("slot_allocations", ctypes.c_int64),
         ("slot_evictions", ctypes.c_int64),
+        ("groups", ctypes.c_int64),
+        ("grouped_requests", ctypes.c_int64),
     ]
 
 
@@ -389,11 +392,11 @@ class Server:
     volumes as they arrive, poll or wait for results, release their slots."""
 
     def __init__(self, ctx: Context, hbm_budget: int, n_streams: int = 4, max_inflight: int = 8,
-                 kp_capacity: int = 1 << 14):
+                 kp_capacity: int = 1 << 14, max_batch: int = 8):
         lib = _load()
         self.ctx = ctx
         self.capacity = int(kp_capacity)
-        cfg = ServerConfig(int(hbm_budget), int(n_streams), int(max_inflight), int(kp_capacity))
+        cfg = ServerConfig(int(hbm_budget), int(n_streams), int(max_inflight), int(kp_capacity), int(max_batch))
         h = ctypes.c_void_p()
         _check(lib.sift3d_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "sift3d_server_create")
         self.handle = h

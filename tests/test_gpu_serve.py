@@ -50,7 +50,7 @@ def test_server_alone_and_in_the_mix_equal_plain():
     dvols = [torch.from_numpy(v).cuda() for v in vols]
     torch.cuda.synchronize()
     refs = [_plain(ctx, v) for v in vols]
-    srv = S.Server(ctx, hbm_budget=8 << 30, n_streams=4, max_inflight=6, kp_capacity=CAP)
+    srv = S.Server(ctx, hbm_budget=8 << 30, n_streams=4, max_inflight=6, max_batch=8, kp_capacity=CAP)
     try:
         # alone: one request at a time
         alone = []
@@ -131,3 +131,30 @@ def test_server_rejects_oversize_and_cancels_on_close():
     assert srv.stats()["pending"] == 1
     srv.close()
     print("[serve] oversize rejected; waiting request cancelled on close", flush=True)
+
+
+def test_server_groups_waiting_requests_of_one_shape():
+    """With one group in flight, requests that arrive meanwhile wait; the next
+    admission takes the waiting requests of the head's shape as one batch
+    extraction. Every result still equals the plain path's."""
+    import torch
+    import paper_2112_10258_amd as S
+    ctx = _ctx()
+    vols = _vols()
+    order = [0, 0, 1, 0, 5, 0, 1, 0, 0, 2, 0, 1]        # indices into SHAPES (0 and 5 share a shape)
+    dvols = [torch.from_numpy(v).cuda() for v in vols]
+    torch.cuda.synchronize()
+    refs = {i: _plain(ctx, vols[i]) for i in set(order)}
+    srv = S.Server(ctx, hbm_budget=8 << 30, n_streams=2, max_inflight=1, max_batch=4, kp_capacity=CAP)
+    try:
+        tickets = [srv.submit(dvols[i]) for i in order]
+        for t, i in zip(tickets, order):
+            _same(srv.fetch(t), refs[i], f"grouped request of volume {i}")
+        for t in tickets:
+            srv.release(t)
+        st = srv.stats()
+        print(f"[serve] grouping: {len(order)} requests in {st['groups']} groups, stats {st}", flush=True)
+        assert st["completed"] == len(order) and st["grouped_requests"] == len(order)
+        assert st["groups"] < len(order), "no requests were grouped"
+    finally:
+        srv.close()
