@@ -60,7 +60,7 @@ COPY_BYTES = 1 << 30
 def kernel_source_hash():
     """Hash of the pyramid kernel sources and their shared header."""
     h = hashlib.sha256()
-    for f in ("pyramid.hip", "separable.hip", "sift3d_internal.h"):
+    for f in ("pyramid.hip", "pyramid_tall.hip", "pyramid_kernel.h", "separable.hip", "sift3d_internal.h"):
         with open(os.path.join(ROOT, "paper_2112_10258_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -92,12 +92,21 @@ def octave0_grids(shape_xyz):
     return {"xy": tiles * cdiv(nz, planes) * 256, "z": cdiv(nx, 32) * cdiv(ny, 8) * cdiv(nz, 16) * 256}
 
 
-def summarize_pmc(fetch_dir, write_dir, workloads, out_path):
+def summarize_pmc(fetch_dir, write_dir, workloads, out_path, reps):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of two rocprofv3 --pmc runs
-    of this script (with --copy-calibration) -> bytes per octave-0 level pass,
-    scaled by what the same counters read for a 1 GiB device copy."""
+    of this script (with --copy-calibration) -> bytes per octave-0 level pass
+    G_1..G_5, scaled by what the same counters read for a 1 GiB device copy.
+
+    Level i of octave 0 (default parameters: radii 4, 5, 6, 8, 10) runs on the
+    fused pass when the octave has >= 24M voxels, or >= 2M voxels and radius
+    <= 8 (the plan's rule); its dispatches are blur_level_kernel<R, true, *>
+    at the largest grid of that instantiation. Otherwise it is the xy + z
+    pair launched alone, at the octave-0 grids of those kernels. The counter
+    runs use --pmc-passes reps, whose last dispatches are the octave-0 passes
+    launched alone, reps times each."""
     import csv
     import glob
+    import re
 
     def rows(d, counter):
         fs = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
@@ -108,14 +117,13 @@ def summarize_pmc(fetch_dir, write_dir, workloads, out_path):
             for r in csv.DictReader(open(f)):
                 if r.get("Counter_Name") == counter:
                     name = r["Kernel_Name"].replace("void ", "").replace("s3d::(anonymous namespace)::", "")
-                    out.append((name, int(r["Grid_Size"]), float(r["Counter_Value"]),
-                                int(r.get("Dispatch_Id", 0))))
+                    out.append((name, int(r["Grid_Size"]), float(r["Counter_Value"])))
         return out
 
     fr, wr = rows(fetch_dir, "FETCH_SIZE"), rows(write_dir, "WRITE_SIZE")
 
     def copy_kib(rs):
-        c = [v for k, g, v, _ in rs if ("copy" in k.lower() or "elementwise" in k.lower()) and v * 1024 > COPY_BYTES / 2]
+        c = [v for k, g, v in rs if ("copy" in k.lower() or "elementwise" in k.lower()) and v * 1024 > COPY_BYTES / 2]
         if not c:
             raise SystemExit("copy calibration dispatch not found")
         return float(np.median(c))
@@ -124,7 +132,7 @@ def summarize_pmc(fetch_dir, write_dir, workloads, out_path):
     f_factor, w_factor = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
     calib = {"bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
              "fetch_factor": round(f_factor, 4), "write_factor": round(w_factor, 4)}
-    out = {"what": "bytes beyond L2 (TCC FETCH_SIZE + WRITE_SIZE) per octave-0 level pass, "
+    out = {"what": "bytes beyond L2 (TCC FETCH_SIZE + WRITE_SIZE) per octave-0 level pass G_1..G_5, "
                    "scaled by the counters' reading on a plain 1 GiB device copy",
            "kernel_source_sha256_16": kernel_source_hash(), "workloads": {}}
     if os.path.exists(out_path):
@@ -134,33 +142,39 @@ def summarize_pmc(fetch_dir, write_dir, workloads, out_path):
                 out["workloads"] = old.get("workloads", {})
         except ValueError:
             pass
+    fused_re = re.compile(r"^blur_level_kernel<(\d+), (true|false)")
+
+    def fused_sel(rs, R):
+        # the --pmc-passes runs end with the octave-0 passes: the last reps
+        # dispatches of this instantiation
+        ds = [v for k, g, v in rs if (m := fused_re.match(k)) and int(m.group(1)) == R and m.group(2) == "true"]
+        return ds[-reps:]
+
     for wl, shape in workloads.items():
+        n = int(np.prod(shape))
         grids = octave0_grids(shape)
-        res = {}
-        for kname, key in (("blur_level_kernel", None), ("blur_xy_kernel", "xy"), ("blur_z_kernel", "z")):
-            sel_f = [v for k, g, v, _ in fr if k.startswith(kname) and (key is None or g == grids[key])]
-            sel_w = [v for k, g, v, _ in wr if k.startswith(kname) and (key is None or g == grids[key])]
-            if key is None and sel_f:
-                # fused passes: the octave-0 ones are the largest dispatches
-                top = max(g for k, g, _, _ in fr if k.startswith(kname))
-                sel_f = [v for k, g, v, _ in fr if k.startswith(kname) and g == top]
-                sel_w = [v for k, g, v, _ in wr if k.startswith(kname) and g == top]
-            if sel_f and sel_w:
-                res[kname] = {"dispatches": len(sel_f),
-                              "fetch_bytes": float(np.mean(sel_f)) * 1024 * f_factor,
-                              "write_bytes": float(np.mean(sel_w)) * 1024 * w_factor}
-        if "blur_level_kernel" in res:
-            k = res["blur_level_kernel"]
-            tot = k["fetch_bytes"] + k["write_bytes"]
-            kern = "blur_level_kernel"
-        elif "blur_xy_kernel" in res and "blur_z_kernel" in res:
-            tot = sum(res[k]["fetch_bytes"] + res[k]["write_bytes"] for k in ("blur_xy_kernel", "blur_z_kernel"))
-            kern = "blur_xy_kernel + blur_z_kernel"
-        else:
+        levels = []
+        for i, R in enumerate((4, 5, 6, 8, 10), start=1):
+            fused = n >= (24 << 20) or (n >= (2 << 20) and R <= 8)
+            if fused:
+                f, w = fused_sel(fr, R), fused_sel(wr, R)
+                kern = f"blur_level_kernel<{R}>"
+            else:
+                f = [sum(v) for v in zip(*[[v for k, g, v in fr if k.startswith(kn) and g == grids[key]][-reps:]
+                                           for kn, key in (("blur_xy_kernel", "xy"), ("blur_z_kernel", "z"))])]
+                w = [sum(v) for v in zip(*[[v for k, g, v in wr if k.startswith(kn) and g == grids[key]][-reps:]
+                                           for kn, key in (("blur_xy_kernel", "xy"), ("blur_z_kernel", "z"))])]
+                kern = "blur_xy_kernel + blur_z_kernel"
+            if not f or not w:
+                continue
+            levels.append({"level": f"G_{i}", "radius": R, "kernel": kern, "dispatches": len(f),
+                           "fetch_bytes": int(np.mean(f) * 1024 * f_factor),
+                           "write_bytes": int(np.mean(w) * 1024 * w_factor)})
+        if not levels:
             continue
-        out["workloads"][wl] = {"kernel": kern, "shape_xyz": list(shape), "per_kernel": res,
-                                "hbm_bytes_per_launch": int(tot), "copy_calibration": calib,
-                                "fetch_dir": fetch_dir, "write_dir": write_dir}
+        tot = float(np.mean([lv["fetch_bytes"] + lv["write_bytes"] for lv in levels]))
+        out["workloads"][wl] = {"shape_xyz": list(shape), "levels": levels, "hbm_bytes_per_launch": int(tot),
+                                "copy_calibration": calib, "fetch_dir": fetch_dir, "write_dir": write_dir}
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
@@ -379,6 +393,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB on the device a few times (reference dispatch for counter runs)")
+    ap.add_argument("--pmc-passes", type=int, default=0,
+                    help="counter runs: after the warm-up, launch each octave-0 level pass this many times and exit")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit (no GPU)")
     ap.add_argument("--pyramid-mode", type=int, default=None, choices=[0, 1, 2],
@@ -394,7 +410,7 @@ def main():
     if args.summarize_pmc:
         shapes = {"config2": (145, 174, 145), "config4": (512, 512, 384)}
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], {args.workload: shapes[args.workload]},
-                      PMC_SUMMARY)
+                      PMC_SUMMARY, args.pmc_passes or 3)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); volumes are independent, "
@@ -434,6 +450,15 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.pmc_passes:
+        passes = plan.pyramid_passes()
+        for i, p in enumerate(passes):
+            if p[0] == 0 and p[1] > 0:
+                for _ in range(args.pmc_passes):
+                    plan.pyramid_pass(i, dvol, buf.ws, stream)
+        torch.cuda.synchronize()
+        log(f"[bench] octave-0 level passes launched {args.pmc_passes} times each for the counters")
+        return
     count = int(buf.count.item())
     log(f"[bench] {plan.n_octaves} octaves, workspace {plan.workspace_bytes / 2**20:.1f} MiB, {count} keypoints")
 

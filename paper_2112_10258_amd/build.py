@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsift3d.so")
-SOURCES = ["pyramid.hip", "separable.hip", "detect.hip", "describe.hip", "api.cpp", "server.cpp"]
+SOURCES = ["pyramid.hip", "pyramid_tall.hip", "separable.hip", "detect.hip", "describe.hip", "api.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -36,7 +36,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 4, verbose: bool = True) -> str:
+def build(jobs: int = 8, verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(_compile, SOURCES))
@@ -53,7 +53,7 @@ def build(jobs: int = 4, verbose: bool = True) -> str:
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("--jobs", type=int, default=8)
     args = ap.parse_args()
     build(args.jobs)
     sys.exit(0)

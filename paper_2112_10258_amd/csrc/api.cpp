@@ -188,7 +188,7 @@ bool fused_choice(const sift3d_params &p, long long n, int r)
 
 // The fused job of a level-pass task, its depth split into `slabs` slabs
 // (block0 left for the caller).
-DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs)
+DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs, int ty)
 {
     const int S = pl->S;
     DFJob f{};
@@ -203,7 +203,7 @@ DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs)
         f.ny = g.ny;
         f.nz = g.nz;
         f.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
-        f.tiles_y = (g.ny + kBlurTY - 1) / kBlurTY;
+        f.tiles_y = (g.ny + ty - 1) / ty;
         f.L = slab_planes(g.nz, slabs, pl->brief_rb);
         f.slabs = (g.nz + f.L - 1) / f.L;
         f.taps = pl->brief_tapset;
@@ -233,20 +233,23 @@ DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs)
     f.ny = g.ny;
     f.nz = g.nz;
     f.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
-    f.tiles_y = (g.ny + kBlurTY - 1) / kBlurTY;
+    f.tiles_y = (g.ny + ty - 1) / ty;
     f.L = slab_planes(g.nz, slabs, L.r);
     f.slabs = (g.nz + f.L - 1) / f.L;
     f.taps = L.tapset;
     return f;
 }
 
+// Tile height of a fused pass launched alone over one octave.
+int solo_ty(const OctaveGeom &g) { return (long long)g.n >= kBlurTallVoxels ? kBlurTYTall : kBlurTYSmall; }
+
 // Slabs per job for a fused launch over jobs with `tiles` (x, y) tiles in
 // total: enough blocks to fill every resident slot of the device once (CUs x
 // the fused pass's workgroups per CU at this radius, from its registers and
 // LDS), no more.
-int fused_slabs(const sift3d_plan *pl, long long tiles, int r, bool dog)
+int fused_slabs(const sift3d_plan *pl, long long tiles, int r, bool dog, int ty)
 {
-    const int per_cu = std::max(1, fused_blocks_per_cu(r, dog));
+    const int per_cu = std::max(1, fused_blocks_per_cu(r, dog, ty));
     const long long slots = (long long)pl->ctx->n_cu * per_cu;
     return (int)std::max<long long>(1, (slots + tiles - 1) / tiles);
 }
@@ -301,7 +304,7 @@ void build_schedule(sift3d_plan *pl)
     };
     auto emit = [&](int type, const std::vector<int> &ts) {
         if (ts.empty()) return;
-        Step st{type, ts, 0, (int)ts.size(), 0, 0, false};
+        Step st{type, ts, 0, (int)ts.size(), 0, 0, false, 0};
         st.first = type == 1 ? (int)pl->xyjobs.size() : (int)pl->zjobs.size();
         int blocks = 0;
         for (int t : ts) {
@@ -332,15 +335,18 @@ void build_schedule(sift3d_plan *pl)
             const bool dog0 = task_dog(left[0]);
             std::vector<int> grp, rest;
             for (int t : left) (task_r(t) == r0 && task_dog(t) == dog0 ? grp : rest).push_back(t);
+            long long voxels = 0;
+            for (int t : grp) voxels += (long long)task_geom(t).n;
+            const int ty = voxels >= kBlurTallVoxels ? kBlurTYTall : kBlurTYSmall;
             long long tiles = 0;
             for (int t : grp) {
                 const OctaveGeom &g = task_geom(t);
-                tiles += (long long)((g.nx + kBlurTX - 1) / kBlurTX) * ((g.ny + kBlurTY - 1) / kBlurTY);
+                tiles += (long long)((g.nx + kBlurTX - 1) / kBlurTX) * ((g.ny + ty - 1) / ty);
             }
-            const int slabs = fused_slabs(pl, tiles, r0, dog0);
-            Step st{0, grp, (int)pl->fjobs.size(), (int)grp.size(), 0, r0, dog0};
+            const int slabs = fused_slabs(pl, tiles, r0, dog0, ty);
+            Step st{0, grp, (int)pl->fjobs.size(), (int)grp.size(), 0, r0, dog0, ty};
             for (int t : grp) {
-                DFJob f = fused_job(pl, pl->tasks[t], slabs);
+                DFJob f = fused_job(pl, pl->tasks[t], slabs, ty);
                 f.block0 = st.n_blocks;
                 st.n_blocks += f.tiles_x * f.tiles_y * f.slabs;
                 pl->fjobs.push_back(f);
@@ -386,8 +392,9 @@ void build_schedule(sift3d_plan *pl)
         if (is_fused(t)) {
             const BlurLaunch &L = pl->blur[pl->tasks[t].pass];
             const OctaveGeom &g = pl->vols[L.vol].oct[L.octave];
-            const long long tiles = (long long)((g.nx + kBlurTX - 1) / kBlurTX) * ((g.ny + kBlurTY - 1) / kBlurTY);
-            DFJob f = fused_job(pl, pl->tasks[t], fused_slabs(pl, tiles, L.r, L.dog));
+            const int ty = solo_ty(g);
+            const long long tiles = (long long)((g.nx + kBlurTX - 1) / kBlurTX) * ((g.ny + ty - 1) / ty);
+            DFJob f = fused_job(pl, pl->tasks[t], fused_slabs(pl, tiles, L.r, L.dog, ty), ty);
             f.block0 = 0;
             pl->solo_f[t] = (int)pl->fjobs.size();
             pl->fjobs.push_back(f);
@@ -630,7 +637,7 @@ int run_step(const sift3d_plan *plan, const Step &stp, const float *d_in, void *
         a.taps = plan->d_taps;
         if (stp.count <= kInlineJobs)
             for (int j = 0; j < stp.count; ++j) a.inl[j] = plan->fjobs[stp.first + j];
-        e = launch_blur(a, stp.max_r, stp.dog, st);
+        e = launch_blur(a, stp.max_r, stp.dog, stp.ty, st);
     } else if (stp.type == 1) {
         XYLaunch a{};
         a.jobs = plan->d_xy + stp.first;
@@ -863,14 +870,15 @@ int sift3d_pyramid_pass(const sift3d_plan *plan, int pass, const float *d_vol, v
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (L.fused) {
         const DFJob &f = plan->fjobs[plan->solo_f[t]];
-        return run_step(plan, Step{0, {t}, plan->solo_f[t], 1, f.tiles_x * f.tiles_y * f.slabs, L.r, L.dog}, d_vol,
-                        d_ws, st);
+        const int ty = solo_ty(plan->vols[L.vol].oct[L.octave]);
+        return run_step(plan, Step{0, {t}, plan->solo_f[t], 1, f.tiles_x * f.tiles_y * f.slabs, L.r, L.dog, ty},
+                        d_vol, d_ws, st);
     }
     const VolPlan &vp = plan->vols[L.vol];
     const OctaveGeom &g = vp.oct[L.octave];
-    rc = run_step(plan, Step{1, {t}, plan->solo_xy[t], 1, xy_blocks(g), L.r, false}, d_vol, d_ws, st);
+    rc = run_step(plan, Step{1, {t}, plan->solo_xy[t], 1, xy_blocks(g), L.r, false, 0}, d_vol, d_ws, st);
     if (rc != SIFT3D_OK) return rc;
-    return run_step(plan, Step{2, {t}, plan->solo_z[t], 1, z_blocks(g), L.r, false}, d_vol, d_ws, st);
+    return run_step(plan, Step{2, {t}, plan->solo_z[t], 1, z_blocks(g), L.r, false, 0}, d_vol, d_ws, st);
 }
 
 int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_keypoint *d_kp, int kp_capacity,

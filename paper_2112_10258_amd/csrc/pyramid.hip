@@ -5,303 +5,40 @@
 // reading G_{i-1} from HBM once (Section 3.2.2: Gaussian Convolution,
 // Difference-of-Gaussian and Sub-sampling, fused here into one pass).
 //
-// Work decomposition: a workgroup owns a 32 x 16 (x, y) tile and a slab of
-// L output planes in z. It streams the input planes of its slab plus R
-// halo planes on each side through LDS: each plane's (16+2R) x (32+2R)
-// halo tile is staged in LDS (coalesced row loads, clamp-to-edge), blurred
+// Work decomposition: a workgroup owns a 32 x TY (x, y) tile (TY = 16, or
+// 32 for launches over >= 24M voxels) and a slab of L output planes in z.
+// It streams the input planes of its slab plus R halo planes on each side
+// through LDS: each plane's (TY+2R) x (32+2R) halo tile is staged in LDS (coalesced row loads, clamp-to-edge), blurred
 // along x into a second LDS tile, then along y into registers. The z pass
 // keeps the last 2R+1 y-blurred values of each output column in a
 // per-thread register ring. The plane loop is unrolled by 2R+1, so each
 // step writes and reads ring slots that are compile-time constants: the
-// ring stays in fixed registers with no copies between steps.
-#include "sift3d_internal.h"
-
-#include <type_traits>
+// ring stays in fixed registers with no copies between steps. The kernel
+// template is in pyramid_kernel.h; this file holds the 16-row instances and
+// the dispatch, pyramid_tall.hip the 32-row instances.
+#include "pyramid_kernel.h"
 
 namespace s3d {
-namespace {
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+// 32-row instances live in pyramid_tall.hip.
+hipError_t launch_blur_tall(const FusedLaunch &a, int r, bool dog, hipStream_t st);
+int fused_blocks_per_cu_tall(int r, bool dog);
 
-// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
-// b % 8). Remap so that each XCD receives one contiguous range of logical
-// tiles: neighbouring tiles then share their halo rows in that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int bid, int n)
+hipError_t launch_blur(const FusedLaunch &a, int r, bool dog, int ty, hipStream_t st)
 {
-    const int per = n / 8, rem = n % 8;
-    const int xcd = bid % 8, idx = bid / 8;
-    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-}
-
-// One symmetric 1D stencil: sum_t w[t] * at(t), t = 0..2R, with w[t] = w[2R-t].
-// Taps are paired and summed from the outermost inward, so the partial sum
-// stays small until the last (largest) terms: fewer roundings at full
-// magnitude than a straight left-to-right chain, same instruction count.
-template <int R, typename F>
-__device__ __forceinline__ float sym_stencil(const float (&w)[2 * R + 1], F at)
-{
-    if constexpr (R == 0) {
-        return w[0] * at(0);
-    } else {
-        float s = w[0] * (at(0) + at(2 * R));
-#pragma unroll
-        for (int k = 1; k < R; ++k) s = __builtin_fmaf(w[k], at(k) + at(2 * R - k), s);
-        return __builtin_fmaf(w[R], at(R), s);
-    }
-}
-
-// f(std::integral_constant<int, P>) for P = I .. N-1: every P is a
-// compile-time constant inside f, whatever the unroller's size limits.
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for<I + 1, N>(f);
-    }
-}
-
-// Job of a block: the last job whose first block is <= bid (jobs sorted by block0).
-__device__ __forceinline__ int find_fjob(const DFJob *jobs, int n, int bid)
-{
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].block0 <= bid)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
-// INL: the jobs are read from the inline copy in the arguments (small
-// launches), else from the device table.
-template <int R, bool DOG, bool INL>
-__global__ void __launch_bounds__(kBlurThreads) blur_level_kernel(const FusedLaunch fl)
-{
-    constexpr int TX = kBlurTX, TY = kBlurTY, NY = kBlurNY, NT = kBlurThreads;
-    constexpr int M = 2 * R + 1;
-    constexpr int AWL = TX + 2 * R;                 // staged width
-    constexpr int AW = (AWL + 3) & ~3;              // LDS row pitch (16-byte rows)
-    constexpr int AH = TY + 2 * R;                  // staged height
-    constexpr int AE = AH * AWL;
-    constexpr int KL = (AE + NT - 1) / NT;          // staged elements per thread
-    constexpr int XQ = TX / 4;                      // x-pass items per row (4 outputs each)
-    constexpr int XIN = 4 + ((2 * R + 3) & ~3);     // x-pass inputs per item, multiple of 4
-    static_assert(NY == 2, "sub-sampling pairs rows inside a thread");
-    // staging tile plus one dummy slot per unused staging lane (branch-free writes)
-    __shared__ __align__(16) float A[AH * AW + KL * NT - AE];
-    __shared__ __align__(16) float B[AH * TX];
-    // centre values (G_{i-1} at the thread's output voxels) of the last R+1
-    // input planes: private to each thread, kept in LDS because the slot
-    // index is not a compile-time constant
-    __shared__ float C[DOG ? (R + 1) * NY * NT : 1];
-
-    const int tid = threadIdx.x;
-    const int logical = xcd_remap(blockIdx.x, fl.n_blocks);
-    const DFJob jb = INL ? fl.inl[find_fjob(fl.inl, fl.n_jobs, logical)]
-                         : fl.jobs[find_fjob(fl.jobs, fl.n_jobs, logical)];
-    const float *const src = jb.src_input ? fl.in + jb.src : reinterpret_cast<const float *>(fl.ws + jb.src);
-    float *const dst = reinterpret_cast<float *>(fl.ws + jb.dst);
-    float *const dogp = DOG ? reinterpret_cast<float *>(fl.ws + jb.dog) : nullptr;
-    float *const subp = jb.sub < 0 ? nullptr : reinterpret_cast<float *>(fl.ws + jb.sub);
-    const float *const wt = fl.taps + (size_t)jb.taps * kMaxTaps;
-    const int local = logical - jb.block0;
-    const int ntile = jb.tiles_x * jb.tiles_y;
-    const int slab = local / ntile;
-    const int t2 = local - slab * ntile;
-    const int tyi = t2 / jb.tiles_x;
-    const int txi = t2 - tyi * jb.tiles_x;
-    const int x0 = txi * TX, y0 = tyi * TY, z0 = slab * jb.L;
-    const int z1 = min(z0 + jb.L, jb.nz);
-    const int nx = jb.nx, ny = jb.ny, nz = jb.nz;
-    const size_t nxy = (size_t)nx * ny;
-
-    // Per-thread staging slots: the same in-plane offsets for every plane.
-    unsigned goff[KL];
-    int loff[KL];
-#pragma unroll
-    for (int k = 0; k < KL; ++k) {
-        const int idx = tid + k * NT;
-        if (idx < AE) {
-            const int r = idx / AWL, c = idx - r * AWL;
-            goff[k] = (unsigned)(clampi(y0 - R + r, 0, ny - 1) * nx + clampi(x0 - R + c, 0, nx - 1));
-            loff[k] = r * AW + c;
-        } else {
-            goff[k] = 0;
-            loff[k] = AH * AW + (idx - AE);
-        }
-    }
-    float pre[KL];
-    auto load_plane = [&](int zi) {
-        const float *p = src + (size_t)clampi(zi, 0, nz - 1) * nxy;
-#pragma unroll
-        for (int k = 0; k < KL; ++k) pre[k] = p[goff[k]];
-    };
-
-    float w[M];
-#pragma unroll
-    for (int t = 0; t < M; ++t) w[t] = wt[t];
-
-    const int tx = tid % TX;
-    const int tyb = (tid / TX) * NY;
-    const int gx = x0 + tx, gy0 = y0 + tyb;
-    const bool ok0 = gx < nx && gy0 < ny, ok1 = gx < nx && gy0 + 1 < ny;
-    const unsigned o0 = (unsigned)(min(gy0, ny - 1) * nx + min(gx, nx - 1));
-    const unsigned o1 = (unsigned)(min(gy0 + 1, ny - 1) * nx + min(gx, nx - 1));
-    float ring[NY][M];
-#pragma unroll
-    for (int j = 0; j < NY; ++j)
-#pragma unroll
-        for (int t = 0; t < M; ++t) ring[j][t] = 0.f;
-    float subacc = 0.f;
-    int cslot = 0;                                  // C slot of the current step (it mod R+1)
-
-    // Input plane z0 - R + it is staged at step it; output plane z0 + it - 2R
-    // completes at step it. The plane loop is unrolled by the ring length so
-    // that every ring slot is a fixed register.
-    const int nplanes = (z1 - z0) + 2 * R;
-    load_plane(z0 - R);
-    for (int base = 0; base < nplanes; base += M) {
-        static_for<0, M>([&](auto pc) {
-            constexpr int p = decltype(pc)::value;
-            const int it = base + p;
-            if (it >= nplanes) return;
-#pragma unroll
-            for (int k = 0; k < KL; ++k) A[loff[k]] = pre[k];
-            __syncthreads();
-            if (it + 1 < nplanes) load_plane(z0 - R + it + 1);
-            const int oz = z0 + it - 2 * R;
-            float cv0 = 0.f, cv1 = 0.f;
-            if constexpr (DOG) {
-                // D_{i-1} needs G_{i-1} at the output voxel: keep this plane's centre
-                // values, and take those of the plane staged R steps ago (slot cslot+1)
-                const int rslot = cslot == R ? 0 : cslot + 1;
-                C[(cslot * NY + 0) * NT + tid] = A[(R + tyb) * AW + R + tx];
-                C[(cslot * NY + 1) * NT + tid] = A[(R + tyb + 1) * AW + R + tx];
-                if (it >= 2 * R) {
-                    cv0 = C[(rslot * NY + 0) * NT + tid];
-                    cv1 = C[(rslot * NY + 1) * NT + tid];
-                }
-                cslot = rslot;
-            }
-
-            // x pass: 4 consecutive outputs per item from one LDS strip
-            for (int item = tid; item < AH * XQ; item += NT) {
-                const int r = item / XQ, xb = (item - r * XQ) * 4;
-                float in[XIN];
-                const float4 *s4 = reinterpret_cast<const float4 *>(&A[r * AW + xb]);
-#pragma unroll
-                for (int q = 0; q < XIN / 4; ++q) {
-                    const float4 v = s4[q];
-                    in[4 * q + 0] = v.x;
-                    in[4 * q + 1] = v.y;
-                    in[4 * q + 2] = v.z;
-                    in[4 * q + 3] = v.w;
-                }
-                float o[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) o[q] = sym_stencil<R>(w, [&](int t) { return in[q + t]; });
-                *reinterpret_cast<float4 *>(&B[r * TX + xb]) = make_float4(o[0], o[1], o[2], o[3]);
-            }
-            __syncthreads();
-
-            // y pass: NY consecutive outputs of column tx, into ring slot p
-            {
-                float col[NY + 2 * R];
-#pragma unroll
-                for (int q = 0; q < NY + 2 * R; ++q) col[q] = B[(tyb + q) * TX + tx];
-#pragma unroll
-                for (int j = 0; j < NY; ++j) ring[j][p] = sym_stencil<R>(w, [&](int t) { return col[j + t]; });
-            }
-
-            if (it >= 2 * R) {
-                // z pass: slot (p + 1 + t) % M holds input plane (it - 2R + t)
-                float zo[NY];
-#pragma unroll
-                for (int j = 0; j < NY; ++j)
-                    zo[j] = sym_stencil<R>(w, [&](int t) { return ring[j][(p + 1 + t) % M]; });
-                float *d = dst + (size_t)oz * nxy;
-                if (ok0) d[o0] = zo[0];
-                if (ok1) d[o1] = zo[1];
-                if constexpr (DOG) {
-                    float *e = dogp + (size_t)oz * nxy;
-                    if (ok0) e[o0] = cv0 - zo[0];
-                    if (ok1) e[o1] = cv1 - zo[1];
-                }
-                if (subp != nullptr) {
-                    const float s2 = zo[0] + zo[1];
-                    const float s4 = s2 + __shfl_xor(s2, 1);
-                    if ((oz & 1) == 0) {
-                        subacc = s4;
-                    } else {
-                        const int X = gx >> 1, Y = gy0 >> 1, Z = oz >> 1;
-                        if ((tx & 1) == 0 && X < jb.mx && Y < jb.my && Z < jb.mz)
-                            subp[((size_t)Z * jb.my + Y) * jb.mx + X] = (subacc + s4) * 0.125f;
-                    }
-                }
-            }
-        });
-    }
-}
-
-template <int R>
-hipError_t launch_r(const FusedLaunch &a, bool dog, hipStream_t st)
-{
-    const dim3 g(a.n_blocks), b(kBlurThreads);
-    const bool inl = a.n_jobs <= kInlineJobs;
-    if (dog && inl)
-        hipLaunchKernelGGL((blur_level_kernel<R, true, true>), g, b, 0, st, a);
-    else if (dog)
-        hipLaunchKernelGGL((blur_level_kernel<R, true, false>), g, b, 0, st, a);
-    else if (inl)
-        hipLaunchKernelGGL((blur_level_kernel<R, false, true>), g, b, 0, st, a);
-    else
-        hipLaunchKernelGGL((blur_level_kernel<R, false, false>), g, b, 0, st, a);
-    return hipGetLastError();
-}
-
-}  // namespace
-
-hipError_t launch_blur(const FusedLaunch &a, int r, bool dog, hipStream_t st)
-{
-    static_assert(kMaxFusedR == 10, "one case per fused radius");
     if (a.n_blocks <= 0) return hipSuccess;
-    switch (r) {
-    case 0: return launch_r<0>(a, dog, st);
-    case 1: return launch_r<1>(a, dog, st);
-    case 2: return launch_r<2>(a, dog, st);
-    case 3: return launch_r<3>(a, dog, st);
-    case 4: return launch_r<4>(a, dog, st);
-    case 5: return launch_r<5>(a, dog, st);
-    case 6: return launch_r<6>(a, dog, st);
-    case 7: return launch_r<7>(a, dog, st);
-    case 8: return launch_r<8>(a, dog, st);
-    case 9: return launch_r<9>(a, dog, st);
-    case 10: return launch_r<10>(a, dog, st);
-    default: return hipErrorInvalidValue;
-    }
+    if (ty == kBlurTYTall) return launch_blur_tall(a, r, dog, st);
+    if (ty == kBlurTYSmall) return fused::launch_ty<kBlurTYSmall>(a, r, dog, st);
+    return hipErrorInvalidValue;
 }
 
-// Workgroups of the fused pass at radius r that one CU holds at once
-// (registers and LDS), 0 on error.
-int fused_blocks_per_cu(int r, bool dog)
+// Workgroups of the fused pass at radius r and tile height ty that one CU
+// holds at once (registers and LDS), 0 on error.
+int fused_blocks_per_cu(int r, bool dog, int ty)
 {
-    int n = 0;
-    hipError_t e = hipErrorInvalidValue;
-#define S3D_OCC(R)                                                                                               \
-    case R:                                                                                                      \
-        e = dog ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, true, true>, kBlurThreads, 0) \
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, false, true>, kBlurThreads, 0); \
-        break;
-    switch (r) {
-        S3D_OCC(0) S3D_OCC(1) S3D_OCC(2) S3D_OCC(3) S3D_OCC(4) S3D_OCC(5) S3D_OCC(6) S3D_OCC(7) S3D_OCC(8)
-        S3D_OCC(9) S3D_OCC(10)
-    default: break;
-    }
-#undef S3D_OCC
-    return e == hipSuccess ? n : 0;
+    if (ty == kBlurTYTall) return fused_blocks_per_cu_tall(r, dog);
+    if (ty == kBlurTYSmall) return fused::occupancy_ty<kBlurTYSmall>(r, dog);
+    return 0;
 }
 
 }  // namespace s3d

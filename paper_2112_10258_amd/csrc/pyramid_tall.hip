@@ -1,0 +1,13 @@
+// 32-row instances of the fused scale-space pass (kernel in pyramid_kernel.h).
+#include "pyramid_kernel.h"
+
+namespace s3d {
+
+hipError_t launch_blur_tall(const FusedLaunch &a, int r, bool dog, hipStream_t st)
+{
+    return fused::launch_ty<kBlurTYTall>(a, r, dog, st);
+}
+
+int fused_blocks_per_cu_tall(int r, bool dog) { return fused::occupancy_ty<kBlurTYTall>(r, dog); }
+
+}  // namespace s3d

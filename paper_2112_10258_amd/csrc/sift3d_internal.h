@@ -32,9 +32,12 @@ constexpr int kMaxVolumes = 4096;
 
 // Fused blur pass geometry (shared by host planning and the kernel).
 constexpr int kBlurTX = 32;                 // tile width in x (one output column per lane)
-constexpr int kBlurTY = 16;                 // tile height in y
 constexpr int kBlurNY = 2;                  // consecutive y outputs per thread
-constexpr int kBlurThreads = kBlurTX * kBlurTY / kBlurNY;
+// Tile height: 32 rows for launches over >= kBlurTallVoxels voxels (less
+// halo staging and x-pass work per output), 16 rows below (more blocks).
+constexpr int kBlurTYSmall = 16, kBlurTYTall = 32;
+constexpr long long kBlurTallVoxels = 24LL << 20;
+constexpr int blur_threads(int ty) { return kBlurTX * ty / kBlurNY; }
 
 // Two-launch (xy, then z) level geometry.
 constexpr int kXYTX = 64;                   // xy tile width (one wavefront per row)
@@ -241,6 +244,7 @@ struct Step {
     std::vector<int> tasks;
     int first, count, n_blocks, max_r;
     bool dog;             // fused launches: jobs write a DoG level
+    int ty;               // fused launches: tile height
 };
 
 struct VolPlan {
@@ -299,8 +303,8 @@ struct sift3d_plan {
 
 namespace s3d {
 // Launchers (return hipError_t of the launch).
-hipError_t launch_blur(const FusedLaunch &a, int r, bool dog, hipStream_t st);
-int fused_blocks_per_cu(int r, bool dog);
+hipError_t launch_blur(const FusedLaunch &a, int r, bool dog, int ty, hipStream_t st);
+int fused_blocks_per_cu(int r, bool dog, int ty);
 hipError_t launch_blur_xy(const XYLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_blur_z(const ZLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_detect(const DetLaunch &a, hipStream_t st);
