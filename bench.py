@@ -116,7 +116,8 @@ def summarize_pmc(fetch_dir, write_dir, workloads, out_path, reps):
         for f in fs:
             for r in csv.DictReader(open(f)):
                 if r.get("Counter_Name") == counter:
-                    name = r["Kernel_Name"].replace("void ", "").replace("s3d::(anonymous namespace)::", "")
+                    name = (r["Kernel_Name"].replace("void ", "").replace("s3d::(anonymous namespace)::", "")
+                            .replace("s3d::fused::", ""))
                     out.append((name, int(r["Grid_Size"]), float(r["Counter_Value"])))
         return out
 
