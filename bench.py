@@ -182,6 +182,61 @@ def summarize_pmc(fetch_dir, write_dir, workloads, out_path, reps):
     print(json.dumps(out, indent=1))
 
 
+def octave0_roofline(plan, passes, pass_ms, workload):
+    """Roofline of the octave-0 level passes G_1..G_{S+2} (blur + DoG +
+    sub-sample): algorithmic bytes per pass over its measured duration."""
+    sel = [i for i, p in enumerate(passes) if p[0] == 0 and p[1] > 0]
+    fused_lv = [f"G_{passes[i][1]}" for i in sel if passes[i][5]]
+    split_lv = [f"G_{passes[i][1]}" for i in sel if not passes[i][5]]
+    kparts = []
+    if fused_lv:
+        kparts.append("blur_level_kernel (" + ", ".join(fused_lv) + ")")
+    if split_lv:
+        kparts.append("blur_xy_kernel + blur_z_kernel (" + ", ".join(split_lv) + ")")
+    bytes_per_launch = sum(passes[i][4] for i in sel) / len(sel)
+    dur_ms = sum(pass_ms[i] for i in sel) / len(sel)
+    achieved = bytes_per_launch / (dur_ms * 1e-3) / 1e9
+    return {
+        "kernel": " + ".join(kparts) + ": octave-0 pyramid level passes (blur + DoG + sub-sample)",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": read_traffic(workload),
+        "bytes_per_launch": int(bytes_per_launch),
+        "avg_launch_us": round(dur_ms * 1e3, 3),
+    }
+
+
+def large_volume_roofline(stream, reps):
+    """The same roofline on the 512x512x384 volume (config 4), whose levels
+    do not fit the last-level cache: the fused pass against HBM."""
+    import torch
+
+    import paper_2112_10258_amd as S
+    from gen import phantoms as P
+    vol = P.config4()
+    nz, ny, nx = vol.shape
+    ctx = S.Context(S.default_params(), P.pair_draws())
+    plan = S.Plan(ctx, (nx, ny, nz), 1 << 17)
+    buf = S.Buffers(plan)
+    dvol = torch.from_numpy(vol).cuda()
+    for _ in range(2):
+        S.run_extract(plan, dvol, buf, stream=stream)
+    torch.cuda.synchronize()
+    ms = time_calls(lambda: S.run_extract(plan, dvol, buf, stream=stream), 3, stream)
+    passes = plan.pyramid_passes()
+    pass_ms = [time_calls(lambda i=i: plan.pyramid_pass(i, dvol, buf.ws, stream), reps, stream)
+               if p[0] == 0 else 0.0 for i, p in enumerate(passes)]
+    out = octave0_roofline(plan, passes, pass_ms, "config4")
+    out["workload"] = "config4: 512x512x384 smoothed noise + 4000 blobs"
+    out["ms_per_extraction"] = round(ms, 4)
+    del buf, plan, dvol
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_vs_plain(steps, stream, extra):
     """32 mixed-size volumes (each axis U{96..192}): one batch-plan call per step
     against 32 one-volume calls per step. Inputs resident in HBM."""
@@ -392,6 +447,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--no-large", action="store_true", help="skip the 512x512x384 roofline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB on the device a few times (reference dispatch for counter runs)")
     ap.add_argument("--pmc-passes", type=int, default=0,
@@ -489,34 +545,16 @@ def main():
     for (o, lev, r, sub, b, fused, vv), t in zip(passes, pass_ms):
         log(f"[bench]   pass o={o} G{lev} r={r} sub={sub}: {t * 1e3:.2f} us, {b / t / 1e6:.0f} GB/s algorithmic")
 
-    # roofline of the blur/DoG pass: octave-0 incremental passes (G_1..G_{S+2})
-    sel = [i for i, p in enumerate(passes) if p[0] == 0 and p[1] > 0]
-    fused_lv = [f"G_{passes[i][1]}" for i in sel if passes[i][5]]
-    split_lv = [f"G_{passes[i][1]}" for i in sel if not passes[i][5]]
-    kparts = []
-    if fused_lv:
-        kparts.append("blur_level_kernel (" + ", ".join(fused_lv) + ")")
-    if split_lv:
-        kparts.append("blur_xy_kernel + blur_z_kernel (" + ", ".join(split_lv) + ")")
-    bytes_per_launch = sum(passes[i][4] for i in sel) / len(sel)
-    dur_ms = sum(pass_ms[i] for i in sel) / len(sel)
-    achieved = bytes_per_launch / (dur_ms * 1e-3) / 1e9
-    traffic = read_traffic(args.workload)
-    roofline = {
-        "kernel": " + ".join(kparts) + ": octave-0 pyramid level passes (blur + DoG + sub-sample)",
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
-        "bytes_per_launch": int(bytes_per_launch),
-        "avg_launch_us": round(dur_ms * 1e3, 3),
-    }
+    roofline = octave0_roofline(plan, passes, pass_ms, args.workload)
+    large = None
+    if not args.no_large and args.workload != "config4":
+        del buf
+        torch.cuda.empty_cache()
+        large = large_volume_roofline(stream, max(3, reps // 4))
+        log(f"[bench] roofline 512x512x384: {large}")
 
     batch = None
     if not args.no_batch:
-        del buf
         torch.cuda.empty_cache()
         batch = batch_vs_plain(args.batch_steps, stream, extra)
         log(f"[bench] batch: {batch}")
@@ -556,6 +594,7 @@ def main():
         "stages_ms": {"pyramid": round(st_pyr, 4), "detect": round(st_det, 4), "siftrank": round(st_sr, 4),
                       "brief_rrief": round(st_br, 4)},
         "roofline": roofline,
+        "roofline_large_volume": large,
         "batch": batch,
         "serve": serve,
         "cpu_baseline": cpu,
