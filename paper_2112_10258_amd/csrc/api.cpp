@@ -549,7 +549,7 @@ int make_plan(sift3d_ctx *ctx, int n, const int *dims, int kp_capacity, sift3d_p
             u.nz = g.nz;
             u.octave = o;
             u.vol = v;
-            u.words = (g.nx + 63) / 64;
+            u.words = (g.nx - 2 + kDTXOut - 1) / kDTXOut;   // interior x 1..nx-2, 62 per word
             u.tiles_x = u.words;
             u.tiles_y = (g.ny - 2 + kDTY - 1) / kDTY;  // interior rows 1..ny-2
             u.tiles_z = (g.nz - 2 + kDTZ - 1) / kDTZ;  // interior planes 1..nz-2

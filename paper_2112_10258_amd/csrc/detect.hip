@@ -268,28 +268,31 @@ __global__ void __launch_bounds__(kScanThreads) detect_scan_kernel(const DetLaun
 // is the max over the 3x3x3 blocks of D_{s-1} and D_{s+1}, the 3x3 (x, y)
 // blocks of D_s at z-1 and z+1, and the 8-voxel ring of D_s at z.
 //
-// One wavefront owns 64 consecutive x of one y row and streams z through a
-// slab: per plane and level it loads rows y-1, y, y+1 (coalesced), takes x
-// neighbours from the adjacent lanes (the two edge lanes load theirs), and
-// keeps 3x3 max/min of the last three planes in registers. The next plane is
-// loaded before the current one is reduced. No LDS, no barriers. Ballots of
-// the flags are the 64-bit words of the per-row keypoint bit masks.
+// One wavefront loads 64 consecutive x (lanes 0 and 63 are halo, lanes
+// 1..62 produce) of one y row and streams z through a slab: per plane and
+// level it loads rows y-1, y, y+1 (coalesced), takes x neighbours from the
+// adjacent lanes with DPP whole-wave shifts, and keeps 3x3 max/min of the
+// last three planes in registers. The next plane is loaded before the
+// current one is reduced. No LDS, no barriers. Ballots of the flags are
+// the 64-bit words of the per-row keypoint bit masks (bit l of word t is
+// x = 62 t + l).
 template <int NL>
 __device__ __forceinline__ void load_plane_rows(const float *D, long long lstride, int nx, int ny, int pz, int x,
-                                                int xe, int y, float (&v)[NL][3], float (&e)[NL][3])
+                                                int y, float (&v)[NL][3])
 {
     const long long nxy = (long long)nx * ny;
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
         const float *pl = D + lstride * l + pz * nxy;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const float *row = pl + (long long)min(max(y - 1 + r, 0), ny - 1) * nx;
-            v[l][r] = row[x];
-            e[l][r] = row[xe];
-        }
+        for (int r = 0; r < 3; ++r) v[l][r] = pl[(long long)min(max(y - 1 + r, 0), ny - 1) * nx + x];
     }
 }
+
+// Value of the lane to the left / right (whole-wave DPP shift; the edge
+// lanes get their own value, they are halo).
+__device__ __forceinline__ float from_left(float v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ float from_right(float v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false); }
 
 template <int S, bool INL>
 __global__ void __launch_bounds__(256) detect_tile_kernel(const DetLaunch a)
@@ -305,13 +308,12 @@ __global__ void __launch_bounds__(256) detect_tile_kernel(const DetLaunch a)
     const int tyi = rest % un.tiles_y, tzi = rest / un.tiles_y;
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
     const int nx = un.nx, ny = un.ny, nz = un.nz;
-    const int x0 = txi * kDTX, y = 1 + tyi * kDTY + wy, z0 = 1 + tzi * kDTZ;
+    const int xl = txi * kDTXOut + lane;             // this lane's column
+    const int y = 1 + tyi * kDTY + wy, z0 = 1 + tzi * kDTZ;
     if (y > ny - 2) return;                          // whole wavefront: no row here
     const int z1 = min(z0 + kDTZ, nz - 1);           // outputs z0 .. z1-1 (interior)
-    const int x = min(x0 + lane, nx - 1);
-    // lane 0 fetches x0-1, lane 63 fetches x0+64 (clamped); others a duplicate
-    const int xe = lane == 0 ? max(x0 - 1, 0) : min(x0 + 64, nx - 1);
-    const bool in_x = x0 + lane >= 1 && x0 + lane <= nx - 2;
+    const int x = min(xl, nx - 1);
+    const bool in_x = lane >= 1 && lane <= kDTXOut && xl <= nx - 2;
 
     float M[NL][3], m[NL][3];
     float cen[S + 1][2], rx[S + 1][2], rn[S + 1][2];   // [.][0] previous plane, [.][1] current
@@ -322,20 +324,18 @@ __global__ void __launch_bounds__(256) detect_tile_kernel(const DetLaunch a)
 #pragma unroll
     for (int l = 0; l <= S; ++l) cen[l][0] = cen[l][1] = rx[l][0] = rx[l][1] = rn[l][0] = rn[l][1] = 0.f;
 
-    float v[NL][3], e[NL][3], vn[NL][3], en[NL][3];
-    load_plane_rows<NL>(D, un.lstride, nx, ny, z0 - 1, x, xe, y, v, e);
+    float v[NL][3], vn[NL][3];
+    load_plane_rows<NL>(D, un.lstride, nx, ny, z0 - 1, x, y, v);
     const int nplanes = (z1 - z0) + 2;
     for (int k = 0; k < nplanes; ++k) {
-        if (k + 1 < nplanes) load_plane_rows<NL>(D, un.lstride, nx, ny, z0 + k, x, xe, y, vn, en);
+        if (k + 1 < nplanes) load_plane_rows<NL>(D, un.lstride, nx, ny, z0 + k, x, y, vn);
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
             float hx[3], hn[3], left1 = 0.f, right1 = 0.f;
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                float left = __shfl_up(v[l][r], 1);
-                float right = __shfl_down(v[l][r], 1);
-                if (lane == 0) left = e[l][r];
-                if (lane == 63) right = e[l][r];
+                const float left = from_left(v[l][r]);
+                const float right = from_right(v[l][r]);
                 hx[r] = fmaxf(fmaxf(left, right), v[l][r]);
                 hn[r] = fminf(fminf(left, right), v[l][r]);
                 if (r == 1) {
@@ -381,10 +381,7 @@ __global__ void __launch_bounds__(256) detect_tile_kernel(const DetLaunch a)
 #pragma unroll
         for (int l = 0; l < NL; ++l)
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                v[l][r] = vn[l][r];
-                e[l][r] = en[l][r];
-            }
+            for (int r = 0; r < 3; ++r) v[l][r] = vn[l][r];
     }
 }
 
@@ -448,7 +445,7 @@ __global__ void __launch_bounds__(kRowBlock) emit_rows_kernel(const DetLaunch a)
     for (int q = 0; q < un.words && idx < a.cap; ++q) {
         unsigned long long w = mw[q];
         while (w != 0ull && idx < a.cap) {
-            const int x = 64 * q + (__ffsll((long long)w) - 1);
+            const int x = kDTXOut * q + (__ffsll((long long)w) - 1);
             w &= w - 1ull;
             const long long vi = (long long)rp.z * nxy + (long long)rp.y * un.nx + x;
             const float v = Ds[vi];

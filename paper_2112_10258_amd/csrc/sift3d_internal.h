@@ -59,9 +59,10 @@ constexpr int kDetThreads = 256;            // 4 waves
 constexpr int kDetRowsPerWave = 4;
 constexpr int kDetRowsPerBlock = (kDetThreads / 64) * kDetRowsPerWave;
 constexpr int kScanThreads = 1024;
-// Strict-extremum path (votes == 80): one wavefront per (64 x, one y row,
-// kDTZ planes); 4 wavefronts (4 consecutive y rows) per block.
-constexpr int kDTX = 64, kDTY = 4, kDTZ = 16;
+// Strict-extremum path (votes == 80): one wavefront per (62 output x plus
+// a halo lane on each side, one y row, kDTZ planes); 4 wavefronts (4
+// consecutive y rows) per block. Mask word t of a row covers x = 62 t + bit.
+constexpr int kDTXOut = 62, kDTY = 4, kDTZ = 16;
 constexpr int kRowBlock = 256;              // rows per count / emit block; volumes start on a block
 
 // ---------------------------------------------------------------- device tables
