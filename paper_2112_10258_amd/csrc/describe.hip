@@ -123,7 +123,7 @@ __device__ __forceinline__ int first_of_block(int b, long long base, int grid)
 // voxel equals the pre-blur stencil evaluated there). Thread i owns pair i:
 // d_i = B_s(p1) - B_s(p2) is the exact double difference of the two samples,
 // its bit comes from a ballot and its rank from a bitonic sort of the
-// (d_i, i) pairs in LDS.
+// (d_i, i) pairs (wavefront shuffles, LDS for the cross-wavefront stages).
 template <bool INL>
 __global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLaunch a)
 {
@@ -238,32 +238,38 @@ __global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLau
         if (do_br && a.rrief != nullptr) {
             // rank of d_i among the n: #{j : d_j < d_i or (d_j == d_i and j < i)},
             // i.e. the position of (d_i, i) in ascending lexicographic order, by a
-            // bitonic sort of the (difference, index) pairs (n padded to 256 with
-            // +inf keys, which sort after every finite difference)
-            sk[tid] = tid < n ? d : __builtin_inf();
-            si[tid] = tid;
-            __syncthreads();
+            // bitonic sort of the (difference, index) pairs held one per thread
+            // (n padded to 256 with +inf keys, which sort after every finite
+            // difference). Partners within a wavefront exchange by shuffles;
+            // only the stages with partners 64 or 128 threads away go through LDS.
+            double key = tid < n ? d : __builtin_inf();
+            int idx = tid;
 #pragma unroll 1
             for (int kk2 = 2; kk2 <= kMaxPairs; kk2 <<= 1) {
 #pragma unroll 1
                 for (int j = kk2 >> 1; j > 0; j >>= 1) {
-                    const int p = tid ^ j;
-                    if (p > tid) {
-                        const double ka = sk[tid], kb = sk[p];
-                        const int ia = si[tid], ib = si[p];
-                        const bool gt = ka > kb || (ka == kb && ia > ib);
-                        if (gt == ((tid & kk2) == 0)) {
-                            sk[tid] = kb;
-                            sk[p] = ka;
-                            si[tid] = ib;
-                            si[p] = ia;
-                        }
+                    double pk;
+                    int pi;
+                    if (j >= 64) {
+                        sk[tid] = key;
+                        si[tid] = idx;
+                        __syncthreads();
+                        pk = sk[tid ^ j];
+                        pi = si[tid ^ j];
+                        __syncthreads();
+                    } else {
+                        pk = __shfl_xor(key, j);
+                        pi = __shfl_xor(idx, j);
                     }
-                    __syncthreads();
+                    const bool gt = key > pk || (key == pk && idx > pi);
+                    const bool up = (tid & kk2) == 0, lower = (tid & j) == 0;
+                    if (lower == up ? gt : !gt) {
+                        key = pk;
+                        idx = pi;
+                    }
                 }
             }
-            const int i = si[tid];
-            if (i < n) a.rrief[k * n + i] = (uint8_t)tid;
+            if (idx < n) a.rrief[k * n + idx] = (uint8_t)tid;
         }
         __syncthreads();
     }
