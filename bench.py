@@ -186,13 +186,12 @@ def octave0_roofline(plan, passes, pass_ms, workload):
     """Roofline of the octave-0 level passes G_1..G_{S+2} (blur + DoG +
     sub-sample): algorithmic bytes per pass over its measured duration."""
     sel = [i for i, p in enumerate(passes) if p[0] == 0 and p[1] > 0]
-    fused_lv = [f"G_{passes[i][1]}" for i in sel if passes[i][5]]
-    split_lv = [f"G_{passes[i][1]}" for i in sel if not passes[i][5]]
+    names = {1: "blur_level_kernel", 2: "blur_compact_kernel", 0: "blur_xy_kernel + blur_z_kernel"}
     kparts = []
-    if fused_lv:
-        kparts.append("blur_level_kernel (" + ", ".join(fused_lv) + ")")
-    if split_lv:
-        kparts.append("blur_xy_kernel + blur_z_kernel (" + ", ".join(split_lv) + ")")
+    for path in (1, 2, 0):
+        lv = [f"G_{passes[i][1]}" for i in sel if passes[i][5] == path]
+        if lv:
+            kparts.append(names[path] + " (" + ", ".join(lv) + ")")
     bytes_per_launch = sum(passes[i][4] for i in sel) / len(sel)
     dur_ms = sum(pass_ms[i] for i in sel) / len(sel)
     achieved = bytes_per_launch / (dur_ms * 1e-3) / 1e9
@@ -454,8 +453,8 @@ def main():
                     help="counter runs: after the warm-up, launch each octave-0 level pass this many times and exit")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit (no GPU)")
-    ap.add_argument("--pyramid-mode", type=int, default=None, choices=[0, 1, 2],
-                    help="0 = by octave size, 1 = fused streaming passes, 2 = xy + z launches")
+    ap.add_argument("--pyramid-mode", type=int, default=None, choices=[0, 1, 2, 3],
+                    help="0 = by octave size, 1 = fused streaming passes, 2 = xy + z launches, 3 = compact passes")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-pool", type=int, default=4)

@@ -59,11 +59,13 @@ typedef struct sift3d_params {
     double siftrank_factor; /* [2.0] SIFT-Rank half-width R = ceil(f * sigma_s), R <= 7 */
     int pyramid_mode;       /* [0] 0 = by size (fused streaming pass for octaves of
                                >= 24M voxels, and for levels of radius <= 8 in
-                               octaves of >= 2M voxels; xy + z launches for the
-                               rest), 1 = always
-                               fused, 2 = always xy + z; results agree to rounding.
-                               Levels whose tap radius exceeds 10 always run as
-                               xy + z launches */
+                               octaves of >= 2M voxels; compact one-launch pass
+                               below 2M voxels, for radii <= 8 only from 1M
+                               voxels on; xy + z launches for the rest),
+                               1 = always fused, 2 = always xy + z, 3 = always
+                               compact; results agree to rounding. Levels whose
+                               tap radius exceeds 10 always run as xy + z
+                               launches */
 } sift3d_params;
 
 /*
@@ -173,7 +175,7 @@ int sift3d_build_pyramid(const sift3d_plan *plan, const float *d_vol, void *d_ws
                          void *stream);
 
 /*
- * The pyramid is built by sift3d_pyramid_pass_count() fused passes, run in
+ * The pyramid is built by sift3d_pyramid_pass_count() level passes, run in
  * index order; sift3d_build_pyramid() runs them all. Pass i reads one level
  * once and writes G_level of `octave`, D_{level-1} (level > 0) and, for
  * level S of a non-final octave, G_0 of the next octave. Exposed so that a
@@ -181,9 +183,9 @@ int sift3d_build_pyramid(const sift3d_plan *plan, const float *d_vol, void *d_ws
  * passes' inputs (pass 0 reads d_vol). The passes do not write the BRIEF
  * pre-blurred levels; sift3d_build_pyramid does.
  *   info[0] = octave, info[1] = level, info[2] = tap radius, info[3] = 1 if
- *   the pass also writes the next octave's G_0, info[4] = 1 if it is one
- *   fused streaming launch, 0 if an xy launch followed by a z launch,
- *   info[5] = volume;
+ *   the pass also writes the next octave's G_0, info[4] = how it runs: 1 =
+ *   one fused streaming launch, 2 = one compact launch, 0 = an xy launch
+ *   followed by a z launch; info[5] = volume;
  *   *bytes = algorithmic HBM bytes of the pass: 4 per voxel read, 4 per
  *   voxel written for G and D, 4 per sub-sampled voxel.
  */

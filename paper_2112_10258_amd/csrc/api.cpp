@@ -53,7 +53,7 @@ int check_params(const sift3d_params *p)
     if (!(p->dog_threshold >= 0.0f) || p->votes < 1 || p->votes > 80) return SIFT3D_E_ARG;
     if (p->brief_n < 0 || p->brief_n > kMaxPairs || p->brief_n % 64 != 0) return SIFT3D_E_ARG;
     if (p->brief_blur < 0.0 || !(p->siftrank_factor > 0.0)) return SIFT3D_E_ARG;
-    if (p->pyramid_mode < 0 || p->pyramid_mode > 2) return SIFT3D_E_ARG;
+    if (p->pyramid_mode < 0 || p->pyramid_mode > 3) return SIFT3D_E_ARG;
     // kernel limits
     const double top = scale_sigma(*p, p->scales + 2);
     const double prev = scale_sigma(*p, p->scales + 1);
@@ -111,6 +111,11 @@ int xy_blocks(const OctaveGeom &g)
 int z_blocks(const OctaveGeom &g)
 {
     return ((g.nx + 31) / 32) * ((g.ny + 7) / 8) * ((g.nz + kZPlanes - 1) / kZPlanes);
+}
+
+int compact_blocks(const OctaveGeom &g)
+{
+    return ((g.nx + kCTX - 1) / kCTX) * ((g.ny + kCTY - 1) / kCTY) * ((g.nz + kCTZ - 1) / kCTZ);
 }
 
 size_t level_off(const OctaveGeom &g, int lev) { return g.base + (size_t)lev * g.level_bytes; }
@@ -177,13 +182,69 @@ void task_jobs(const sift3d_plan *pl, const Task &k, DXYJob &xy, DZJob &z)
     z.gz = (g->nz + kZPlanes - 1) / kZPlanes;
 }
 
-// Whether a level of an octave of n voxels blurred with radius r runs on
-// the fused pass (compiled for radii up to kMaxFusedR; larger ones run split).
-bool fused_choice(const sift3d_params &p, long long n, int r)
+// How a level of an octave of n voxels blurred with radius r runs. The
+// fused and compact passes are compiled for radii up to 10; larger radii
+// always run split.
+int level_path(const sift3d_params &p, long long n, int r)
 {
-    if (r > kMaxFusedR || p.pyramid_mode == 2) return false;
-    if (p.pyramid_mode == 1) return true;
-    return n >= kFusedMinVoxels || (n >= kFusedMidVoxels && r <= kFusedMidMaxR);
+    switch (p.pyramid_mode) {
+    case 1: return r <= kMaxFusedR ? kPathFused : kPathSplit;
+    case 2: return kPathSplit;
+    case 3: return r <= kCompactMaxR ? kPathCompact : kPathSplit;
+    default: break;
+    }
+    if (n >= kFusedMinVoxels) return r <= kMaxFusedR ? kPathFused : kPathSplit;
+    if (n >= kFusedMidVoxels) return r <= kFusedMidMaxR ? kPathFused : kPathSplit;
+    if (n >= kCompactWideVoxels && r > kFusedMidMaxR) return kPathSplit;
+    return r <= kCompactMaxR ? kPathCompact : kPathSplit;
+}
+
+// The compact job of a task (block0 left for the caller).
+DCJob compact_job(const sift3d_plan *pl, const Task &k)
+{
+    const int S = pl->S;
+    DCJob c{};
+    const OctaveGeom *g;
+    if (k.kind == 1) {
+        // BRIEF pre-blur: G_s -> B_s, no DoG, no sub-sample
+        g = &pl->vols[k.vol].oct[k.octave];
+        c.src = (long long)level_off(*g, lev_G(k.s));
+        c.dst = (long long)level_off(*g, lev_B(S, k.s));
+        c.dog = -1;
+        c.sub = -1;
+        c.r = pl->brief_rb;
+        c.taps = pl->brief_tapset;
+    } else {
+        const BlurLaunch &L = pl->blur[k.pass];
+        const VolPlan &vp = pl->vols[L.vol];
+        g = &vp.oct[L.octave];
+        if (L.src_kind < 0) {
+            c.src = (long long)vp.in_off;
+            c.src_input = 1;
+        } else {
+            c.src = (long long)level_off(*g, lev_G(L.src_idx));
+        }
+        c.dst = (long long)level_off(*g, lev_G(L.dst_idx));
+        c.dog = L.dog ? (long long)level_off(*g, lev_D(S, L.dog_idx)) : -1;
+        if (L.sub_octave >= 0) {
+            const OctaveGeom &m = vp.oct[L.sub_octave];
+            c.sub = (long long)level_off(m, lev_G(0));
+            c.mx = m.nx;
+            c.my = m.ny;
+            c.mz = m.nz;
+        } else {
+            c.sub = -1;
+        }
+        c.r = L.r;
+        c.taps = L.tapset;
+    }
+    c.nx = g->nx;
+    c.ny = g->ny;
+    c.nz = g->nz;
+    c.tiles_x = (g->nx + kCTX - 1) / kCTX;
+    c.tiles_y = (g->ny + kCTY - 1) / kCTY;
+    c.tiles_z = (g->nz + kCTZ - 1) / kCTZ;
+    return c;
 }
 
 // The fused job of a level-pass task, its depth split into `slabs` slabs
@@ -266,6 +327,7 @@ void build_schedule(sift3d_plan *pl)
     pl->xyjobs.clear();
     pl->zjobs.clear();
     pl->fjobs.clear();
+    pl->cjobs.clear();
     for (size_t b = 0; b < pl->blur.size(); ++b)
         pl->tasks.push_back(Task{0, (int)b, pl->blur[b].vol, pl->blur[b].octave, 0});
     if (pl->brief_rb >= 0)
@@ -295,12 +357,27 @@ void build_schedule(sift3d_plan *pl)
         const Task &k = pl->tasks[t];
         return pl->vols[k.vol].oct[k.kind == 0 ? pl->blur[k.pass].octave : k.octave];
     };
-    // pre-blurs go on the fused pass by the same rule as the level passes
+    // pre-blurs take their path by the same rule as the level passes
     const sift3d_params &pp = pl->ctx->p;
-    auto is_fused = [&](int t) {
+    auto path_of = [&](int t) {
         const Task &k = pl->tasks[t];
-        if (k.kind == 0) return pl->blur[k.pass].fused;
-        return fused_choice(pp, (long long)task_geom(t).n, pl->brief_rb);
+        if (k.kind == 0) return pl->blur[k.pass].path;
+        return level_path(pp, (long long)task_geom(t).n, pl->brief_rb);
+    };
+    auto is_fused = [&](int t) { return path_of(t) == kPathFused; };
+    auto is_split = [&](int t) { return path_of(t) == kPathSplit; };
+    // one compact launch for all ready compact tasks (any radii)
+    auto emit_compact = [&](const std::vector<int> &ts) {
+        if (ts.empty()) return;
+        Step st{3, ts, (int)pl->cjobs.size(), (int)ts.size(), 0, 0, false, 0};
+        for (int t : ts) {
+            DCJob c = compact_job(pl, pl->tasks[t]);
+            c.block0 = st.n_blocks;
+            st.n_blocks += c.tiles_x * c.tiles_y * c.tiles_z;
+            st.max_r = std::max(st.max_r, c.r);
+            pl->cjobs.push_back(c);
+        }
+        pl->sched.push_back(st);
     };
     auto emit = [&](int type, const std::vector<int> &ts) {
         if (ts.empty()) return;
@@ -361,15 +438,20 @@ void build_schedule(sift3d_plan *pl)
         std::vector<int> fs;
         for (int t = 0; t < nt; ++t)
             if (!done[t] && is_fused(t) && ready(t)) fs.push_back(t);
+        std::vector<int> cs;
+        for (int t = 0; t < nt; ++t)
+            if (!done[t] && path_of(t) == kPathCompact && ready(t)) cs.push_back(t);
         emit_fused(fs);
-        for (int t : fs) {
-            done[t] = 1;
-            --remaining;
-            progress = true;
-        }
+        emit_compact(cs);
+        for (const std::vector<int> *v : {&fs, &cs})
+            for (int t : *v) {
+                done[t] = 1;
+                --remaining;
+                progress = true;
+            }
         std::vector<int> xs;
         for (int t = 0; t < nt; ++t)
-            if (!done[t] && !xy_done[t] && !is_fused(t) && ready(t)) xs.push_back(t);
+            if (!done[t] && !xy_done[t] && is_split(t) && ready(t)) xs.push_back(t);
         emit(1, xs);
         for (int t : xs) xy_done[t] = 1;
         std::vector<int> zs;
@@ -387,8 +469,16 @@ void build_schedule(sift3d_plan *pl)
     pl->solo_xy.assign(nt, -1);
     pl->solo_z.assign(nt, -1);
     pl->solo_f.assign(nt, -1);
+    pl->solo_c.assign(nt, -1);
     for (int t = 0; t < nt; ++t) {
-        if (pl->tasks[t].kind == 1 && is_fused(t)) continue;  // pre-blurs have no single-pass entry
+        if (pl->tasks[t].kind == 1 && !is_split(t)) continue;  // pre-blurs have no single-pass entry
+        if (path_of(t) == kPathCompact) {
+            DCJob c = compact_job(pl, pl->tasks[t]);
+            c.block0 = 0;
+            pl->solo_c[t] = (int)pl->cjobs.size();
+            pl->cjobs.push_back(c);
+            continue;
+        }
         if (is_fused(t)) {
             const BlurLaunch &L = pl->blur[pl->tasks[t].pass];
             const OctaveGeom &g = pl->vols[L.vol].oct[L.octave];
@@ -420,8 +510,9 @@ int upload_tables(sift3d_plan *pl)
     const size_t b_xy = al(std::max<size_t>(1, pl->xyjobs.size()) * sizeof(DXYJob));
     const size_t b_z = al(std::max<size_t>(1, pl->zjobs.size()) * sizeof(DZJob));
     const size_t b_f = al(std::max<size_t>(1, pl->fjobs.size()) * sizeof(DFJob));
+    const size_t b_c = al(std::max<size_t>(1, pl->cjobs.size()) * sizeof(DCJob));
     const size_t b_taps = al(pl->tapsets.size() * kMaxTaps * sizeof(float));
-    const size_t total = b_units + b_vols + b_xy + b_z + b_f + b_taps;
+    const size_t total = b_units + b_vols + b_xy + b_z + b_f + b_c + b_taps;
     std::vector<char> host(total, 0);
     size_t off = 0;
     std::memcpy(host.data() + off, pl->units.data(), pl->units.size() * sizeof(DUnit));
@@ -434,6 +525,8 @@ int upload_tables(sift3d_plan *pl)
     off += b_z;
     std::memcpy(host.data() + off, pl->fjobs.data(), pl->fjobs.size() * sizeof(DFJob));
     off += b_f;
+    std::memcpy(host.data() + off, pl->cjobs.data(), pl->cjobs.size() * sizeof(DCJob));
+    off += b_c;
     for (size_t i = 0; i < pl->tapsets.size(); ++i)
         std::memcpy(host.data() + off + i * kMaxTaps * sizeof(float), pl->tapsets[i].data(), kMaxTaps * sizeof(float));
     hipError_t e = hipMalloc(&pl->d_tables, total);
@@ -449,7 +542,8 @@ int upload_tables(sift3d_plan *pl)
     pl->d_xy = reinterpret_cast<DXYJob *>(d + b_units + b_vols);
     pl->d_z = reinterpret_cast<DZJob *>(d + b_units + b_vols + b_xy);
     pl->d_f = reinterpret_cast<DFJob *>(d + b_units + b_vols + b_xy + b_z);
-    pl->d_taps = reinterpret_cast<float *>(d + b_units + b_vols + b_xy + b_z + b_f);
+    pl->d_c = reinterpret_cast<DCJob *>(d + b_units + b_vols + b_xy + b_z + b_f);
+    pl->d_taps = reinterpret_cast<float *>(d + b_units + b_vols + b_xy + b_z + b_f + b_c);
     return SIFT3D_OK;
 }
 
@@ -594,7 +688,7 @@ int make_plan(sift3d_ctx *ctx, int n, const int *dims, int kp_capacity, sift3d_p
                 L.dst_idx = i;
                 L.dog_idx = i - 1;
                 L.sub_octave = (i == S && o + 1 < no) ? o + 1 : -1;
-                L.fused = fused_choice(p, (long long)g.n, L.r);
+                L.path = level_path(p, (long long)g.n, L.r);
                 pl->blur.push_back(L);
             }
         }
@@ -638,6 +732,17 @@ int run_step(const sift3d_plan *plan, const Step &stp, const float *d_in, void *
         if (stp.count <= kInlineJobs)
             for (int j = 0; j < stp.count; ++j) a.inl[j] = plan->fjobs[stp.first + j];
         e = launch_blur(a, stp.max_r, stp.dog, stp.ty, st);
+    } else if (stp.type == 3) {
+        CompactLaunch a{};
+        a.jobs = plan->d_c + stp.first;
+        a.n_jobs = stp.count;
+        a.n_blocks = stp.n_blocks;
+        a.ws = ws;
+        a.in = d_in;
+        a.taps = plan->d_taps;
+        if (stp.count <= kInlineJobs)
+            for (int j = 0; j < stp.count; ++j) a.inl[j] = plan->cjobs[stp.first + j];
+        e = launch_blur_compact(a, stp.max_r, st);
     } else if (stp.type == 1) {
         XYLaunch a{};
         a.jobs = plan->d_xy + stp.first;
@@ -844,7 +949,7 @@ int sift3d_pyramid_pass_info(const sift3d_plan *plan, int pass, int info[6], siz
         info[1] = L.dst_idx;
         info[2] = L.r;
         info[3] = L.sub_octave >= 0 ? 1 : 0;
-        info[4] = L.fused ? 1 : 0;
+        info[4] = L.path;
         info[5] = L.vol;
     }
     if (bytes != nullptr) {
@@ -868,7 +973,12 @@ int sift3d_pyramid_pass(const sift3d_plan *plan, int pass, const float *d_vol, v
     for (size_t k = 0; k < plan->tasks.size(); ++k)
         if (plan->tasks[k].kind == 0 && plan->tasks[k].pass == pass) t = (int)k;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (L.fused) {
+    if (L.path == kPathCompact) {
+        const DCJob &c = plan->cjobs[plan->solo_c[t]];
+        return run_step(plan, Step{3, {t}, plan->solo_c[t], 1, c.tiles_x * c.tiles_y * c.tiles_z, L.r, false, 0},
+                        d_vol, d_ws, st);
+    }
+    if (L.path == kPathFused) {
         const DFJob &f = plan->fjobs[plan->solo_f[t]];
         const int ty = solo_ty(plan->vols[L.vol].oct[L.octave]);
         return run_step(plan, Step{0, {t}, plan->solo_f[t], 1, f.tiles_x * f.tiles_y * f.slabs, L.r, L.dog, ty},

@@ -53,6 +53,14 @@ constexpr long long kFusedMinVoxels = 24LL << 20;
 constexpr long long kFusedMidVoxels = 2LL << 20;
 constexpr int kFusedMidMaxR = 8;
 constexpr int kMaxFusedR = 10;              // largest tap radius of the fused pass
+// One-launch pass for small octaves: 32 x 8 x 4 output tiles computed from
+// their whole source footprint; used below kFusedMidVoxels, except for radii
+// above kFusedMidMaxR from kCompactWideVoxels on (there the footprint
+// re-reads make the xy + z pair faster).
+constexpr int kCTX = 32, kCTY = 8, kCTZ = 4;
+constexpr long long kCompactWideVoxels = 1LL << 20;
+constexpr int kCompactThreads = 256;
+constexpr int kCompactMaxR = 10;
 
 // Detection geometry.
 constexpr int kDetThreads = 256;            // 4 waves
@@ -137,6 +145,22 @@ struct DFJob {
     int pad_[3];
 };
 
+// One job of a compact launch: one level (or BRIEF pre-blur) of one octave
+// of one volume, as tiles_x * tiles_y * tiles_z workgroups.
+struct DCJob {
+    long long src;        // workspace byte offset, or input element offset if src_input
+    long long dst;        // workspace byte offset of G_i
+    long long dog;        // D_{i-1} = src - dst (< 0: none)
+    long long sub;        // next octave's G_0 (< 0: none)
+    int src_input;
+    int nx, ny, nz;
+    int mx, my, mz;       // dims of `sub`
+    int tiles_x, tiles_y, tiles_z;
+    int block0;
+    int r, taps;          // tap radius, tap-set index
+    int pad_[3];
+};
+
 // Launches with few jobs also carry them inline (read through the scalar
 // cache from the argument segment instead of a dependent global load).
 constexpr int kInlineJobs = 8;
@@ -149,6 +173,15 @@ struct FusedLaunch {
     const float *in;      // packed input volumes
     const float *taps;    // [n_tapsets][kMaxTaps]
     DFJob inl[kInlineJobs];
+};
+
+struct CompactLaunch {
+    const DCJob *jobs;    // this launch's jobs, block0 ascending (radii may differ)
+    int n_jobs, n_blocks;
+    char *ws;
+    const float *in;
+    const float *taps;
+    DCJob inl[kInlineJobs];
 };
 
 struct XYLaunch {
@@ -216,12 +249,16 @@ struct OctaveGeom {
     size_t base;          // workspace byte offset of G_0
 };
 
+// How a level (or pre-blur) runs: an xy launch then a z launch, the fused
+// streaming pass, or the compact pass.
+constexpr int kPathSplit = 0, kPathFused = 1, kPathCompact = 2;
+
 // One pyramid level: G_dst of `octave` of volume `vol` from G_src (or the input).
 struct BlurLaunch {
     int vol;
     int r;
     bool dog;
-    bool fused;           // fused streaming pass, else xy + z jobs
+    int path;             // kPathSplit, kPathFused or kPathCompact
     int tapset;           // index into sift3d_plan::tapsets
     int src_kind;         // -1 = input volume, 0 = G level of the octave
     int src_idx, dst_idx, dog_idx;
@@ -241,7 +278,7 @@ struct Task {
 // split tasks (their jobs are entries [first, first + count) of the device
 // job table of that kind).
 struct Step {
-    int type;             // 0 = fused launch, 1 = xy launch, 2 = z launch
+    int type;             // 0 = fused launch, 1 = xy launch, 2 = z launch, 3 = compact launch
     std::vector<int> tasks;
     int first, count, n_blocks, max_r;
     bool dog;             // fused launches: jobs write a DoG level
@@ -285,13 +322,15 @@ struct sift3d_plan {
     std::vector<s3d::Task> tasks;
     std::vector<s3d::Step> sched;       // launches of sift3d_build_pyramid
     std::vector<int> solo_xy, solo_z;   // per task: index of its single-job entry (-1: fused)
-    std::vector<int> solo_f;            // per task: index of its single-job fused entry (-1: split)
+    std::vector<int> solo_f;            // per task: index of its single-job fused entry (-1: none)
+    std::vector<int> solo_c;            // per task: index of its single-job compact entry (-1: none)
     // host copies of the device tables
     std::vector<s3d::DUnit> units;
     std::vector<s3d::DVol> dvols;
     std::vector<s3d::DXYJob> xyjobs;
     std::vector<s3d::DZJob> zjobs;
     std::vector<s3d::DFJob> fjobs;
+    std::vector<s3d::DCJob> cjobs;
     // device tables (one allocation, owned by the plan)
     void *d_tables;
     s3d::DUnit *d_units;
@@ -299,6 +338,7 @@ struct sift3d_plan {
     s3d::DXYJob *d_xy;
     s3d::DZJob *d_z;
     s3d::DFJob *d_f;
+    s3d::DCJob *d_c;
     float *d_taps;
 };
 
@@ -308,6 +348,7 @@ hipError_t launch_blur(const FusedLaunch &a, int r, bool dog, int ty, hipStream_
 int fused_blocks_per_cu(int r, bool dog, int ty);
 hipError_t launch_blur_xy(const XYLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_blur_z(const ZLaunch &a, int max_r, hipStream_t st);
+hipError_t launch_blur_compact(const CompactLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_detect(const DetLaunch &a, hipStream_t st);
 hipError_t launch_describe(const DescLaunch &a, int grid, hipStream_t st);
 

@@ -306,7 +306,8 @@ class Plan:
                                             _vp(_stream(stream))), "sift3d_build_pyramid")
 
     def pyramid_passes(self):
-        """[(octave, level, radius, writes_sub, algorithmic_bytes, fused, volume)] in dependency order."""
+        """[(octave, level, radius, writes_sub, algorithmic_bytes, path, volume)] in dependency order;
+        path: 1 = fused streaming launch, 2 = compact launch, 0 = xy + z launches."""
         lib = _load()
         n = ctypes.c_int()
         _check(lib.sift3d_pyramid_pass_count(self.handle, ctypes.byref(n)), "sift3d_pyramid_pass_count")

@@ -57,7 +57,7 @@ def test_bad_params_rejected():
     import paper_2112_10258_amd as S
     draws = P.pair_draws()
     for kw in (dict(brief_n=100), dict(votes=0), dict(votes=81), dict(scales=0), dict(min_dim=2),
-               dict(pyramid_mode=3)):
+               dict(pyramid_mode=4), dict(pyramid_mode=-1)):
         with pytest.raises(S.Sift3dError) as ei:
             S.pair_offsets(S.default_params(**kw), draws, 1)
         assert ei.value.code == -1

@@ -31,10 +31,11 @@ def _run_plain(vol, cap, **kw):
     return res
 
 
-@pytest.mark.parametrize("cap,mode", [(4096, 0), (7, 0), (4096, 1)])
+@pytest.mark.parametrize("cap,mode", [(4096, 0), (7, 0), (4096, 1), (4096, 2)])
 def test_batch_equals_plain(cap, mode):
-    """mode 1 puts every level on the fused pass: one fused launch per level
-    covers all volumes (a job table with per-volume slabs)."""
+    """mode 0 runs these small octaves on the compact pass, mode 1 on the
+    fused pass (one fused launch per level covers all volumes: a job table
+    with per-volume slabs), mode 2 as xy + z launches."""
     import torch
     import paper_2112_10258_amd as S
     vols = _vols()

@@ -32,10 +32,13 @@ def _vol(name):
         return P.config1(), dict(n_octaves=2, pyramid_mode=1)
     if name == "ragged_fused":
         return P.noise_blob_volume((45, 38, 53), 21, n_blobs=10, margin=6), dict(min_dim=8, pyramid_mode=1)
+    if name == "ragged_split":
+        # the xy + z launches on every octave
+        return P.noise_blob_volume((45, 38, 53), 21, n_blobs=10, margin=6), dict(min_dim=8, pyramid_mode=2)
     raise KeyError(name)
 
 
-CASES = ["config1", "ragged", "flat", "config2", "config1_fused", "ragged_fused"]
+CASES = ["config1", "ragged", "flat", "config2", "config1_fused", "ragged_fused", "ragged_split"]
 _cache = {}
 
 
