@@ -147,8 +147,10 @@ int sift3d_plan_octave_dims(const sift3d_plan *plan, int volume, int octave, int
 
 /*
  * Device pointer of one pyramid level inside a workspace: kind 0 = G_idx
- * (idx 0..S+2), kind 1 = D_idx (idx 0..S+1). A view, no copy; the level is
- * a [nz][ny][nx] float32 array of the octave's dims.
+ * (idx 0..S+2), kind 1 = D_idx (idx 0..S+1), kind 2 = B_idx, the BRIEF
+ * pre-blur of G_idx (idx 1..S; only when the plan pre-blurs, i.e.
+ * brief_blur > 0 and brief_n > 0). A view, no copy; the level is a
+ * [nz][ny][nx] float32 array of the octave's dims.
  */
 int sift3d_level(const sift3d_plan *plan, void *d_ws, int volume, int octave, int kind, int idx,
                  float **d_ptr);

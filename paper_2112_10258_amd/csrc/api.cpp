@@ -249,7 +249,7 @@ DCJob compact_job(const sift3d_plan *pl, const Task &k)
 
 // The fused job of a level-pass task, its depth split into `slabs` slabs
 // (block0 left for the caller).
-DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs, int ty)
+DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs, int ty, bool with_pb = false)
 {
     const int S = pl->S;
     DFJob f{};
@@ -268,6 +268,7 @@ DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs, int ty)
         f.L = slab_planes(g.nz, slabs, pl->brief_rb);
         f.slabs = (g.nz + f.L - 1) / f.L;
         f.taps = pl->brief_tapset;
+        f.pb = -1;
         return f;
     }
     const BlurLaunch &L = pl->blur[k.pass];
@@ -298,6 +299,13 @@ DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs, int ty)
     f.L = slab_planes(g.nz, slabs, L.r);
     f.slabs = (g.nz + f.L - 1) / f.L;
     f.taps = L.tapset;
+    if (with_pb) {
+        // B_s of the source level G_s (s = src_idx)
+        f.pb = (long long)level_off(g, lev_B(S, L.src_idx));
+        f.pb_taps = pl->brief_tapset;
+    } else {
+        f.pb = -1;
+    }
     return f;
 }
 
@@ -308,9 +316,9 @@ int solo_ty(const OctaveGeom &g) { return (long long)g.n >= kBlurTallVoxels ? kB
 // total: enough blocks to fill every resident slot of the device once (CUs x
 // the fused pass's workgroups per CU at this radius, from its registers and
 // LDS), no more.
-int fused_slabs(const sift3d_plan *pl, long long tiles, int r, bool dog, int ty)
+int fused_slabs(const sift3d_plan *pl, long long tiles, int r, bool dog, bool pb, int ty)
 {
-    const int per_cu = std::max(1, fused_blocks_per_cu(r, dog, ty));
+    const int per_cu = std::max(1, fused_blocks_per_cu(r, dog, pb, ty));
     const long long slots = (long long)pl->ctx->n_cu * per_cu;
     return (int)std::max<long long>(1, (slots + tiles - 1) / tiles);
 }
@@ -366,6 +374,25 @@ void build_schedule(sift3d_plan *pl)
     };
     auto is_fused = [&](int t) { return path_of(t) == kPathFused; };
     auto is_split = [&](int t) { return path_of(t) == kPathSplit; };
+    // A fused level pass G_{s+1} (s = 1..S) also writes B_s when the
+    // pre-blur radius is kFusedPreR: that pre-blur task is then done by it.
+    std::vector<char> with_pb(nt, 0);
+    int absorbed = 0;
+    if (pl->brief_rb == kFusedPreR)
+        for (int t = 0; t < nt; ++t) {
+            const Task &k = pl->tasks[t];
+            if (k.kind != 0 || !is_fused(t)) continue;
+            const BlurLaunch &L = pl->blur[k.pass];
+            if (!L.dog || L.src_kind != 0 || L.src_idx < 1 || L.src_idx > S || L.r < kFusedPreR) continue;
+            for (int u = 0; u < nt; ++u) {
+                const Task &b = pl->tasks[u];
+                if (b.kind == 1 && !done[u] && b.vol == L.vol && b.octave == L.octave && b.s == L.src_idx) {
+                    done[u] = 1;
+                    with_pb[t] = 1;
+                    ++absorbed;
+                }
+            }
+        }
     // one compact launch for all ready compact tasks (any radii)
     auto emit_compact = [&](const std::vector<int> &ts) {
         if (ts.empty()) return;
@@ -404,14 +431,16 @@ void build_schedule(sift3d_plan *pl)
         st.n_blocks = blocks;
         pl->sched.push_back(st);
     };
-    // one fused launch per (radius, DoG) group of ready fused tasks
+    // one fused launch per (radius, DoG, pre-blur) group of ready fused tasks
     auto emit_fused = [&](const std::vector<int> &ts) {
         std::vector<int> left = ts;
         while (!left.empty()) {
             const int r0 = task_r(left[0]);
             const bool dog0 = task_dog(left[0]);
+            const bool pb0 = with_pb[left[0]] != 0;
             std::vector<int> grp, rest;
-            for (int t : left) (task_r(t) == r0 && task_dog(t) == dog0 ? grp : rest).push_back(t);
+            for (int t : left)
+                (task_r(t) == r0 && task_dog(t) == dog0 && (with_pb[t] != 0) == pb0 ? grp : rest).push_back(t);
             long long voxels = 0;
             for (int t : grp) voxels += (long long)task_geom(t).n;
             const int ty = voxels >= kBlurTallVoxels ? kBlurTYTall : kBlurTYSmall;
@@ -420,10 +449,10 @@ void build_schedule(sift3d_plan *pl)
                 const OctaveGeom &g = task_geom(t);
                 tiles += (long long)((g.nx + kBlurTX - 1) / kBlurTX) * ((g.ny + ty - 1) / ty);
             }
-            const int slabs = fused_slabs(pl, tiles, r0, dog0, ty);
-            Step st{0, grp, (int)pl->fjobs.size(), (int)grp.size(), 0, r0, dog0, ty};
+            const int slabs = fused_slabs(pl, tiles, r0, dog0, pb0, ty);
+            Step st{0, grp, (int)pl->fjobs.size(), (int)grp.size(), 0, r0, dog0, ty, pb0};
             for (int t : grp) {
-                DFJob f = fused_job(pl, pl->tasks[t], slabs, ty);
+                DFJob f = fused_job(pl, pl->tasks[t], slabs, ty, pb0);
                 f.block0 = st.n_blocks;
                 st.n_blocks += f.tiles_x * f.tiles_y * f.slabs;
                 pl->fjobs.push_back(f);
@@ -432,7 +461,7 @@ void build_schedule(sift3d_plan *pl)
             left.swap(rest);
         }
     };
-    int remaining = nt;
+    int remaining = nt - absorbed;
     while (remaining > 0) {
         bool progress = false;
         std::vector<int> fs;
@@ -484,7 +513,7 @@ void build_schedule(sift3d_plan *pl)
             const OctaveGeom &g = pl->vols[L.vol].oct[L.octave];
             const int ty = solo_ty(g);
             const long long tiles = (long long)((g.nx + kBlurTX - 1) / kBlurTX) * ((g.ny + ty - 1) / ty);
-            DFJob f = fused_job(pl, pl->tasks[t], fused_slabs(pl, tiles, L.r, L.dog, ty), ty);
+            DFJob f = fused_job(pl, pl->tasks[t], fused_slabs(pl, tiles, L.r, L.dog, false, ty), ty);
             f.block0 = 0;
             pl->solo_f[t] = (int)pl->fjobs.size();
             pl->fjobs.push_back(f);
@@ -731,7 +760,7 @@ int run_step(const sift3d_plan *plan, const Step &stp, const float *d_in, void *
         a.taps = plan->d_taps;
         if (stp.count <= kInlineJobs)
             for (int j = 0; j < stp.count; ++j) a.inl[j] = plan->fjobs[stp.first + j];
-        e = launch_blur(a, stp.max_r, stp.dog, stp.ty, st);
+        e = launch_blur(a, stp.max_r, stp.dog, stp.pb, stp.ty, st);
     } else if (stp.type == 3) {
         CompactLaunch a{};
         a.jobs = plan->d_c + stp.first;
@@ -914,7 +943,12 @@ int sift3d_level(const sift3d_plan *plan, void *d_ws, int volume, int octave, in
     if (plan == nullptr || d_ws == nullptr || d_ptr == nullptr || volume < 0 || volume >= plan->n_vol)
         return SIFT3D_E_ARG;
     const VolPlan &vp = plan->vols[volume];
-    if (octave < 0 || octave >= (int)vp.oct.size() || kind < 0 || kind > 1) return SIFT3D_E_ARG;
+    if (octave < 0 || octave >= (int)vp.oct.size() || kind < 0 || kind > 2) return SIFT3D_E_ARG;
+    if (kind == 2) {
+        if (plan->brief_rb < 0 || idx < 1 || idx > plan->S) return SIFT3D_E_ARG;
+        *d_ptr = ws_float(d_ws, level_off(vp.oct[octave], lev_B(plan->S, idx)));
+        return SIFT3D_OK;
+    }
     if (idx < 0 || idx >= (kind == 0 ? plan->S + 3 : plan->S + 2)) return SIFT3D_E_ARG;
     *d_ptr = ws_float(d_ws, level_off(vp.oct[octave], kind == 0 ? lev_G(idx) : lev_D(plan->S, idx)));
     return SIFT3D_OK;

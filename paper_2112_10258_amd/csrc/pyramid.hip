@@ -2,6 +2,7 @@
 //   G_i = G_{i-1} blurred by a separable Gaussian (x, then y, then z),
 //   D_{i-1} = G_{i-1} - G_i                     (optional),
 //   the 2x2x2 mean of G_i into the next octave's G_0 (optional),
+//   B_{i-1} = the BRIEF pre-blur of G_{i-1}      (optional),
 // reading G_{i-1} from HBM once (Section 3.2.2: Gaussian Convolution,
 // Difference-of-Gaussian and Sub-sampling, fused here into one pass).
 //
@@ -21,23 +22,24 @@
 namespace s3d {
 
 // 32-row instances live in pyramid_tall.hip.
-hipError_t launch_blur_tall(const FusedLaunch &a, int r, bool dog, hipStream_t st);
-int fused_blocks_per_cu_tall(int r, bool dog);
+hipError_t launch_blur_tall(const FusedLaunch &a, int r, bool dog, bool pb, hipStream_t st);
+int fused_blocks_per_cu_tall(int r, bool dog, bool pb);
 
-hipError_t launch_blur(const FusedLaunch &a, int r, bool dog, int ty, hipStream_t st)
+hipError_t launch_blur(const FusedLaunch &a, int r, bool dog, bool pb, int ty, hipStream_t st)
 {
     if (a.n_blocks <= 0) return hipSuccess;
-    if (ty == kBlurTYTall) return launch_blur_tall(a, r, dog, st);
-    if (ty == kBlurTYSmall) return fused::launch_ty<kBlurTYSmall>(a, r, dog, st);
+    if (ty == kBlurTYTall) return launch_blur_tall(a, r, dog, pb, st);
+    if (ty == kBlurTYSmall) return fused::launch_ty<kBlurTYSmall>(a, r, dog, pb, st);
     return hipErrorInvalidValue;
 }
 
 // Workgroups of the fused pass at radius r and tile height ty that one CU
-// holds at once (registers and LDS), 0 on error.
-int fused_blocks_per_cu(int r, bool dog, int ty)
+// holds at once (registers and LDS), 0 on error or for a combination that
+// has no instance.
+int fused_blocks_per_cu(int r, bool dog, bool pb, int ty)
 {
-    if (ty == kBlurTYTall) return fused_blocks_per_cu_tall(r, dog);
-    if (ty == kBlurTYSmall) return fused::occupancy_ty<kBlurTYSmall>(r, dog);
+    if (ty == kBlurTYTall) return fused_blocks_per_cu_tall(r, dog, pb);
+    if (ty == kBlurTYSmall) return fused::occupancy_ty<kBlurTYSmall>(r, dog, pb);
     return 0;
 }
 

@@ -66,12 +66,21 @@ __device__ __forceinline__ int find_fjob(const DFJob *jobs, int n, int bid)
 }
 
 // INL: the jobs are read from the inline copy in the arguments (small
-// launches), else from the device table.
-template <int R, bool DOG, bool INL, int TY>
+// launches), else from the device table. PB: the jobs also write B_s, the
+// BRIEF pre-blur (radius kFusedPreR) of their source level G_s, from the
+// same staged planes: x outputs from the x pass's row registers, y into a
+// third LDS tile, z through a 2*kFusedPreR+1 register shift ring. Each
+// stencil is the one a stand-alone pre-blur pass evaluates, in the same
+// order, so B_s is the same either way.
+template <int R, bool DOG, bool INL, int TY, bool PB>
 __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const FusedLaunch fl)
 {
     constexpr int TX = kBlurTX, NY = kBlurNY, NT = blur_threads(TY);
     constexpr int M = 2 * R + 1;
+    constexpr int RB = PB ? kFusedPreR : 0;         // pre-blur radius
+    constexpr int MB = 2 * RB + 1;
+    constexpr int BH = TY + 2 * RB;                 // pre-blur rows of the x pass
+    static_assert(!PB || (DOG && R >= kFusedPreR), "the pre-blur rides on level passes with a halo >= its radius");
     constexpr int AWL = TX + 2 * R;                 // staged width
     constexpr int AW = (AWL + 3) & ~3;              // LDS row pitch (16-byte rows)
     constexpr int AH = TY + 2 * R;                  // staged height
@@ -87,6 +96,7 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
     // input planes: private to each thread, kept in LDS because the slot
     // index is not a compile-time constant
     __shared__ float C[DOG ? (R + 1) * NY * NT : 1];
+    __shared__ __align__(16) float B2[PB ? BH * TX : 1];
 
     const int tid = threadIdx.x;
     const int logical = xcd_remap(blockIdx.x, fl.n_blocks);
@@ -133,6 +143,18 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
     float w[M];
 #pragma unroll
     for (int t = 0; t < M; ++t) w[t] = wt[t];
+    float wb[MB];
+    float ringb[NY][MB];
+    float *const pbp = PB ? reinterpret_cast<float *>(fl.ws + jb.pb) : nullptr;
+    if constexpr (PB) {
+        const float *wbt = fl.taps + (size_t)jb.pb_taps * kMaxTaps;
+#pragma unroll
+        for (int t = 0; t < MB; ++t) wb[t] = wbt[t];
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+#pragma unroll
+            for (int t = 0; t < MB; ++t) ringb[j][t] = 0.f;
+    }
 
     const int tx = tid % TX;
     const int tyb = (tid / TX) * NY;
@@ -194,6 +216,17 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
 #pragma unroll
                 for (int q = 0; q < 4; ++q) o[q] = sym_stencil<R>(w, [&](int t) { return in[q + t]; });
                 *reinterpret_cast<float4 *>(&B[r * TX + xb]) = make_float4(o[0], o[1], o[2], o[3]);
+                if constexpr (PB) {
+                    // rows y0 - RB .. y0 + TY + RB of the pre-blur, x from the same registers
+                    if (r >= R - RB && r < R + TY + RB) {
+                        float ob[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            ob[q] = sym_stencil<RB>(wb, [&](int t) { return in[q + R - RB + t]; });
+                        *reinterpret_cast<float4 *>(&B2[(r - (R - RB)) * TX + xb]) =
+                            make_float4(ob[0], ob[1], ob[2], ob[3]);
+                    }
+                }
             }
             __syncthreads();
 
@@ -204,6 +237,30 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
                 for (int q = 0; q < NY + 2 * R; ++q) col[q] = B[(tyb + q) * TX + tx];
 #pragma unroll
                 for (int j = 0; j < NY; ++j) ring[j][p] = sym_stencil<R>(w, [&](int t) { return col[j + t]; });
+            }
+
+            if constexpr (PB) {
+                // pre-blur: y pass into the shift ring (oldest plane first), then z
+                float colb[NY + 2 * RB];
+#pragma unroll
+                for (int q = 0; q < NY + 2 * RB; ++q) colb[q] = B2[(tyb + q) * TX + tx];
+#pragma unroll
+                for (int j = 0; j < NY; ++j) {
+#pragma unroll
+                    for (int t = 0; t + 1 < MB; ++t) ringb[j][t] = ringb[j][t + 1];
+                    ringb[j][MB - 1] = sym_stencil<RB>(wb, [&](int t) { return colb[j + t]; });
+                }
+                // the ring now holds input planes zin - 2RB .. zin (zin = z0 - R + it);
+                // its centre plane is an output plane of this slab from step R + RB on
+                const int qz = z0 - R + it - RB;
+                if (it >= R + RB && qz < z1) {
+                    float *d = pbp + (size_t)qz * nxy;
+#pragma unroll
+                    for (int j = 0; j < NY; ++j) {
+                        const float v = sym_stencil<RB>(wb, [&](int t) { return ringb[j][t]; });
+                        if (j == 0 ? ok0 : ok1) d[j == 0 ? o0 : o1] = v;
+                    }
+                }
             }
 
             if (it >= 2 * R) {
@@ -238,68 +295,96 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
 
 
 template <int R, int TY>
-hipError_t launch_rt(const FusedLaunch &a, bool dog, hipStream_t st)
+hipError_t launch_rt(const FusedLaunch &a, bool dog, bool pb, hipStream_t st)
 {
     const dim3 g(a.n_blocks), b(blur_threads(TY));
     const bool inl = a.n_jobs <= kInlineJobs;
+    if (pb) {
+        if constexpr (R >= kFusedPreR) {
+            if (!dog) return hipErrorInvalidValue;
+            if (inl)
+                hipLaunchKernelGGL((blur_level_kernel<R, true, true, TY, true>), g, b, 0, st, a);
+            else
+                hipLaunchKernelGGL((blur_level_kernel<R, true, false, TY, true>), g, b, 0, st, a);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (dog && inl)
-        hipLaunchKernelGGL((blur_level_kernel<R, true, true, TY>), g, b, 0, st, a);
+        hipLaunchKernelGGL((blur_level_kernel<R, true, true, TY, false>), g, b, 0, st, a);
     else if (dog)
-        hipLaunchKernelGGL((blur_level_kernel<R, true, false, TY>), g, b, 0, st, a);
+        hipLaunchKernelGGL((blur_level_kernel<R, true, false, TY, false>), g, b, 0, st, a);
     else if (inl)
-        hipLaunchKernelGGL((blur_level_kernel<R, false, true, TY>), g, b, 0, st, a);
+        hipLaunchKernelGGL((blur_level_kernel<R, false, true, TY, false>), g, b, 0, st, a);
     else
-        hipLaunchKernelGGL((blur_level_kernel<R, false, false, TY>), g, b, 0, st, a);
+        hipLaunchKernelGGL((blur_level_kernel<R, false, false, TY, false>), g, b, 0, st, a);
     return hipGetLastError();
 }
 
 template <int R, int TY>
-int occupancy_rt(bool dog)
+int occupancy_rt(bool dog, bool pb)
 {
     int n = 0;
-    const hipError_t e =
-        dog ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, true, true, TY>, blur_threads(TY), 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, false, true, TY>, blur_threads(TY),
-                                                           0);
+    hipError_t e;
+    if constexpr (R >= kFusedPreR) {
+        if (pb && dog)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, true, true, TY, true>,
+                                                             blur_threads(TY), 0);
+        else if (pb)
+            return 0;
+        else if (dog)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, true, true, TY, false>,
+                                                             blur_threads(TY), 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, false, true, TY, false>,
+                                                             blur_threads(TY), 0);
+    } else {
+        if (pb) return 0;
+        e = dog ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, true, true, TY, false>,
+                                                               blur_threads(TY), 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blur_level_kernel<R, false, true, TY, false>,
+                                                               blur_threads(TY), 0);
+    }
     return e == hipSuccess ? n : 0;
 }
 
 // Launch (or query the occupancy of) the instance for radius r, tile height TY.
 template <int TY>
-hipError_t launch_ty(const FusedLaunch &a, int r, bool dog, hipStream_t st)
+hipError_t launch_ty(const FusedLaunch &a, int r, bool dog, bool pb, hipStream_t st)
 {
     static_assert(kMaxFusedR == 10, "one case per fused radius");
     switch (r) {
-    case 0: return launch_rt<0, TY>(a, dog, st);
-    case 1: return launch_rt<1, TY>(a, dog, st);
-    case 2: return launch_rt<2, TY>(a, dog, st);
-    case 3: return launch_rt<3, TY>(a, dog, st);
-    case 4: return launch_rt<4, TY>(a, dog, st);
-    case 5: return launch_rt<5, TY>(a, dog, st);
-    case 6: return launch_rt<6, TY>(a, dog, st);
-    case 7: return launch_rt<7, TY>(a, dog, st);
-    case 8: return launch_rt<8, TY>(a, dog, st);
-    case 9: return launch_rt<9, TY>(a, dog, st);
-    case 10: return launch_rt<10, TY>(a, dog, st);
+    case 0: return launch_rt<0, TY>(a, dog, pb, st);
+    case 1: return launch_rt<1, TY>(a, dog, pb, st);
+    case 2: return launch_rt<2, TY>(a, dog, pb, st);
+    case 3: return launch_rt<3, TY>(a, dog, pb, st);
+    case 4: return launch_rt<4, TY>(a, dog, pb, st);
+    case 5: return launch_rt<5, TY>(a, dog, pb, st);
+    case 6: return launch_rt<6, TY>(a, dog, pb, st);
+    case 7: return launch_rt<7, TY>(a, dog, pb, st);
+    case 8: return launch_rt<8, TY>(a, dog, pb, st);
+    case 9: return launch_rt<9, TY>(a, dog, pb, st);
+    case 10: return launch_rt<10, TY>(a, dog, pb, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <int TY>
-int occupancy_ty(int r, bool dog)
+int occupancy_ty(int r, bool dog, bool pb)
 {
     switch (r) {
-    case 0: return occupancy_rt<0, TY>(dog);
-    case 1: return occupancy_rt<1, TY>(dog);
-    case 2: return occupancy_rt<2, TY>(dog);
-    case 3: return occupancy_rt<3, TY>(dog);
-    case 4: return occupancy_rt<4, TY>(dog);
-    case 5: return occupancy_rt<5, TY>(dog);
-    case 6: return occupancy_rt<6, TY>(dog);
-    case 7: return occupancy_rt<7, TY>(dog);
-    case 8: return occupancy_rt<8, TY>(dog);
-    case 9: return occupancy_rt<9, TY>(dog);
-    case 10: return occupancy_rt<10, TY>(dog);
+    case 0: return occupancy_rt<0, TY>(dog, pb);
+    case 1: return occupancy_rt<1, TY>(dog, pb);
+    case 2: return occupancy_rt<2, TY>(dog, pb);
+    case 3: return occupancy_rt<3, TY>(dog, pb);
+    case 4: return occupancy_rt<4, TY>(dog, pb);
+    case 5: return occupancy_rt<5, TY>(dog, pb);
+    case 6: return occupancy_rt<6, TY>(dog, pb);
+    case 7: return occupancy_rt<7, TY>(dog, pb);
+    case 8: return occupancy_rt<8, TY>(dog, pb);
+    case 9: return occupancy_rt<9, TY>(dog, pb);
+    case 10: return occupancy_rt<10, TY>(dog, pb);
     default: return 0;
     }
 }

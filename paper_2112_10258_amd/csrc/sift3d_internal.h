@@ -53,6 +53,9 @@ constexpr long long kFusedMinVoxels = 24LL << 20;
 constexpr long long kFusedMidVoxels = 2LL << 20;
 constexpr int kFusedMidMaxR = 8;
 constexpr int kMaxFusedR = 10;              // largest tap radius of the fused pass
+// Pre-blur radius that the fused pass can write alongside a level: pass
+// G_{s+1} stages G_s with a halo of R >= kFusedPreR, so it also writes B_s.
+constexpr int kFusedPreR = 3;
 // One-launch pass for small octaves: 32 x 8 x 4 output tiles computed from
 // their whole source footprint; used below kFusedMidVoxels, except for radii
 // above kFusedMidMaxR from kCompactWideVoxels on (there the footprint
@@ -142,7 +145,8 @@ struct DFJob {
     int tiles_x, tiles_y, slabs;
     int block0;           // first block of the job within its launch
     int taps;             // tap-set index
-    int pad_[3];
+    int pb_taps;          // tap set of the BRIEF pre-blur written alongside (pb >= 0)
+    long long pb;         // B_s = pre-blur of this job's source G_s (< 0: none)
 };
 
 // One job of a compact launch: one level (or BRIEF pre-blur) of one octave
@@ -283,6 +287,7 @@ struct Step {
     int first, count, n_blocks, max_r;
     bool dog;             // fused launches: jobs write a DoG level
     int ty;               // fused launches: tile height
+    bool pb;              // fused launches: jobs also write a BRIEF pre-blurred level
 };
 
 struct VolPlan {
@@ -344,8 +349,8 @@ struct sift3d_plan {
 
 namespace s3d {
 // Launchers (return hipError_t of the launch).
-hipError_t launch_blur(const FusedLaunch &a, int r, bool dog, int ty, hipStream_t st);
-int fused_blocks_per_cu(int r, bool dog, int ty);
+hipError_t launch_blur(const FusedLaunch &a, int r, bool dog, bool pb, int ty, hipStream_t st);
+int fused_blocks_per_cu(int r, bool dog, bool pb, int ty);
 hipError_t launch_blur_xy(const XYLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_blur_z(const ZLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_blur_compact(const CompactLaunch &a, int max_r, hipStream_t st);

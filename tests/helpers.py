@@ -44,6 +44,10 @@ def gpu_extract(vol: np.ndarray, cap: int = 1 << 15, draws=None, levels: bool = 
                     for o in range(plan.n_octaves)]
         res["D"] = [[plan.level(buf.ws, o, 1, i).cpu().numpy() for i in range(gp.scales + 2)]
                     for o in range(plan.n_octaves)]
+        if gp.brief_blur > 0 and gp.brief_n > 0:
+            # B[o][s - 1] = pre-blurred G_s, s = 1..S
+            res["B"] = [[plan.level(buf.ws, o, 2, s).cpu().numpy() for s in range(1, gp.scales + 1)]
+                        for o in range(plan.n_octaves)]
     res["_keep"] = (ctx, plan, buf, dvol)
     return res
 

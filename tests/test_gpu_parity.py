@@ -71,6 +71,24 @@ def test_levels_match_oracle(name):
 
 
 @pytest.mark.parametrize("name", CASES)
+def test_preblur_levels_match_oracle(name):
+    """B_s (the BRIEF pre-blur, Section 3.2.3) of every octave equals the
+    oracle's blur of the GPU's own G_s by sigma_b, whichever kernel wrote it
+    (on config 2: the octave-0 fused level passes G_2..G_4, which write
+    B_1..B_3 alongside; the compact pass below)."""
+    vol, g, p, ref = _run(name)
+    errs = {}
+    for o, Gs in enumerate(g["G"]):
+        for s in range(1, p.scales + 1):
+            want = O.blur(Gs[s].astype(np.float64), p.brief_blur, p.trunc)
+            errs[f"B{o}.{s}"] = level_rel_err(g["B"][o][s - 1], want)
+    worst = max(errs, key=errs.get)
+    print(f"[parity] {name}: worst pre-blur rel err {errs[worst]:.3e} at {worst}")
+    bad = {k: v for k, v in errs.items() if v > LEVEL_RTOL}
+    assert not bad, f"pre-blurred levels over {LEVEL_RTOL}: {bad}"
+
+
+@pytest.mark.parametrize("name", CASES)
 def test_detection_stagewise_bit_identical(name):
     vol, g, p, ref = _run(name)
     want = O.detect([[d.astype(np.float64) for d in Ds] for Ds in g["D"]], p)
