@@ -1083,9 +1083,8 @@ int sift3d_describe(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes, 
     a.n_units = (int)plan->units.size();
     if (a.n_units <= kInlineUnits)
         for (int u = 0; u < a.n_units; ++u) a.inl[u] = plan->units[u];
-    // four workgroups per CU are resident (LDS and registers); blocks loop over the keypoints
-    const int grid = (int)std::min<long long>((long long)kp_capacity * plan->n_vol, 1024);
-    const hipError_t e = launch_describe(a, grid, static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_describe(a, (long long)kp_capacity * plan->n_vol, plan->ctx->n_cu,
+                                         static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }
 

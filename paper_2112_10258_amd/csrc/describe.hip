@@ -1,13 +1,15 @@
 // Keypoint descriptors on gfx950: upright 3D SIFT-Rank (Section 2: 2x2x2
-// spatial x 8 orientation bins, normalised by ranking) and the BRIEF /
-// RRIEF descriptors (Section 3.2.3), in one launch. One workgroup (4
-// wavefronts) per keypoint; workgroups loop over the keypoint lists, whose
-// lengths are read from device memory, so the launch never waits on the
-// host. The keypoints of all volumes of a plan are dealt to the workgroups
-// as one flat sequence.
+// spatial x 8 orientation bins, normalised by ranking), one workgroup per
+// keypoint, and the BRIEF / RRIEF descriptors (Section 3.2.3), one
+// wavefront per keypoint. Workgroups (wavefronts) loop over the keypoint
+// lists, whose lengths are read from device memory, so the launches never
+// wait on the host. The keypoints of all volumes of a plan are dealt to
+// them as one flat sequence.
 //
 // Floating-point sums are accumulated in double precision in a fixed order
 // (no atomics), so results are bit-reproducible run to run.
+#include <algorithm>
+
 #include "sift3d_internal.h"
 
 namespace s3d {
@@ -24,8 +26,13 @@ constexpr int kSiftTile = 2 * kMaxSiftR + 3;
 // One (dx, dy) column of the SIFT-Rank window, read from the staged cube T
 // (T[k][j][i] = G_s at clamp(corner + (i, j, k)), corner = keypoint - R - 1):
 // the sample q = clamp(v + d) and its neighbours clamp(q +- 1) always fall
-// inside the cube, so each is one LDS read. |g| is accumulated per (z half,
-// orientation octant) in double.
+// inside the cube, so each is one LDS read. |g| is evaluated in single
+// precision (relative error <= 4.5 * 2^-24: the differences, squares, sum
+// and square root each round once) and accumulated per (z half,
+// orientation octant) in double. Bins are sums of positive terms, so each
+// carries the same relative error bound and two bins' difference is off by
+// at most 5.4e-7 of the largest bin. The octant signs are exact: a float
+// difference has the sign of the exact difference.
 template <int R>
 __device__ __forceinline__ void sift_column(const float *T, int nx, int ny, int nz, int kx, int ky, int kz, int dx,
                                             int dy, double (&acc)[16])
@@ -45,11 +52,11 @@ __device__ __forceinline__ void sift_column(const float *T, int nx, int ny, int 
         const float fxp = row[lxp], fxm = row[lxm];
         const float fyp = T[(lz * TW + lyp) * TW + lx], fym = T[(lz * TW + lym) * TW + lx];
         const float fzp = T[(lzp * TW + ly) * TW + lx], fzm = T[(lzm * TW + ly) * TW + lx];
-        const double gx = 0.5 * ((double)fxp - (double)fxm);
-        const double gy = 0.5 * ((double)fyp - (double)fym);
-        const double gz = 0.5 * ((double)fzp - (double)fzm);
-        const double m = sqrt(gx * gx + gy * gy + gz * gz);
-        const int bo = (gx > 0.0) + 2 * (gy > 0.0) + 4 * (gz > 0.0);
+        const float gx = 0.5f * (fxp - fxm);
+        const float gy = 0.5f * (fyp - fym);
+        const float gz = 0.5f * (fzp - fzm);
+        const double m = (double)__builtin_sqrtf(gx * gx + gy * gy + gz * gz);
+        const int bo = (gx > 0.0f) + 2 * (gy > 0.0f) + 4 * (gz > 0.0f);
         // dz is a compile-time constant here: a sample feeds only its z half
         // (both halves, with half weight, on the centre plane)
         if (dz < 0) {
@@ -109,23 +116,15 @@ __device__ __forceinline__ int first_of_block(int b, long long base, int grid)
     return (int)(r < 0 ? r + grid : r);
 }
 
-// One workgroup per keypoint, both descriptor families.
-//
-// SIFT-Rank. Each of the first (2R+1)^2 threads owns one (dx, dy) column of
-// the (2R+1)^3 window and walks dz, accumulating |g| per (z half,
-// orientation octant); the centre plane dz = 0 adds half to each z half.
-// The column sums are then added up within each of the 9 (sign dx, sign dy)
-// classes (144 threads, fixed order), and each of the 64 bins combines the 9
-// class sums with their x/y half weights, and is ranked.
-//
-// BRIEF / RRIEF. B_s is G_s already blurred by the sigma_b pre-blur (a
-// whole-level separable pass with the same clamp-to-edge rule, so B_s at a
-// voxel equals the pre-blur stencil evaluated there). Thread i owns pair i:
-// d_i = B_s(p1) - B_s(p2) is the exact double difference of the two samples,
-// its bit comes from a ballot and its rank from a bitonic sort of the
-// (d_i, i) pairs (wavefront shuffles, LDS for the cross-wavefront stages).
+// SIFT-Rank, one workgroup per keypoint. Each of the first (2R+1)^2 threads
+// owns one (dx, dy) column of the (2R+1)^3 window and walks dz,
+// accumulating |g| per (z half, orientation octant); the centre plane dz = 0
+// adds half to each z half. The column sums are then added up within each
+// of the 9 (sign dx, sign dy) classes (row sums per x class, then over the
+// rows of each y class, in a fixed order), and each of the 64 bins combines
+// the 9 class sums with their x/y half weights, and is ranked.
 template <bool INL>
-__global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLaunch a)
+__global__ void __launch_bounds__(kDescThreads, 4) siftrank_kernel(const DescLaunch a)
 {
     constexpr int kCols = (2 * kMaxSiftR + 1) * (2 * kMaxSiftR + 1);
     static_assert(kCols <= kDescThreads, "one thread per window column");
@@ -135,14 +134,10 @@ __global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLau
     __shared__ __align__(16) char scratch[kPartBytes > kTileFloats * 4 ? kPartBytes : kTileFloats * 4];
     float *const T = reinterpret_cast<float *>(scratch);
     double(*const part)[17] = reinterpret_cast<double(*)[17]>(scratch);
+    __shared__ double rows[2 * kMaxSiftR + 1][3][16];   // per (row, x class) sums
     __shared__ double cls[9][16];
     __shared__ double hist[64];
-    __shared__ double sk[kMaxPairs];    // RRIEF sort keys (difference, pair index)
-    __shared__ int si[kMaxPairs];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n = a.brief_n, nw = n / 64;
-    const bool do_sr = a.siftrank != nullptr;
-    const bool do_br = (a.brief != nullptr || a.rrief != nullptr) && n > 0;
+    const int tid = threadIdx.x;
     long long base = 0;
     for (int v = 0; v < a.n_vol; ++v) {
     const int count = min(a.counts[v], a.cap);
@@ -152,76 +147,66 @@ __global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLau
         const sift3d_keypoint kp = a.kp[k];
         if (kp.octave < 0 || kp.octave >= vol.n_units || kp.scale < 1 || kp.scale > a.S) {
             // not a keypoint of this plan
-            if (do_sr && tid < 64) a.siftrank[k * 64 + tid] = 0;
-            if (a.rrief != nullptr && tid < n) a.rrief[k * n + tid] = 0;
-            if (a.brief != nullptr && tid < nw) a.brief[k * nw + tid] = 0;
+            if (tid < 64) a.siftrank[k * 64 + tid] = 0;
             continue;
         }
         const DUnit &oc = (INL ? a.inl[vol.unit0 + kp.octave] : a.units[vol.unit0 + kp.octave]);
         const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
-
-        // BRIEF samples first: their loads overlap the SIFT-Rank work
-        double d = 0.0;
-        if (do_br && tid < n) {
-            const float *B = reinterpret_cast<const float *>(a.ws + oc.b1) + oc.lstride * (kp.scale - 1);
-            const int32_t *o = a.pairs + ((size_t)(kp.scale - 1) * n + tid) * 6;
-            const int x1 = clampi(kp.x + o[0], 0, nx - 1), y1 = clampi(kp.y + o[1], 0, ny - 1);
-            const int z1 = clampi(kp.z + o[2], 0, nz - 1);
-            const int x2 = clampi(kp.x + o[3], 0, nx - 1), y2 = clampi(kp.y + o[4], 0, ny - 1);
-            const int z2 = clampi(kp.z + o[5], 0, nz - 1);
-            const float b1 = B[((size_t)z1 * ny + y1) * nx + x1];
-            const float b2 = B[((size_t)z2 * ny + y2) * nx + x2];
-            d = (double)b1 - (double)b2;
+        const float *G = reinterpret_cast<const float *>(a.ws + oc.g0) + oc.lstride * kp.scale;
+        const int R = a.sift_R[kp.scale];
+        const int W = 2 * R + 1;
+        double acc[16];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) acc[b] = 0.0;
+        switch (R) {
+        case 1: sift_window<1>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+        case 2: sift_window<2>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+        case 3: sift_window<3>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+        case 4: sift_window<4>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+        case 5: sift_window<5>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+        case 6: sift_window<6>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+        default: sift_window<7>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
         }
-
-        if (do_sr) {
-            const float *G = reinterpret_cast<const float *>(a.ws + oc.g0) + oc.lstride * kp.scale;
-            const int R = a.sift_R[kp.scale];
-            const int W = 2 * R + 1;
-            double acc[16];
+        __syncthreads();   // the column sums overwrite the staged cube
+        if (tid < W * W) {
 #pragma unroll
-            for (int b = 0; b < 16; ++b) acc[b] = 0.0;
-            switch (R) {
-            case 1: sift_window<1>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-            case 2: sift_window<2>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-            case 3: sift_window<3>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-            case 4: sift_window<4>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-            case 5: sift_window<5>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-            case 6: sift_window<6>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-            default: sift_window<7>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-            }
-            __syncthreads();   // the column sums overwrite the staged cube
-            if (tid < W * W) {
-#pragma unroll
-                for (int b = 0; b < 16; ++b) part[tid][b] = acc[b];
-            }
-            __syncthreads();
-            if (tid < 144) {
-                // class q = (cy, cx), value j: columns with dx, dy in the class ranges
-                const int q = tid >> 4, j = tid & 15;
-                const int cy = q / 3, cx = q - cy * 3;
-                const int y0 = cy == 0 ? 0 : (cy == 1 ? R : R + 1), y1 = cy == 0 ? R : (cy == 1 ? R + 1 : W);
-                const int x0 = cx == 0 ? 0 : (cx == 1 ? R : R + 1), x1 = cx == 0 ? R : (cx == 1 ? R + 1 : W);
-                double sum = 0.0;
-                for (int yy = y0; yy < y1; ++yy)
-                    for (int xx = x0; xx < x1; ++xx) sum += part[yy * W + xx][j];
-                cls[q][j] = sum;
-            }
-            __syncthreads();
-            if (tid < 64) {
-                const int bs = tid >> 3, bo = tid & 7;
-                const int bx = bs & 1, by = (bs >> 1) & 1, bz = bs >> 2;
-                double h = 0.0;
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    const int cy = q / 3, cx = q - cy * 3;
-                    h += (half_weight(cx, bx) * half_weight(cy, by)) * cls[q][8 * bz + bo];
-                }
-                hist[tid] = h;
-            }
+            for (int b = 0; b < 16; ++b) part[tid][b] = acc[b];
         }
         __syncthreads();
-        if (do_sr && tid < 64) {
+        // class sums in two steps (each a chain of at most R adds): along x
+        // within each row and x class, then over the rows of each y class
+        for (int item = tid; item < W * 48; item += kDescThreads) {
+            const int yy = item / 48, rem = item - yy * 48;
+            const int cx = rem >> 4, j = rem & 15;
+            const int x0 = cx == 0 ? 0 : (cx == 1 ? R : R + 1), x1 = cx == 0 ? R : (cx == 1 ? R + 1 : W);
+            double sum = 0.0;
+            for (int xx = x0; xx < x1; ++xx) sum += part[yy * W + xx][j];
+            rows[yy][cx][j] = sum;
+        }
+        __syncthreads();
+        if (tid < 144) {
+            // class q = (cy, cx), value j: columns with dx, dy in the class ranges
+            const int q = tid >> 4, j = tid & 15;
+            const int cy = q / 3, cx = q - cy * 3;
+            const int y0 = cy == 0 ? 0 : (cy == 1 ? R : R + 1), y1 = cy == 0 ? R : (cy == 1 ? R + 1 : W);
+            double sum = 0.0;
+            for (int yy = y0; yy < y1; ++yy) sum += rows[yy][cx][j];
+            cls[q][j] = sum;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int bs = tid >> 3, bo = tid & 7;
+            const int bx = bs & 1, by = (bs >> 1) & 1, bz = bs >> 2;
+            double h = 0.0;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int cy = q / 3, cx = q - cy * 3;
+                h += (half_weight(cx, bx) * half_weight(cy, by)) * cls[q][8 * bz + bo];
+            }
+            hist[tid] = h;
+        }
+        __syncthreads();
+        if (tid < 64) {
             const double h = hist[tid];
             int r = 0;
 #pragma unroll 8
@@ -231,47 +216,126 @@ __global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLau
             }
             a.siftrank[k * 64 + tid] = (uint8_t)r;
         }
-        if (do_br && tid < n) {
-            const unsigned long long m = __ballot(d > 0.0);
-            if (a.brief != nullptr && lane == 0) a.brief[k * nw + wave] = m;
+        __syncthreads();
+    }
+    base += count;
+    }
+}
+
+// BRIEF / RRIEF, one wavefront per keypoint (four per workgroup, each on
+// its own keypoints). B_s is G_s already blurred by the sigma_b pre-blur (a
+// whole-level separable pass with the same clamp-to-edge rule, so B_s at a
+// voxel equals the pre-blur stencil evaluated there). Lane l holds pairs
+// 64 j + l, j < 4: d = B_s(p1) - B_s(p2) is the exact double difference of
+// the two samples; word j of the binary descriptor is the ballot of d > 0
+// over register j. RRIEF ranks (position of (d_i, i) in ascending
+// lexicographic order, i.e. #{m : d_m < d_i or (d_m == d_i and m < i)})
+// come from a bitonic sort of the 256 (difference, index) pairs (n padded
+// with +inf keys, which sort after every finite difference) held as
+// element 64 j + l: partners 64 or 128 apart are registers of the same
+// lane, the others are lanes of the same register. No barriers, no LDS.
+constexpr int kBriefRegs = kMaxPairs / 64;
+
+__device__ __forceinline__ bool pair_gt(double ka, int ia, double kb, int ib)
+{
+    return ka > kb || (ka == kb && ia > ib);
+}
+
+template <bool INL>
+__global__ void __launch_bounds__(kDescThreads) brief_kernel(const DescLaunch a)
+{
+    const int lane = threadIdx.x & 63;
+    // wave index: uniform across the wave
+    const int gw = __builtin_amdgcn_readfirstlane(blockIdx.x * (kDescThreads / 64) + (threadIdx.x >> 6));
+    const int nwaves = gridDim.x * (kDescThreads / 64);
+    const int n = a.brief_n, nw = n / 64;
+    long long base = 0;
+    for (int v = 0; v < a.n_vol; ++v) {
+    const int count = min(a.counts[v], a.cap);
+    const DVol vol = a.vols[v];
+    for (int kk = first_of_block(gw, base, nwaves); kk < count; kk += nwaves) {
+        const size_t k = (size_t)v * a.cap + kk;
+        const sift3d_keypoint kp = a.kp[k];
+        if (kp.octave < 0 || kp.octave >= vol.n_units || kp.scale < 1 || kp.scale > a.S) {
+            // not a keypoint of this plan
+#pragma unroll
+            for (int j = 0; j < kBriefRegs; ++j) {
+                const int i = 64 * j + lane;
+                if (a.rrief != nullptr && i < n) a.rrief[k * n + i] = 0;
+            }
+            if (a.brief != nullptr && lane < nw) a.brief[k * nw + lane] = 0;
+            continue;
         }
-        if (do_br && a.rrief != nullptr) {
-            // rank of d_i among the n: #{j : d_j < d_i or (d_j == d_i and j < i)},
-            // i.e. the position of (d_i, i) in ascending lexicographic order, by a
-            // bitonic sort of the (difference, index) pairs held one per thread
-            // (n padded to 256 with +inf keys, which sort after every finite
-            // difference). Partners within a wavefront exchange by shuffles;
-            // only the stages with partners 64 or 128 threads away go through LDS.
-            double key = tid < n ? d : __builtin_inf();
-            int idx = tid;
-#pragma unroll 1
+        const DUnit &oc = (INL ? a.inl[vol.unit0 + kp.octave] : a.units[vol.unit0 + kp.octave]);
+        const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
+        const float *B = reinterpret_cast<const float *>(a.ws + oc.b1) + oc.lstride * (kp.scale - 1);
+        double key[kBriefRegs];
+        int idx[kBriefRegs];
+#pragma unroll
+        for (int j = 0; j < kBriefRegs; ++j) {
+            const int i = 64 * j + lane;
+            idx[j] = i;
+            key[j] = __builtin_inf();
+            if (i < n) {
+                const int32_t *o = a.pairs + ((size_t)(kp.scale - 1) * n + i) * 6;
+                const int x1 = clampi(kp.x + o[0], 0, nx - 1), y1 = clampi(kp.y + o[1], 0, ny - 1);
+                const int z1 = clampi(kp.z + o[2], 0, nz - 1);
+                const int x2 = clampi(kp.x + o[3], 0, nx - 1), y2 = clampi(kp.y + o[4], 0, ny - 1);
+                const int z2 = clampi(kp.z + o[5], 0, nz - 1);
+                const float b1 = B[((size_t)z1 * ny + y1) * nx + x1];
+                const float b2 = B[((size_t)z2 * ny + y2) * nx + x2];
+                key[j] = (double)b1 - (double)b2;
+            }
+        }
+        if (a.brief != nullptr) {
+#pragma unroll
+            for (int j = 0; j < kBriefRegs; ++j) {
+                const unsigned long long m = __ballot(key[j] > 0.0);   // +inf pads only past n
+                if (j < nw && lane == 0) a.brief[k * nw + j] = m;
+            }
+        }
+        if (a.rrief != nullptr) {
+#pragma unroll
             for (int kk2 = 2; kk2 <= kMaxPairs; kk2 <<= 1) {
-#pragma unroll 1
-                for (int j = kk2 >> 1; j > 0; j >>= 1) {
-                    double pk;
-                    int pi;
-                    if (j >= 64) {
-                        sk[tid] = key;
-                        si[tid] = idx;
-                        __syncthreads();
-                        pk = sk[tid ^ j];
-                        pi = si[tid ^ j];
-                        __syncthreads();
+#pragma unroll
+                for (int jj = kk2 >> 1; jj > 0; jj >>= 1) {
+                    if (jj >= 64) {
+                        const int jr = jj >> 6;
+#pragma unroll
+                        for (int j = 0; j < kBriefRegs; ++j) {
+                            if (j & jr) continue;
+                            const int j2 = j | jr;
+                            const bool up = ((64 * j + lane) & kk2) == 0;
+                            // the lower element keeps the smaller pair on an ascending run
+                            if (pair_gt(key[j], idx[j], key[j2], idx[j2]) == up) {
+                                const double tk = key[j];
+                                const int ti = idx[j];
+                                key[j] = key[j2];
+                                idx[j] = idx[j2];
+                                key[j2] = tk;
+                                idx[j2] = ti;
+                            }
+                        }
                     } else {
-                        pk = __shfl_xor(key, j);
-                        pi = __shfl_xor(idx, j);
-                    }
-                    const bool gt = key > pk || (key == pk && idx > pi);
-                    const bool up = (tid & kk2) == 0, lower = (tid & j) == 0;
-                    if (lower == up ? gt : !gt) {
-                        key = pk;
-                        idx = pi;
+                        const bool lower = (lane & jj) == 0;
+#pragma unroll
+                        for (int j = 0; j < kBriefRegs; ++j) {
+                            const double pk = __shfl_xor(key[j], jj);
+                            const int pi = __shfl_xor(idx[j], jj);
+                            const bool up = ((64 * j + lane) & kk2) == 0;
+                            const bool gt = pair_gt(key[j], idx[j], pk, pi);
+                            if (lower == up ? gt : !gt) {
+                                key[j] = pk;
+                                idx[j] = pi;
+                            }
+                        }
                     }
                 }
             }
-            if (idx < n) a.rrief[k * n + idx] = (uint8_t)tid;
+#pragma unroll
+            for (int j = 0; j < kBriefRegs; ++j)
+                if (idx[j] < n) a.rrief[k * n + idx[j]] = (uint8_t)(64 * j + lane);
         }
-        __syncthreads();
     }
     base += count;
     }
@@ -279,16 +343,42 @@ __global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLau
 
 }  // namespace
 
-hipError_t launch_describe(const DescLaunch &a, int grid, hipStream_t st)
+// Workgroups of `k` resident on one CU (registers and LDS), at least 1.
+template <typename K>
+static int blocks_per_cu(K k)
 {
-    if (grid <= 0) return hipSuccess;
-    if (a.siftrank == nullptr && (a.brief == nullptr && a.rrief == nullptr)) return hipSuccess;
-    if (a.brief_n < 0 || a.brief_n > kDescThreads || a.brief_n % 64 != 0) return hipErrorInvalidValue;
-    if (a.n_units <= kInlineUnits)
-        hipLaunchKernelGGL(describe_kernel<true>, dim3(grid), dim3(kDescThreads), 0, st, a);
-    else
-        hipLaunchKernelGGL(describe_kernel<false>, dim3(grid), dim3(kDescThreads), 0, st, a);
-    return hipGetLastError();
+    int n = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kDescThreads, 0) == hipSuccess && n > 0 ? n : 1;
+}
+
+// Grids: enough workgroups to fill every resident slot once (the kernels
+// loop over the keypoints), and no more than the keypoint slots need.
+hipError_t launch_describe(const DescLaunch &a, long long kp_slots, int n_cu, hipStream_t st)
+{
+    if (a.brief_n < 0 || a.brief_n > kMaxPairs || a.brief_n % 64 != 0) return hipErrorInvalidValue;
+    if (kp_slots <= 0) return hipSuccess;
+    const bool inl = a.n_units <= kInlineUnits;
+    if (a.siftrank != nullptr) {
+        static const int per_cu = blocks_per_cu(siftrank_kernel<true>);
+        const int grid = (int)std::min<long long>(kp_slots, (long long)per_cu * n_cu);
+        if (inl)
+            hipLaunchKernelGGL(siftrank_kernel<true>, dim3(grid), dim3(kDescThreads), 0, st, a);
+        else
+            hipLaunchKernelGGL(siftrank_kernel<false>, dim3(grid), dim3(kDescThreads), 0, st, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if ((a.brief != nullptr || a.rrief != nullptr) && a.brief_n > 0) {
+        static const int per_cu = blocks_per_cu(brief_kernel<true>);
+        const int waves = kDescThreads / 64;
+        const int grid = (int)std::min<long long>((kp_slots + waves - 1) / waves, (long long)per_cu * n_cu);
+        if (inl)
+            hipLaunchKernelGGL(brief_kernel<true>, dim3(grid), dim3(kDescThreads), 0, st, a);
+        else
+            hipLaunchKernelGGL(brief_kernel<false>, dim3(grid), dim3(kDescThreads), 0, st, a);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 }  // namespace s3d

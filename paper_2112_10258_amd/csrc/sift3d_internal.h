@@ -355,7 +355,7 @@ hipError_t launch_blur_xy(const XYLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_blur_z(const ZLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_blur_compact(const CompactLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_detect(const DetLaunch &a, hipStream_t st);
-hipError_t launch_describe(const DescLaunch &a, int grid, hipStream_t st);
+hipError_t launch_describe(const DescLaunch &a, long long kp_slots, int n_cu, hipStream_t st);
 
 // Workspace levels of an octave, in units of one padded level.
 inline int lev_G(int i) { return i; }
