@@ -14,6 +14,8 @@
 //          each volume's total;
 //   emit:  blocks with keypoints write each one at (block offset - the
 //          volume's first offset) + row prefix + rank within the row.
+#include <type_traits>
+
 #include "sift3d_internal.h"
 
 namespace s3d {
@@ -276,23 +278,45 @@ __global__ void __launch_bounds__(kScanThreads) detect_scan_kernel(const DetLaun
 // current one is reduced. No LDS, no barriers. Ballots of the flags are
 // the 64-bit words of the per-row keypoint bit masks (bit l of word t is
 // x = 62 t + l).
+
+// Rows y-1, y, y+1 of plane pz of every level, as buffer loads: each plane
+// is a buffer resource built in scalar registers (base, size), the per-lane
+// part is a 32-bit byte offset inside the plane (a plane is at most 2^30
+// floats), so a load costs no per-lane address arithmetic (plain global
+// loads made the compiler add a 64-bit per-lane address for every row).
+// Offsets stay inside the plane (clamped rows, clamped x).
+constexpr int kRawBufferWord3 = 0x00020000;   // dword 3 of a raw (untyped) buffer resource on gfx9
+
 template <int NL>
-__device__ __forceinline__ void load_plane_rows(const float *D, long long lstride, int nx, int ny, int pz, int x,
-                                                int y, float (&v)[NL][3])
+__device__ __forceinline__ void load_plane_rows(const float *D, long long lstride, long long nxy, int pz,
+                                                const unsigned (&boff)[3], float (&v)[NL][3])
 {
-    const long long nxy = (long long)nx * ny;
+    const int bytes = (int)(unsigned)min(nxy * 4, 0xffffffffLL);   // bound of the offsets (unsigned)
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-        const float *pl = D + lstride * l + pz * nxy;
+        const float *pl = D + lstride * l + (long long)pz * nxy;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(pl), (short)0, bytes, kRawBufferWord3);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) v[l][r] = pl[(long long)min(max(y - 1 + r, 0), ny - 1) * nx + x];
+        for (int r = 0; r < 3; ++r) v[l][r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)boff[r], 0, 0));
     }
 }
 
-// Value of the lane to the left / right (whole-wave DPP shift; the edge
-// lanes get their own value, they are halo).
-__device__ __forceinline__ float from_left(float v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false); }
-__device__ __forceinline__ float from_right(float v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false); }
+// f(std::integral_constant<int, P>) for P = I .. N-1 (compile-time P in f).
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// Value of the lane to the left / right (whole-wave DPP shift). Lane 0
+// (left) and lane 63 (right) have no source and read 0: they are halo
+// lanes, whose own results are never used.
+__device__ __forceinline__ float from_left(float v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ float from_right(float v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
 
 template <int S, bool INL>
 __global__ void __launch_bounds__(256) detect_tile_kernel(const DetLaunch a)
@@ -315,8 +339,12 @@ __global__ void __launch_bounds__(256) detect_tile_kernel(const DetLaunch a)
     const int x = min(xl, nx - 1);
     const bool in_x = lane >= 1 && lane <= kDTXOut && xl <= nx - 2;
 
+    // Rings over the planes, indexed by plane number: M/m[l][k % 3] = 3x3
+    // max/min of level l at plane k, cen/rx/rn[s][k % 2] = centre value and
+    // 8-ring max/min of D_s at plane k, v[k % 2] = the rows of plane k (the
+    // plane loop is unrolled by 6, so every slot is a fixed register).
     float M[NL][3], m[NL][3];
-    float cen[S + 1][2], rx[S + 1][2], rn[S + 1][2];   // [.][0] previous plane, [.][1] current
+    float cen[S + 1][2], rx[S + 1][2], rn[S + 1][2];
 #pragma unroll
     for (int l = 0; l < NL; ++l)
 #pragma unroll
@@ -324,64 +352,65 @@ __global__ void __launch_bounds__(256) detect_tile_kernel(const DetLaunch a)
 #pragma unroll
     for (int l = 0; l <= S; ++l) cen[l][0] = cen[l][1] = rx[l][0] = rx[l][1] = rn[l][0] = rn[l][1] = 0.f;
 
-    float v[NL][3], vn[NL][3];
-    load_plane_rows<NL>(D, un.lstride, nx, ny, z0 - 1, x, y, v);
+    const long long nxy = (long long)nx * ny;
+    unsigned roff[3];   // byte offsets of rows y-1, y, y+1 at column x
+#pragma unroll
+    for (int r = 0; r < 3; ++r) roff[r] = 4u * (unsigned)(min(max(y - 1 + r, 0), ny - 1) * nx + x);
+    float v[2][NL][3];
+    load_plane_rows<NL>(D, un.lstride, nxy, z0 - 1, roff, v[0]);
     const int nplanes = (z1 - z0) + 2;
-    for (int k = 0; k < nplanes; ++k) {
-        if (k + 1 < nplanes) load_plane_rows<NL>(D, un.lstride, nx, ny, z0 + k, x, y, vn);
+    for (int base = 0; base < nplanes; base += 6) {
+        static_for<0, 6>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int b = p % 2, nb = (p + 1) % 2;          // plane buffers of k, k+1
+            constexpr int q0 = (p + 1) % 3, q1 = (p + 2) % 3, q2 = p % 3;   // M slots of k-2, k-1, k
+            constexpr int c0 = (p + 1) % 2, c1 = p % 2;          // cen/rx/rn slots of k-1, k
+            const int k = base + p;
+            if (k >= nplanes) return;
+            if (k + 1 < nplanes) load_plane_rows<NL>(D, un.lstride, nxy, z0 + k, roff, v[nb]);
 #pragma unroll
-        for (int l = 0; l < NL; ++l) {
-            float hx[3], hn[3], left1 = 0.f, right1 = 0.f;
+            for (int l = 0; l < NL; ++l) {
+                float hx[3], hn[3], left1 = 0.f, right1 = 0.f;
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const float left = from_left(v[l][r]);
-                const float right = from_right(v[l][r]);
-                hx[r] = fmaxf(fmaxf(left, right), v[l][r]);
-                hn[r] = fminf(fminf(left, right), v[l][r]);
-                if (r == 1) {
-                    left1 = left;
-                    right1 = right;
+                for (int r = 0; r < 3; ++r) {
+                    const float left = from_left(v[b][l][r]);
+                    const float right = from_right(v[b][l][r]);
+                    hx[r] = fmaxf(fmaxf(left, right), v[b][l][r]);
+                    hn[r] = fminf(fminf(left, right), v[b][l][r]);
+                    if (r == 1) {
+                        left1 = left;
+                        right1 = right;
+                    }
+                }
+                M[l][q2] = fmaxf(fmaxf(hx[0], hx[1]), hx[2]);
+                m[l][q2] = fminf(fminf(hn[0], hn[1]), hn[2]);
+                if (l >= 1 && l <= S) {
+                    cen[l][c1] = v[b][l][1];
+                    rx[l][c1] = fmaxf(fmaxf(hx[0], hx[2]), fmaxf(left1, right1));
+                    rn[l][c1] = fminf(fminf(hn[0], hn[2]), fminf(left1, right1));
                 }
             }
-            M[l][0] = M[l][1];
-            M[l][1] = M[l][2];
-            M[l][2] = fmaxf(fmaxf(hx[0], hx[1]), hx[2]);
-            m[l][0] = m[l][1];
-            m[l][1] = m[l][2];
-            m[l][2] = fminf(fminf(hn[0], hn[1]), hn[2]);
-            if (l >= 1 && l <= S) {
-                cen[l][0] = cen[l][1];
-                cen[l][1] = v[l][1];
-                rx[l][0] = rx[l][1];
-                rx[l][1] = fmaxf(fmaxf(hx[0], hx[2]), fmaxf(left1, right1));
-                rn[l][0] = rn[l][1];
-                rn[l][1] = fminf(fminf(hn[0], hn[2]), fminf(left1, right1));
-            }
-        }
-        if (k >= 2) {
-            const int z = z0 + k - 2;
-            const long long row_z = (long long)(z - 1) * (ny - 2) + (y - 1);
+            if (k >= 2) {
+                const int z = z0 + k - 2;
+                const long long row_z = (long long)(z - 1) * (ny - 2) + (y - 1);
 #pragma unroll
-            for (int s = 1; s <= S; ++s) {
-                const float vv = cen[s][0];
-                float mx = fmaxf(fmaxf(M[s - 1][0], M[s - 1][1]), M[s - 1][2]);
-                mx = fmaxf(mx, fmaxf(fmaxf(M[s + 1][0], M[s + 1][1]), M[s + 1][2]));
-                mx = fmaxf(mx, fmaxf(fmaxf(M[s][0], M[s][2]), rx[s][0]));
-                float mn = fminf(fminf(m[s - 1][0], m[s - 1][1]), m[s - 1][2]);
-                mn = fminf(mn, fminf(fminf(m[s + 1][0], m[s + 1][1]), m[s + 1][2]));
-                mn = fminf(mn, fminf(fminf(m[s][0], m[s][2]), rn[s][0]));
-                const bool flag = in_x && fabsf(vv) > a.thr && (vv > mx || vv < mn);
-                const unsigned long long bits = __ballot(flag);
-                if (lane == 0) {
-                    const long long row = (long long)(s - 1) * (nz - 2) * (ny - 2) + row_z;
-                    masks[row * un.words + txi] = bits;
+                for (int s = 1; s <= S; ++s) {
+                    const float vv = cen[s][c0];
+                    float mx = fmaxf(fmaxf(M[s - 1][q0], M[s - 1][q1]), M[s - 1][q2]);
+                    mx = fmaxf(mx, fmaxf(fmaxf(M[s + 1][q0], M[s + 1][q1]), M[s + 1][q2]));
+                    mx = fmaxf(mx, fmaxf(fmaxf(M[s][q0], M[s][q2]), rx[s][c0]));
+                    float mn = fminf(fminf(m[s - 1][q0], m[s - 1][q1]), m[s - 1][q2]);
+                    mn = fminf(mn, fminf(fminf(m[s + 1][q0], m[s + 1][q1]), m[s + 1][q2]));
+                    mn = fminf(mn, fminf(fminf(m[s][q0], m[s][q2]), rn[s][c0]));
+                    const bool flag = in_x && fabsf(vv) > a.thr && (vv > mx || vv < mn);
+                    const unsigned long long bits = __ballot(flag);
+                    if (lane == 0) {
+                        const long long row = (long long)(s - 1) * (nz - 2) * (ny - 2) + row_z;
+                        masks[row * un.words + txi] = bits;
+                    }
                 }
             }
-        }
-#pragma unroll
-        for (int l = 0; l < NL; ++l)
-#pragma unroll
-            for (int r = 0; r < 3; ++r) v[l][r] = vn[l][r];
+        });
     }
 }
 
