@@ -119,6 +119,8 @@ int sift3d_pair_offsets(const sift3d_params *p, const double *pair_draws, int n_
  * offsets only) uploaded synchronously; freed by sift3d_plan_destroy.
  * kp_capacity >= 0 is the size of the caller's keypoint and descriptor
  * buffers per volume. The plan keeps a pointer to ctx, which must outlive it.
+ * Shapes: nx, ny, nz >= 1, nx * ny <= 2^28 (a plane of at most 1 GiB) and
+ * nx * ny * nz <= 2^40; SIFT3D_E_ARG otherwise.
  */
 int sift3d_plan_create(sift3d_ctx *ctx, int nx, int ny, int nz, int kp_capacity, sift3d_plan **out);
 

@@ -13,6 +13,28 @@ namespace fused {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// Plane accesses go through buffer resources: a plane's base and size sit
+// in scalar registers and each lane adds a 32-bit byte offset, so loads and
+// stores cost no per-lane 64-bit address arithmetic. A store whose offset
+// is kDropOffset lies past every plane (planes are at most 1 GiB) and is
+// discarded by the hardware range check: out-of-volume lanes store
+// unconditionally instead of branching around the store.
+constexpr int kRawBufferWord3 = 0x00020000;   // dword 3 of a raw (untyped) buffer resource on gfx9
+constexpr unsigned kDropOffset = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, (int)bytes, kRawBufferWord3);
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t rs, unsigned boff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)boff, 0, 0));
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t rs, unsigned boff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, (int)boff, 0, 0);
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
 // b % 8). Remap so that each XCD receives one contiguous range of logical
 // tiles: neighbouring tiles then share their halo rows in that XCD's L2.
@@ -117,8 +139,9 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
     const int z1 = min(z0 + jb.L, jb.nz);
     const int nx = jb.nx, ny = jb.ny, nz = jb.nz;
     const size_t nxy = (size_t)nx * ny;
+    const unsigned plane_bytes = (unsigned)(nxy * sizeof(float));
 
-    // Per-thread staging slots: the same in-plane offsets for every plane.
+    // Per-thread staging slots: the same in-plane byte offsets for every plane.
     unsigned goff[KL];
     int loff[KL];
 #pragma unroll
@@ -126,7 +149,7 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
         const int idx = tid + k * NT;
         if (idx < AE) {
             const int r = idx / AWL, c = idx - r * AWL;
-            goff[k] = (unsigned)(clampi(y0 - R + r, 0, ny - 1) * nx + clampi(x0 - R + c, 0, nx - 1));
+            goff[k] = 4u * (unsigned)(clampi(y0 - R + r, 0, ny - 1) * nx + clampi(x0 - R + c, 0, nx - 1));
             loff[k] = r * AW + c;
         } else {
             goff[k] = 0;
@@ -135,9 +158,9 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
     }
     float pre[KL];
     auto load_plane = [&](int zi) {
-        const float *p = src + (size_t)clampi(zi, 0, nz - 1) * nxy;
+        const auto rs = plane_rsrc(src + (size_t)clampi(zi, 0, nz - 1) * nxy, plane_bytes);
 #pragma unroll
-        for (int k = 0; k < KL; ++k) pre[k] = p[goff[k]];
+        for (int k = 0; k < KL; ++k) pre[k] = buf_load(rs, goff[k]);
     };
 
     float w[M];
@@ -159,9 +182,15 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
     const int tx = tid % TX;
     const int tyb = (tid / TX) * NY;
     const int gx = x0 + tx, gy0 = y0 + tyb;
-    const bool ok0 = gx < nx && gy0 < ny, ok1 = gx < nx && gy0 + 1 < ny;
-    const unsigned o0 = (unsigned)(min(gy0, ny - 1) * nx + min(gx, nx - 1));
-    const unsigned o1 = (unsigned)(min(gy0 + 1, ny - 1) * nx + min(gx, nx - 1));
+    // byte offsets of the thread's two outputs in a plane (kDropOffset outside the volume)
+    const unsigned o0 = gx < nx && gy0 < ny ? 4u * (unsigned)(gy0 * nx + gx) : kDropOffset;
+    const unsigned o1 = gx < nx && gy0 + 1 < ny ? 4u * (unsigned)((gy0 + 1) * nx + gx) : kDropOffset;
+    // byte offset of the 2x2x2 mean this thread writes in a plane of the next
+    // octave's G_0 (even x, the thread holding both rows of the y pair)
+    const int sub_plane = jb.mx * jb.my;
+    const unsigned so = (tx & 1) == 0 && (gx >> 1) < jb.mx && (gy0 >> 1) < jb.my
+                            ? 4u * (unsigned)((gy0 >> 1) * jb.mx + (gx >> 1))
+                            : kDropOffset;
     float ring[NY][M];
 #pragma unroll
     for (int j = 0; j < NY; ++j)
@@ -254,12 +283,10 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
                 // its centre plane is an output plane of this slab from step R + RB on
                 const int qz = z0 - R + it - RB;
                 if (it >= R + RB && qz < z1) {
-                    float *d = pbp + (size_t)qz * nxy;
+                    const auto rs = plane_rsrc(pbp + (size_t)qz * nxy, plane_bytes);
 #pragma unroll
-                    for (int j = 0; j < NY; ++j) {
-                        const float v = sym_stencil<RB>(wb, [&](int t) { return ringb[j][t]; });
-                        if (j == 0 ? ok0 : ok1) d[j == 0 ? o0 : o1] = v;
-                    }
+                    for (int j = 0; j < NY; ++j)
+                        buf_store(rs, j == 0 ? o0 : o1, sym_stencil<RB>(wb, [&](int t) { return ringb[j][t]; }));
                 }
             }
 
@@ -269,23 +296,22 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
 #pragma unroll
                 for (int j = 0; j < NY; ++j)
                     zo[j] = sym_stencil<R>(w, [&](int t) { return ring[j][(p + 1 + t) % M]; });
-                float *d = dst + (size_t)oz * nxy;
-                if (ok0) d[o0] = zo[0];
-                if (ok1) d[o1] = zo[1];
+                const auto rd = plane_rsrc(dst + (size_t)oz * nxy, plane_bytes);
+                buf_store(rd, o0, zo[0]);
+                buf_store(rd, o1, zo[1]);
                 if constexpr (DOG) {
-                    float *e = dogp + (size_t)oz * nxy;
-                    if (ok0) e[o0] = cv0 - zo[0];
-                    if (ok1) e[o1] = cv1 - zo[1];
+                    const auto re = plane_rsrc(dogp + (size_t)oz * nxy, plane_bytes);
+                    buf_store(re, o0, cv0 - zo[0]);
+                    buf_store(re, o1, cv1 - zo[1]);
                 }
                 if (subp != nullptr) {
                     const float s2 = zo[0] + zo[1];
                     const float s4 = s2 + __shfl_xor(s2, 1);
                     if ((oz & 1) == 0) {
                         subacc = s4;
-                    } else {
-                        const int X = gx >> 1, Y = gy0 >> 1, Z = oz >> 1;
-                        if ((tx & 1) == 0 && X < jb.mx && Y < jb.my && Z < jb.mz)
-                            subp[((size_t)Z * jb.my + Y) * jb.mx + X] = (subacc + s4) * 0.125f;
+                    } else if ((oz >> 1) < jb.mz) {
+                        const auto rsub = plane_rsrc(subp + (size_t)(oz >> 1) * sub_plane, 4u * (unsigned)sub_plane);
+                        buf_store(rsub, so, (subacc + s4) * 0.125f);
                     }
                 }
             }

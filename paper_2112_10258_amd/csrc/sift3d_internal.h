@@ -53,6 +53,7 @@ constexpr long long kFusedMinVoxels = 24LL << 20;
 constexpr long long kFusedMidVoxels = 2LL << 20;
 constexpr int kFusedMidMaxR = 8;
 constexpr int kMaxFusedR = 10;              // largest tap radius of the fused pass
+constexpr int kMinSlabPlanes = 12;          // shortest slab of a fused launch (output planes)
 // Pre-blur radius that the fused pass can write alongside a level: pass
 // G_{s+1} stages G_s with a halo of R >= kFusedPreR, so it also writes B_s.
 constexpr int kFusedPreR = 3;

@@ -162,6 +162,16 @@ def test_determinism_bitwise():
         assert np.array_equal(a[f], b[f])
 
 
+def test_plan_rejects_oversized_planes():
+    """Planes are addressed with 32-bit byte offsets: nx * ny above 2^28 is
+    refused at plan time (no launch), 2^28 itself is accepted by the check."""
+    import paper_2112_10258_amd as S
+    ctx = S.Context(S.default_params(), P.pair_draws())
+    with pytest.raises(S.Sift3dError) as ei:
+        S.Plan(ctx, (1 << 15, 1 << 14, 16), 16)
+    assert ei.value.code == -1
+
+
 def test_capacity_overflow_keeps_canonical_prefix():
     vol, kw = _vol("config1")
     full = gpu_extract(vol, levels=False, **kw)
