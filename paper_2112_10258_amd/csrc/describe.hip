@@ -124,7 +124,7 @@ __device__ __forceinline__ int first_of_block(int b, long long base, int grid)
 // rows of each y class, in a fixed order), and each of the 64 bins combines
 // the 9 class sums with their x/y half weights, and is ranked.
 template <bool INL>
-__global__ void __launch_bounds__(kDescThreads, 4) siftrank_kernel(const DescLaunch a)
+__device__ __forceinline__ void siftrank_body(const DescLaunch &a, int blk, int nblk)
 {
     constexpr int kCols = (2 * kMaxSiftR + 1) * (2 * kMaxSiftR + 1);
     static_assert(kCols <= kDescThreads, "one thread per window column");
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(kDescThreads, 4) siftrank_kernel(const DescLau
     for (int v = 0; v < a.n_vol; ++v) {
     const int count = min(a.counts[v], a.cap);
     const DVol vol = a.vols[v];
-    for (int kk = first_of_block(blockIdx.x, base, gridDim.x); kk < count; kk += gridDim.x) {
+    for (int kk = first_of_block(blk, base, nblk); kk < count; kk += nblk) {
         const size_t k = (size_t)v * a.cap + kk;
         const sift3d_keypoint kp = a.kp[k];
         if (kp.octave < 0 || kp.octave >= vol.n_units || kp.scale < 1 || kp.scale > a.S) {
@@ -242,12 +242,12 @@ __device__ __forceinline__ bool pair_gt(double ka, int ia, double kb, int ib)
 }
 
 template <bool INL>
-__global__ void __launch_bounds__(kDescThreads) brief_kernel(const DescLaunch a)
+__device__ __forceinline__ void brief_body(const DescLaunch &a, int blk, int nblk)
 {
     const int lane = threadIdx.x & 63;
     // wave index: uniform across the wave
-    const int gw = __builtin_amdgcn_readfirstlane(blockIdx.x * (kDescThreads / 64) + (threadIdx.x >> 6));
-    const int nwaves = gridDim.x * (kDescThreads / 64);
+    const int gw = __builtin_amdgcn_readfirstlane(blk * (kDescThreads / 64) + (threadIdx.x >> 6));
+    const int nwaves = nblk * (kDescThreads / 64);
     const int n = a.brief_n, nw = n / 64;
     long long base = 0;
     for (int v = 0; v < a.n_vol; ++v) {
@@ -341,6 +341,19 @@ __global__ void __launch_bounds__(kDescThreads) brief_kernel(const DescLaunch a)
     }
 }
 
+// Both descriptor families in one launch: workgroups [0, sr_blocks) compute
+// SIFT-Rank, the others BRIEF / RRIEF, so the two run side by side (the
+// roles are uniform per workgroup).
+template <bool INL>
+__global__ void __launch_bounds__(kDescThreads, 4) describe_kernel(const DescLaunch a)
+{
+    const int b = blockIdx.x;
+    if (b < a.sr_blocks)
+        siftrank_body<INL>(a, b, a.sr_blocks);
+    else
+        brief_body<INL>(a, b - a.sr_blocks, gridDim.x - a.sr_blocks);
+}
+
 }  // namespace
 
 // Workgroups of `k` resident on one CU (registers and LDS), at least 1.
@@ -351,34 +364,39 @@ static int blocks_per_cu(K k)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kDescThreads, 0) == hipSuccess && n > 0 ? n : 1;
 }
 
-// Grids: enough workgroups to fill every resident slot once (the kernels
-// loop over the keypoints), and no more than the keypoint slots need.
-hipError_t launch_describe(const DescLaunch &a, long long kp_slots, int n_cu, hipStream_t st)
+// Grid: the device's resident slots filled once (the workgroups loop over
+// the keypoints). SIFT-Rank takes one workgroup per keypoint slot and
+// BRIEF / RRIEF one per four while both fit; past that they share the
+// slots 3 : 1 (a SIFT-Rank keypoint costs about three times a BRIEF one).
+hipError_t launch_describe(const DescLaunch &a0, long long kp_slots, int n_cu, hipStream_t st)
 {
-    if (a.brief_n < 0 || a.brief_n > kMaxPairs || a.brief_n % 64 != 0) return hipErrorInvalidValue;
+    if (a0.brief_n < 0 || a0.brief_n > kMaxPairs || a0.brief_n % 64 != 0) return hipErrorInvalidValue;
     if (kp_slots <= 0) return hipSuccess;
-    const bool inl = a.n_units <= kInlineUnits;
-    if (a.siftrank != nullptr) {
-        static const int per_cu = blocks_per_cu(siftrank_kernel<true>);
-        const int grid = (int)std::min<long long>(kp_slots, (long long)per_cu * n_cu);
-        if (inl)
-            hipLaunchKernelGGL(siftrank_kernel<true>, dim3(grid), dim3(kDescThreads), 0, st, a);
-        else
-            hipLaunchKernelGGL(siftrank_kernel<false>, dim3(grid), dim3(kDescThreads), 0, st, a);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    const bool sr = a0.siftrank != nullptr;
+    const bool br = (a0.brief != nullptr || a0.rrief != nullptr) && a0.brief_n > 0;
+    if (!sr && !br) return hipSuccess;
+    static const int per_cu = blocks_per_cu(describe_kernel<true>);
+    const long long slots = (long long)per_cu * n_cu;
+    const int waves = kDescThreads / 64;
+    long long gs = sr ? kp_slots : 0, gb = br ? (kp_slots + waves - 1) / waves : 0;
+    if (gs + gb > slots) {
+        if (!br)
+            gs = slots;
+        else if (!sr)
+            gb = slots;
+        else {
+            gb = std::max<long long>(1, std::min(gb, slots / 4));
+            gs = std::max<long long>(1, slots - gb);
+        }
     }
-    if ((a.brief != nullptr || a.rrief != nullptr) && a.brief_n > 0) {
-        static const int per_cu = blocks_per_cu(brief_kernel<true>);
-        const int waves = kDescThreads / 64;
-        const int grid = (int)std::min<long long>((kp_slots + waves - 1) / waves, (long long)per_cu * n_cu);
-        if (inl)
-            hipLaunchKernelGGL(brief_kernel<true>, dim3(grid), dim3(kDescThreads), 0, st, a);
-        else
-            hipLaunchKernelGGL(brief_kernel<false>, dim3(grid), dim3(kDescThreads), 0, st, a);
-        return hipGetLastError();
-    }
-    return hipSuccess;
+    DescLaunch a = a0;
+    a.sr_blocks = (int)gs;
+    const dim3 grid((unsigned)(gs + gb));
+    if (a.n_units <= kInlineUnits)
+        hipLaunchKernelGGL(describe_kernel<true>, grid, dim3(kDescThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(describe_kernel<false>, grid, dim3(kDescThreads), 0, st, a);
+    return hipGetLastError();
 }
 
 }  // namespace s3d

@@ -242,6 +242,7 @@ struct DescLaunch {
     int brief_n;
     const int32_t *pairs;         // [S][brief_n][2][3] (scale s at index s-1)
     int n_units;
+    int sr_blocks;                // workgroups [0, sr_blocks) compute SIFT-Rank, the rest BRIEF / RRIEF
     DUnit inl[kInlineUnits];      // copy of units when n_units <= kInlineUnits
 };
 
