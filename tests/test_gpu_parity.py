@@ -187,6 +187,36 @@ def test_capacity_overflow_keeps_canonical_prefix():
     assert zero["count"] == n and len(zero["keypoints"]) == 0
 
 
+def test_describe_one_family_equals_both():
+    """The descriptor launch splits its workgroups between SIFT-Rank and
+    BRIEF / RRIEF according to what is asked for: each family alone, with a
+    small and a large keypoint capacity (one workgroup per slot, and the
+    3 : 1 split once the slots exceed the device), equals the call that
+    writes both."""
+    import torch
+
+    import paper_2112_10258_amd as S
+    vol, kw = _vol("config1")
+    ctx = S.Context(S.default_params(**kw), P.pair_draws())
+    nz, ny, nx = vol.shape
+    for cap in (256, 1 << 14):
+        plan = S.Plan(ctx, (nx, ny, nz), cap)
+        buf = S.Buffers(plan)
+        S.run_extract(plan, torch.from_numpy(vol).cuda(), buf)
+        torch.cuda.synchronize()
+        both = S.fetch_results(plan, buf)
+        assert both["count"] > 0
+        for f in ("siftrank", "brief", "rrief"):
+            getattr(buf, f).zero_()
+        plan.describe(buf.ws, buf.kp, buf.count, siftrank=buf.siftrank)
+        plan.describe(buf.ws, buf.kp, buf.count, brief=buf.brief)
+        plan.describe(buf.ws, buf.kp, buf.count, rrief=buf.rrief)
+        torch.cuda.synchronize()
+        alone = S.fetch_results(plan, buf)
+        for f in ("siftrank", "brief", "rrief"):
+            assert np.array_equal(alone[f], both[f]), (cap, f)
+
+
 def test_constant_volume_has_no_keypoints():
     vol = np.full((40, 40, 40), 0.5, dtype=np.float32)
     g = gpu_extract(vol, min_dim=8)
