@@ -121,13 +121,6 @@ int compact_blocks(const OctaveGeom &g)
 
 size_t level_off(const OctaveGeom &g, int lev) { return g.base + (size_t)lev * g.level_bytes; }
 
-int find_pass(const sift3d_plan *pl, int v, int o, int level)
-{
-    for (size_t b = 0; b < pl->blur.size(); ++b)
-        if (pl->blur[b].vol == v && pl->blur[b].octave == o && pl->blur[b].dst_idx == level) return (int)b;
-    return -1;
-}
-
 // The xy and z jobs of a split task (block0 left for the caller).
 void task_jobs(const sift3d_plan *pl, const Task &k, DXYJob &xy, DZJob &z)
 {
@@ -345,21 +338,37 @@ void build_schedule(sift3d_plan *pl)
                 for (int s = 1; s <= S; ++s) pl->tasks.push_back(Task{1, -1, v, o, s});
     const int nt = (int)pl->tasks.size();
     std::vector<char> xy_done(nt, 0), done(nt, 0);
-    std::vector<int> task_of_pass(pl->blur.size(), -1);
-    for (int t = 0; t < nt; ++t)
-        if (pl->tasks[t].kind == 0) task_of_pass[pl->tasks[t].pass] = t;
-    auto pass_done = [&](int v, int o, int level) {
-        const int b = find_pass(pl, v, o, level);
-        return b >= 0 && done[task_of_pass[b]];
-    };
-    auto ready = [&](int t) {
+    // task of the level pass writing G_level of (volume, octave), and of each
+    // pre-blur task, in dense tables (linear in the number of tasks)
+    const int nlev = S + 3;
+    auto key = [&](int v, int o, int level) { return ((size_t)v * kMaxOctaves + o) * nlev + level; };
+    std::vector<int> level_task((size_t)pl->n_vol * kMaxOctaves * nlev, -1);
+    std::vector<int> preblur_task((size_t)pl->n_vol * kMaxOctaves * nlev, -1);
+    for (int t = 0; t < nt; ++t) {
         const Task &k = pl->tasks[t];
-        if (k.kind == 1) return pass_done(k.vol, k.octave, k.s);
+        if (k.kind == 0) {
+            const BlurLaunch &L = pl->blur[k.pass];
+            level_task[key(L.vol, L.octave, L.dst_idx)] = t;
+        } else {
+            preblur_task[key(k.vol, k.octave, k.s)] = t;
+        }
+    }
+    // the task whose completion makes task t ready (-1: ready from the start)
+    std::vector<int> dep(nt, -1);
+    for (int t = 0; t < nt; ++t) {
+        const Task &k = pl->tasks[t];
+        if (k.kind == 1) {
+            dep[t] = level_task[key(k.vol, k.octave, k.s)];
+            continue;
+        }
         const BlurLaunch &L = pl->blur[k.pass];
-        if (L.src_kind < 0) return true;
-        if (L.src_idx == 0 && L.octave > 0) return pass_done(L.vol, L.octave - 1, S);  // G_0 from the sub-sample
-        return pass_done(L.vol, L.octave, L.src_idx);
-    };
+        if (L.src_kind < 0) continue;
+        if (L.src_idx == 0 && L.octave > 0)
+            dep[t] = level_task[key(L.vol, L.octave - 1, S)];  // G_0 from the sub-sample
+        else
+            dep[t] = level_task[key(L.vol, L.octave, L.src_idx)];
+    }
+    auto ready = [&](int t) { return dep[t] < 0 || done[dep[t]]; };
     auto task_r = [&](int t) { return pl->tasks[t].kind == 0 ? pl->blur[pl->tasks[t].pass].r : pl->brief_rb; };
     auto task_dog = [&](int t) { return pl->tasks[t].kind == 0 && pl->blur[pl->tasks[t].pass].dog; };
     auto task_geom = [&](int t) -> const OctaveGeom & {
@@ -385,13 +394,11 @@ void build_schedule(sift3d_plan *pl)
             if (k.kind != 0 || !is_fused(t)) continue;
             const BlurLaunch &L = pl->blur[k.pass];
             if (!L.dog || L.src_kind != 0 || L.src_idx < 1 || L.src_idx > S || L.r < kFusedPreR) continue;
-            for (int u = 0; u < nt; ++u) {
-                const Task &b = pl->tasks[u];
-                if (b.kind == 1 && !done[u] && b.vol == L.vol && b.octave == L.octave && b.s == L.src_idx) {
-                    done[u] = 1;
-                    with_pb[t] = 1;
-                    ++absorbed;
-                }
+            const int u = preblur_task[key(L.vol, L.octave, L.src_idx)];
+            if (u >= 0 && !done[u]) {
+                done[u] = 1;
+                with_pb[t] = 1;
+                ++absorbed;
             }
         }
     // one compact launch for all ready compact tasks (any radii)
