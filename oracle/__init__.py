@@ -16,8 +16,8 @@ order of the paper (Carluer et al., arXiv 2112.10258):
 4. 4D extremum detection by the sum of signs over 80 neighbours with the
    peak/valley values +/-80 (Section 3.2.2, 4D Peak Detection).
 5. Descriptors: upright SIFT-Rank (Related Work: 2x2x2 spatial x 8
-   orientation bins, ranked), BRIEF and RRIEF with point-pair method 3 and
-   a Gaussian patch pre-blur (Section 3.2.3).
+   orientation bins, ranked), BRIEF and RRIEF with any of the five point-pair
+   methods and a Gaussian patch pre-blur (Section 3.2.3).
 
 Readings where the paper is silent are listed in the design notes; each is
 named here where it is applied (R-numbers).
@@ -124,6 +124,7 @@ class Params:
     brief_n: int = 256          # pairs per BRIEF/RRIEF descriptor (R14)
     brief_blur: float = 0.95    # patch pre-blur sigma_b, octave voxels (R16)
     siftrank_factor: float = 2.0  # SIFT-Rank window half-width R = ceil(f * sigma_s) (R11)
+    brief_method: int = 3       # point-pair selection method 1..5 (Section 3.2.3; R15, R21-R23)
 
 
 # ---------------------------------------------------------------- primitives
@@ -273,19 +274,67 @@ def siftrank_radius(p: Params, s: int) -> int:
     return int(math.ceil(p.siftrank_factor * scale_sigma(p, s)))
 
 
-def pair_offsets(draws: np.ndarray, p: Params, s: int) -> np.ndarray:
-    """Integer (x,y,z) offsets of point-pair method 3 at scale s, [n][2][3].
+def _chi3_cdf(x: float) -> float:
+    """P(|z|^2 <= x) for z ~ N(0, I_3): the chi-square CDF with 3 degrees of freedom."""
+    return math.erf(math.sqrt(x / 2.0)) - math.sqrt(2.0 * x / math.pi) * math.exp(-x / 2.0)
 
-    Method 3 (Section 3.2.3): p1 ~ N(0, sigma), p2 ~ N(p1, sigma), with sigma
-    the keypoint scale in octave voxels (R13). From standard-normal draws
-    z1, z2: u1 = z1, u2 = z1 + z2; offset = floor(sigma_s * u + 0.5).
+
+def pair_points(draws: np.ndarray, p: Params, s: int) -> np.ndarray:
+    """Real-valued (x,y,z) points (p1, p2) of the n pairs at scale s, [n][2][3].
+
+    The five selection methods of Section 3.2.3, with sigma the keypoint
+    scale in octave voxels (R13) and the pair draws (z1, z2), two
+    standard-normal 3-vectors per pair, as the only randomness (R15):
+      1: p1, p2 uniform in the ball of radius 2 sigma (R21). A point is
+         direction z/|z| times radius 2 sigma F(|w|^2)^(1/3), F the
+         chi-square(3) CDF, so F(|w|^2) is uniform; p1 takes z1's direction
+         and z2's norm, p2 the reverse (direction and norm of a normal
+         vector are independent, so p1 and p2 are independent);
+      2: p1 = sigma z1, p2 = sigma z2;
+      3: p1 = sigma z1, p2 = p1 + sigma z2;
+      4: p1 = 0, p2 = sigma z2 (R22);
+      5: p1 = 0, p2 on a regular spherical grid: n/64 radii
+         2 sigma (k+1)/(n/64), 8 polar angles pi (j + 1/2)/8, 8 azimuths
+         2 pi (i + (j mod 2)/2)/8, pair 64 k + 8 j + i (R23).
     """
     z = np.asarray(draws, dtype=np.float64).reshape(-1, 2, 3)[: p.brief_n]
+    n = len(z)
     sig = scale_sigma(p, s)
-    u = np.empty_like(z)
-    u[:, 0] = z[:, 0]
-    u[:, 1] = z[:, 0] + z[:, 1]
-    return np.floor(sig * u + 0.5).astype(np.int32)
+    out = np.zeros((n, 2, 3))
+    m = p.brief_method
+    if m == 1:
+        for i in range(n):
+            a, b = z[i, 0], z[i, 1]
+            na, nb = float(np.sqrt(a @ a)), float(np.sqrt(b @ b))
+            if na > 0:
+                out[i, 0] = a / na * (2.0 * sig * np.cbrt(_chi3_cdf(nb * nb)))
+            if nb > 0:
+                out[i, 1] = b / nb * (2.0 * sig * np.cbrt(_chi3_cdf(na * na)))
+    elif m == 2:
+        out[:, 0] = sig * z[:, 0]
+        out[:, 1] = sig * z[:, 1]
+    elif m == 3:
+        out[:, 0] = sig * z[:, 0]
+        out[:, 1] = sig * (z[:, 0] + z[:, 1])
+    elif m == 4:
+        out[:, 1] = sig * z[:, 1]
+    elif m == 5:
+        nr = max(1, p.brief_n // 64)
+        for q in range(n):
+            k, j, i = q // 64, (q // 8) % 8, q % 8
+            r = 2.0 * sig * (k + 1) / nr
+            th = math.pi * (j + 0.5) / 8.0
+            ph = 2.0 * math.pi * (i + 0.5 * (j % 2)) / 8.0
+            out[q, 1] = (r * math.sin(th) * math.cos(ph), r * math.sin(th) * math.sin(ph), r * math.cos(th))
+    else:
+        raise ValueError("brief_method must be 1..5")
+    return out
+
+
+def pair_offsets(draws: np.ndarray, p: Params, s: int) -> np.ndarray:
+    """Integer (x,y,z) offsets of the pairs at scale s, [n][2][3]: each point
+    of pair_points rounded to the nearest voxel, floor(c + 0.5)."""
+    return np.floor(pair_points(draws, p, s) + 0.5).astype(np.int32)
 
 
 # ---------------------------------------------------------------- pipeline

@@ -16,7 +16,7 @@ def oracle_params(gp) -> O.Params:
     return O.Params(n_octaves=gp.n_octaves, min_dim=gp.min_dim, scales=gp.scales, sigma0=gp.sigma0,
                     sigma_in=gp.sigma_in, trunc=gp.trunc, dog_threshold=float(np.float32(gp.dog_threshold)),
                     votes=gp.votes, brief_n=gp.brief_n, brief_blur=gp.brief_blur,
-                    siftrank_factor=gp.siftrank_factor)
+                    siftrank_factor=gp.siftrank_factor, brief_method=gp.brief_method)
 
 
 def gpu_extract(vol: np.ndarray, cap: int = 1 << 15, draws=None, levels: bool = True, **params):

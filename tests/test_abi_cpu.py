@@ -46,23 +46,30 @@ def test_default_params_and_error_strings():
 
 def test_pair_offsets_host_function_matches_oracle():
     import paper_2112_10258_amd as S
-    for n in (64, 256):
-        p = S.default_params(brief_n=n)
-        draws = P.pair_draws(3, n)
-        for s in (1, 2, 3):
-            assert np.array_equal(S.pair_offsets(p, draws, s), O.pair_offsets(draws, O.Params(brief_n=n), s))
+    for m in range(1, 6):
+        for n in (64, 128, 256):
+            p = S.default_params(brief_n=n, brief_method=m)
+            draws = P.pair_draws(3 + m, n)
+            for s in (1, 2, 3):
+                want = O.pair_offsets(draws, O.Params(brief_n=n, brief_method=m), s)
+                assert np.array_equal(S.pair_offsets(p, draws, s), want), (m, n, s)
 
 
 def test_bad_params_rejected():
     import paper_2112_10258_amd as S
     draws = P.pair_draws()
     for kw in (dict(brief_n=100), dict(votes=0), dict(votes=81), dict(scales=0), dict(min_dim=2),
-               dict(pyramid_mode=4), dict(pyramid_mode=-1)):
+               dict(pyramid_mode=4), dict(pyramid_mode=-1), dict(brief_method=0), dict(brief_method=6)):
         with pytest.raises(S.Sift3dError) as ei:
             S.pair_offsets(S.default_params(**kw), draws, 1)
         assert ei.value.code == -1
     with pytest.raises(S.Sift3dError) as ei:
         S.pair_offsets(S.default_params(siftrank_factor=5.0), draws, 1)
+    assert ei.value.code == -6
+    # the paper's sigma_b sweep reaches 3.05 (pre-blur radius 10); past radius 10 is refused
+    S.pair_offsets(S.default_params(brief_blur=3.05), draws, 1)
+    with pytest.raises(S.Sift3dError) as ei:
+        S.pair_offsets(S.default_params(brief_blur=3.4), draws, 1)
     assert ei.value.code == -6
     with pytest.raises(S.Sift3dError):
         S.pair_offsets(S.default_params(), draws[:10], 1)

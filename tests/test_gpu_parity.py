@@ -217,6 +217,49 @@ def test_describe_one_family_equals_both():
             assert np.array_equal(alone[f], both[f]), (cap, f)
 
 
+@pytest.mark.parametrize("method", [1, 2, 4, 5])
+def test_brief_pair_methods(method):
+    """BRIEF bits and RRIEF ranks with each of the other point-pair methods of
+    Section 3.2.3 match the oracle on the GPU's own levels (bits exact except
+    |d| < 1e-6, ranks exact except differences within 1e-6)."""
+    vol, kw = _vol("config1")
+    g = gpu_extract(vol, brief_method=method, **kw)
+    p = oracle_params(g["params"])
+    assert p.brief_method == method
+    k = g["keypoints"]
+    assert len(k) > 0
+    d = O.describe([[x.astype(np.float64) for x in Gs] for Gs in g["G"]], k, P.pair_draws(), p)
+    gb = unpack_bits(g["brief"], p.brief_n)
+    ob = unpack_bits(d["brief"], p.brief_n)
+    diff = gb != ob
+    assert np.all(np.abs(d["diff"][diff]) < MARGIN), "BRIEF bit mismatch outside the margin"
+    for i in range(len(k)):
+        assert rank_mismatch_excused(d["diff"][i], g["rrief"][i], d["rrief"][i], MARGIN), i
+    if method in (4, 5):
+        # p1 at the centre: every pair compares the keypoint's own voxel
+        assert np.all(O.pair_offsets(P.pair_draws(), p, 1)[:, 0] == 0)
+    print(f"[parity] brief method {method}: {len(k)} keypoints, bits differing {int(diff.sum())}", flush=True)
+
+
+def test_brief_wide_preblur():
+    """The largest pre-blur of the paper's sigma_b sweep (3.05: tap radius 10)
+    runs as its own level tasks; B_s and the descriptors match the oracle."""
+    vol, kw = _vol("config1")
+    g = gpu_extract(vol, brief_blur=3.05, **kw)
+    p = oracle_params(g["params"])
+    for o, Gs in enumerate(g["G"]):
+        for s in range(1, p.scales + 1):
+            want = O.blur(Gs[s].astype(np.float64), p.brief_blur, p.trunc)
+            assert level_rel_err(g["B"][o][s - 1], want) <= LEVEL_RTOL, (o, s)
+    k = g["keypoints"]
+    d = O.describe([[x.astype(np.float64) for x in Gs] for Gs in g["G"]], k, P.pair_draws(), p)
+    gb = unpack_bits(g["brief"], p.brief_n)
+    ob = unpack_bits(d["brief"], p.brief_n)
+    assert np.all(np.abs(d["diff"][gb != ob]) < MARGIN)
+    for i in range(len(k)):
+        assert rank_mismatch_excused(d["diff"][i], g["rrief"][i], d["rrief"][i], MARGIN), i
+
+
 def test_constant_volume_has_no_keypoints():
     vol = np.full((40, 40, 40), 0.5, dtype=np.float32)
     g = gpu_extract(vol, min_dim=8)

@@ -311,6 +311,68 @@ def test_pair_offsets_follow_method_3():
     assert np.all(off == np.floor(off))
 
 
+def _pairs(method, n, seed=98):
+    p = O.Params(brief_n=n, brief_method=method)
+    return p, O.pair_points(P.pair_draws(seed, n), p, 3), O.scale_sigma(p, 3)
+
+
+def test_pair_points_method_1_uniform_in_ball():
+    # uniform in the ball of radius a = 2 sigma: (|p|/a)^3 ~ U(0,1), so its mean
+    # is 1/2 and variance 1/12; E[x^2] = a^2/5 per axis; p1 and p2 independent
+    p, pts, sig = _pairs(1, 60000)
+    a = 2.0 * sig
+    for w in (0, 1):
+        q = pts[:, w]
+        r = np.sqrt((q * q).sum(axis=1))
+        assert r.max() <= a * (1 + 1e-12)
+        u = (r / a) ** 3
+        assert u.mean() == pytest.approx(0.5, abs=0.005)
+        assert u.var() == pytest.approx(1.0 / 12.0, abs=0.003)
+        assert (q[:, 2] ** 2).mean() / a ** 2 == pytest.approx(0.2, rel=0.03)
+        assert np.abs(q.mean(axis=0)).max() < 0.03 * a
+    assert abs(np.corrcoef(pts[:, 0, 0], pts[:, 1, 0])[0, 1]) < 0.02
+    assert abs(np.corrcoef(np.abs(pts[:, 0]).sum(1), np.abs(pts[:, 1]).sum(1))[0, 1]) < 0.02
+
+
+def test_pair_points_method_2_independent_normals():
+    p, pts, sig = _pairs(2, 60000)
+    a, b = pts[:, 0].ravel(), pts[:, 1].ravel()
+    assert np.var(a) / sig ** 2 == pytest.approx(1.0, rel=0.03)
+    assert np.var(b) / sig ** 2 == pytest.approx(1.0, rel=0.03)
+    assert abs(np.corrcoef(a, b)[0, 1]) < 0.02
+
+
+def test_pair_points_method_4_centre_and_normal():
+    p, pts, sig = _pairs(4, 60000)
+    assert np.all(pts[:, 0] == 0.0)
+    b = pts[:, 1].ravel()
+    assert np.var(b) / sig ** 2 == pytest.approx(1.0, rel=0.03)
+    assert abs(b.mean()) < 0.03 * sig
+
+
+def test_pair_points_method_5_spherical_grid():
+    # p1 at the centre; p2 on n/64 shells of radius 2 sigma (k+1)/(n/64), 64 points
+    # per shell symmetric about the centre (zero mean), no two points equal
+    for n in (64, 256):
+        p, pts, sig = _pairs(5, n)
+        assert np.all(pts[:, 0] == 0.0)
+        q = pts[:, 1]
+        r = np.sqrt((q * q).sum(axis=1))
+        nr = n // 64
+        for k in range(nr):
+            shell = q[64 * k:64 * (k + 1)]
+            assert np.allclose(r[64 * k:64 * (k + 1)], 2.0 * sig * (k + 1) / nr, rtol=1e-12)
+            assert np.abs(shell.mean(axis=0)).max() < 1e-12 * sig
+        assert len({tuple(np.round(v, 9)) for v in q}) == n
+
+
+def test_pair_offsets_round_the_points():
+    for m in range(1, 6):
+        p = O.Params(brief_method=m)
+        draws = P.pair_draws(4, 256)
+        assert np.array_equal(O.pair_offsets(draws, p, 2), np.floor(O.pair_points(draws, p, 2) + 0.5))
+
+
 def test_rank_is_stable_permutation():
     v = np.array([3.0, 1.0, 3.0, -2.0, 1.0])
     assert O.rank(v).tolist() == [3, 1, 4, 0, 2]
