@@ -55,7 +55,8 @@ typedef struct sift3d_params {
     float dog_threshold;    /* [0.01] keypoints need |D| > dog_threshold         */
     int votes;              /* [80] sum-of-signs acceptance |f| >= votes, 1..80  */
     int brief_n;            /* [256] BRIEF/RRIEF pairs, multiple of 64, <= 256   */
-    double brief_blur;      /* [0.95] patch pre-blur sigma_b (0 = none), <= 2.0  */
+    double brief_blur;      /* [0.95] patch pre-blur sigma_b (0 = none); its tap
+                               radius ceil(trunc * sigma_b) <= 10 */
     double siftrank_factor; /* [2.0] SIFT-Rank half-width R = ceil(f * sigma_s), R <= 7 */
     int pyramid_mode;       /* [0] 0 = by size (fused streaming pass for octaves of
                                >= 24M voxels, and for levels of radius <= 8 in
@@ -66,6 +67,13 @@ typedef struct sift3d_params {
                                compact; results agree to rounding. Levels whose
                                tap radius exceeds 10 always run as xy + z
                                launches */
+    int brief_method;       /* [3] point-pair selection (Section 3.2.3), sigma the
+                               keypoint scale: 1 = p1, p2 uniform in the ball of
+                               radius 2 sigma; 2 = p1, p2 ~ N(0, sigma); 3 = p1 ~
+                               N(0, sigma), p2 ~ N(p1, sigma); 4 = p1 at the
+                               centre, p2 ~ N(0, sigma); 5 = p1 at the centre,
+                               p2 on a regular spherical grid. Built from the
+                               pair draws as sift3d_pair_offsets describes */
 } sift3d_params;
 
 /*
@@ -108,7 +116,17 @@ int sift3d_ctx_params(const sift3d_ctx *ctx, sift3d_params *out);
 /*
  * Integer pair offsets of scale s (1..S) that a context built from the same
  * parameters and draws uses: out is [brief_n][2][3] (x,y,z). Pure host
- * function (no device needed).
+ * function (no device needed). pair_draws holds two standard-normal
+ * 3-vectors (z1, z2) per pair; with sigma the scale-s sigma in octave
+ * voxels, the real-valued points are, by brief_method:
+ *   1: p1 = 2 sigma F(|z2|^2)^(1/3) z1/|z1|, p2 = 2 sigma F(|z1|^2)^(1/3) z2/|z2|,
+ *      F the chi-square CDF with 3 degrees of freedom (uniform in the ball);
+ *   2: p1 = sigma z1, p2 = sigma z2;    3: p1 = sigma z1, p2 = sigma (z1 + z2);
+ *   4: p1 = 0, p2 = sigma z2;
+ *   5: p1 = 0, p2 = pair 64 k + 8 j + i of a spherical grid: radius
+ *      2 sigma (k+1)/(n/64), polar angle pi (j + 1/2)/8, azimuth
+ *      2 pi (i + (j mod 2)/2)/8 (z1, z2 unused);
+ * each coordinate rounded as floor(c + 0.5).
  */
 int sift3d_pair_offsets(const sift3d_params *p, const double *pair_draws, int n_draws, int scale,
                         int32_t *out);

@@ -54,6 +54,7 @@ int check_params(const sift3d_params *p)
     if (p->brief_n < 0 || p->brief_n > kMaxPairs || p->brief_n % 64 != 0) return SIFT3D_E_ARG;
     if (p->brief_blur < 0.0 || !(p->siftrank_factor > 0.0)) return SIFT3D_E_ARG;
     if (p->pyramid_mode < 0 || p->pyramid_mode > 3) return SIFT3D_E_ARG;
+    if (p->brief_method < 1 || p->brief_method > 5) return SIFT3D_E_ARG;
     // kernel limits
     const double top = scale_sigma(*p, p->scales + 2);
     const double prev = scale_sigma(*p, p->scales + 1);
@@ -78,19 +79,76 @@ int slab_planes(int nz, int slabs)
     return std::min(L, (nz + 1) & ~1);
 }
 
-// Method 3 point pairs (Section 3.2.3): p1 ~ N(0, sigma), p2 ~ N(p1, sigma)
-// with sigma the keypoint scale in octave voxels. From draws (z1, z2):
-// u1 = z1, u2 = z1 + z2, offset = floor(sigma_s * u + 0.5). out: [n][2][3].
+// P(|z|^2 <= x) for a standard-normal 3-vector z (chi-square CDF, 3 dof).
+static double chi3_cdf(double x)
+{
+    return std::erf(std::sqrt(x / 2.0)) - std::sqrt(2.0 * x / M_PI) * std::exp(-x / 2.0);
+}
+
+// Point pairs of the five selection methods (Section 3.2.3), sigma = the
+// keypoint scale in octave voxels, each point rounded to the nearest voxel
+// (floor(c + 0.5)). The randomness is the draws (z1, z2), two standard-normal
+// 3-vectors per pair. out: [n][2][3].
+//   1: p1, p2 uniform in the ball of radius 2 sigma: direction z/|z|, radius
+//      2 sigma F(|w|^2)^(1/3) with F the chi-square(3) CDF (so F(|w|^2) is
+//      uniform); p1 = (direction of z1, norm of z2), p2 the reverse.
+//   2: p1 = sigma z1, p2 = sigma z2.
+//   3: p1 = sigma z1, p2 = sigma (z1 + z2), i.e. p2 ~ N(p1, sigma).
+//   4: p1 = 0, p2 = sigma z2.
+//   5: p1 = 0, p2 on a regular spherical grid: n/64 radii 2 sigma (k+1)/(n/64),
+//      polar angles pi (j + 1/2)/8, azimuths 2 pi (i + (j mod 2)/2)/8, pair
+//      64 k + 8 j + i.
 void pair_offsets(const sift3d_params &p, const double *draws, int s, int32_t *out)
 {
     const double sig = scale_sigma(p, s);
-    for (int i = 0; i < p.brief_n; ++i)
-        for (int d = 0; d < 3; ++d) {
-            const double z1 = draws[(size_t)i * 6 + d], z2 = draws[(size_t)i * 6 + 3 + d];
-            const double u1 = z1, u2 = z1 + z2;
-            out[(size_t)i * 6 + d] = (int32_t)std::floor(sig * u1 + 0.5);
-            out[(size_t)i * 6 + 3 + d] = (int32_t)std::floor(sig * u2 + 0.5);
+    const int n = p.brief_n;
+    auto put = [&](int i, int which, const double c[3]) {
+        for (int d = 0; d < 3; ++d) out[(size_t)i * 6 + which * 3 + d] = (int32_t)std::floor(c[d] + 0.5);
+    };
+    for (int i = 0; i < n; ++i) {
+        const double *z1 = draws + (size_t)i * 6, *z2 = z1 + 3;
+        double a[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
+        switch (p.brief_method) {
+        case 1: {
+            const double n1 = std::sqrt(z1[0] * z1[0] + z1[1] * z1[1] + z1[2] * z1[2]);
+            const double n2 = std::sqrt(z2[0] * z2[0] + z2[1] * z2[1] + z2[2] * z2[2]);
+            const double ra = 2.0 * sig * std::cbrt(chi3_cdf(n2 * n2));
+            const double rb = 2.0 * sig * std::cbrt(chi3_cdf(n1 * n1));
+            for (int d = 0; d < 3; ++d) {
+                a[d] = n1 > 0.0 ? z1[d] / n1 * ra : 0.0;
+                b[d] = n2 > 0.0 ? z2[d] / n2 * rb : 0.0;
+            }
+            break;
         }
+        case 2:
+            for (int d = 0; d < 3; ++d) {
+                a[d] = sig * z1[d];
+                b[d] = sig * z2[d];
+            }
+            break;
+        case 4:
+            for (int d = 0; d < 3; ++d) b[d] = sig * z2[d];
+            break;
+        case 5: {
+            const int nr = std::max(1, n / 64);
+            const int k = i / 64, j = (i / 8) % 8, q = i % 8;
+            const double r = 2.0 * sig * (k + 1) / nr;
+            const double th = M_PI * (j + 0.5) / 8.0, ph = 2.0 * M_PI * (q + 0.5 * (j % 2)) / 8.0;
+            b[0] = r * std::sin(th) * std::cos(ph);
+            b[1] = r * std::sin(th) * std::sin(ph);
+            b[2] = r * std::cos(th);
+            break;
+        }
+        default:   // 3
+            for (int d = 0; d < 3; ++d) {
+                a[d] = sig * z1[d];
+                b[d] = sig * (z1[d] + z2[d]);
+            }
+            break;
+        }
+        put(i, 0, a);
+        put(i, 1, b);
+    }
 }
 
 // Planes per xy block: 4 while that still leaves >= 1024 blocks for the
@@ -827,6 +885,7 @@ int sift3d_default_params(sift3d_params *p)
     p->brief_blur = 0.95;
     p->siftrank_factor = 2.0;
     p->pyramid_mode = 0;
+    p->brief_method = 3;
     return SIFT3D_OK;
 }
 

@@ -26,7 +26,7 @@ constexpr int kMaxScales = 5;               // S; S+3 Gaussian levels per octave
 constexpr int kMaxR = 16;                   // largest blur tap radius
 constexpr int kMaxTaps = 2 * kMaxR + 1;
 constexpr int kMaxSiftR = 7;                // SIFT-Rank window half-width
-constexpr int kMaxBriefR = 6;               // pre-blur tap radius
+constexpr int kMaxBriefR = 10;              // pre-blur tap radius (runs on the level kernels)
 constexpr int kMaxPairs = 256;
 constexpr int kMaxVolumes = 4096;
 

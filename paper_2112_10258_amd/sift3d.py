@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("brief_blur", ctypes.c_double),
         ("siftrank_factor", ctypes.c_double),
         ("pyramid_mode", ctypes.c_int),
+        ("brief_method", ctypes.c_int),
     ]
 
 
