@@ -208,6 +208,27 @@ def octave0_roofline(plan, passes, pass_ms, workload):
     }
 
 
+def match_throughput(stream, n=16384, reps=5):
+    """Nearest-neighbour matching (sift3d_match) of n x n seeded synthetic
+    descriptors: 64-element rank vectors (random permutations, as SIFT-Rank
+    rows are) and 4-word BRIEF rows. Reported as pairs compared per second."""
+    import torch
+
+    import paper_2112_10258_amd as S
+    rng = np.random.default_rng(2112)
+    A = torch.from_numpy(np.argsort(rng.random((n, 64)), axis=1).astype(np.uint8)).cuda()
+    B = torch.from_numpy(np.argsort(rng.random((n, 64)), axis=1).astype(np.uint8)).cuda()
+    Wa = torch.from_numpy(rng.integers(-2 ** 63, 2 ** 63 - 1, size=(n, 4), dtype=np.int64)).cuda()
+    Wb = torch.from_numpy(rng.integers(-2 ** 63, 2 ** 63 - 1, size=(n, 4), dtype=np.int64)).cuda()
+    torch.cuda.synchronize()
+    out = {"pairs": n * n}
+    for name, a, b, kind in (("siftrank64", A, B, S.MATCH_RANKS), ("brief256", Wa, Wb, S.MATCH_BRIEF)):
+        S.match(a, b, kind, stream)
+        ms = time_calls(lambda: S.match(a, b, kind, stream), reps, stream)
+        out[name] = {"ms": round(ms, 4), "g_pairs_per_s": round(n * n / (ms * 1e-3) / 1e9, 2)}
+    return out
+
+
 def large_volume_roofline(stream, reps):
     """The same roofline on the 512x512x384 volume (config 4), whose levels
     do not fit the last-level cache: the fused pass against HBM."""
@@ -552,6 +573,9 @@ def main():
         large = large_volume_roofline(stream, max(3, reps // 4))
         log(f"[bench] roofline 512x512x384: {large}")
 
+    match = match_throughput(stream)
+    log(f"[bench] match: {match}")
+
     batch = None
     if not args.no_batch:
         torch.cuda.empty_cache()
@@ -596,6 +620,7 @@ def main():
         "roofline_large_volume": large,
         "batch": batch,
         "serve": serve,
+        "match": match,
         "cpu_baseline": cpu,
         "paper_context": "paper: 1.4 s CPU, 0.2 s GPU per 145x174x145 volume (~3000 keypoints, hardware unnamed)",
     }

@@ -358,6 +358,28 @@ double sift3d_server_clock(void);
 int sift3d_server_destroy(sift3d_server *srv);
 
 /* Static description of an error code. */
+/*
+ * Nearest-neighbour matching of descriptors (keypoints are matched by their
+ * descriptors, Section 3.3). For every row i of A: d_idx[i] = the index of
+ * the nearest row of B (the lowest index among equal distances), d_d1[i] =
+ * its distance, d_d2[i] = the smallest distance over the other rows of B
+ * (for a ratio test). Exact integer distances:
+ *   kind SIFT3D_MATCH_BRIEF: rows of row_elems (1..4) uint64 words, the
+ *     Hamming distance;
+ *   kind SIFT3D_MATCH_RANKS: rows of row_elems (64, 128, 192 or 256) uint8
+ *     ranks (SIFT-Rank, RRIEF), the squared Euclidean distance. Rank vectors
+ *     of one length all have the same norm, so this orders neighbours as the
+ *     distance of the unit-length normalised vectors does.
+ * d_a [n_a][row], d_b [n_b][row] (4-byte aligned) and the int32 outputs
+ * [n_a] are device memory owned by the caller. n_b == 0 gives d_idx = -1 and
+ * d_d1 = d_d2 = INT32_MAX; n_b == 1 gives d_d2 = INT32_MAX. Stream-ordered,
+ * allocates nothing. SIFT3D_E_ARG for a bad kind, size or pointer.
+ */
+#define SIFT3D_MATCH_BRIEF 0
+#define SIFT3D_MATCH_RANKS 1
+int sift3d_match(int kind, const void *d_a, int n_a, const void *d_b, int n_b, int row_elems, int32_t *d_idx,
+                 int32_t *d_d1, int32_t *d_d2, void *stream);
+
 const char *sift3d_error_string(int code);
 
 /* hipError_t of the last failing HIP call made by the library on this thread. */

@@ -337,6 +337,45 @@ def pair_offsets(draws: np.ndarray, p: Params, s: int) -> np.ndarray:
     return np.floor(pair_points(draws, p, s) + 0.5).astype(np.int32)
 
 
+# ---------------------------------------------------------------- matching
+
+def match_nn(A: np.ndarray, B: np.ndarray, kind: int):
+    """Nearest neighbour in B of every descriptor of A, by brute force.
+
+    The descriptors' consumer (Section 3.3: keypoints are matched by their
+    descriptors). kind 0: binary BRIEF words [n][w] (uint64), distance =
+    Hamming distance; kind 1 / 2: rank vectors [n][m] (uint8, SIFT-Rank /
+    RRIEF), distance = squared Euclidean distance of the rank vectors (rank
+    vectors all have the same norm, so this orders neighbours exactly as
+    the distance of the unit-length normalised vectors does). Returns
+    (idx, d1, d2): the index of the nearest element of B (the lowest index
+    among equal distances; -1 when B is empty), its distance, and the
+    second-smallest distance over the other elements of B (2^31 - 1 when B
+    has fewer than two elements).
+    """
+    A = np.asarray(A)
+    B = np.asarray(B)
+    na, nb = len(A), len(B)
+    big = 2 ** 31 - 1
+    idx = np.full(na, -1, dtype=np.int64)
+    d1 = np.full(na, big, dtype=np.int64)
+    d2 = np.full(na, big, dtype=np.int64)
+    for i in range(na):
+        if kind == 0:
+            x = np.bitwise_xor(A[i].astype(np.uint64)[None, :], B.astype(np.uint64))
+            d = np.array([sum(bin(int(w)).count("1") for w in row) for row in x], dtype=np.int64)
+        else:
+            diff = A[i].astype(np.int64)[None, :] - B.astype(np.int64)
+            d = (diff * diff).sum(axis=1)
+        if nb == 0:
+            continue
+        j = int(np.argmin(d))            # first occurrence: the lowest index
+        idx[i], d1[i] = j, d[j]
+        if nb > 1:
+            d2[i] = np.min(np.delete(d, j))
+    return idx, d1, d2
+
+
 # ---------------------------------------------------------------- pipeline
 
 @dataclass

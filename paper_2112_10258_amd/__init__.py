@@ -7,6 +7,8 @@ declared in include/sift3d.h.
 from .sift3d import (  # noqa: F401
     KEYPOINT_BYTES,
     KEYPOINT_DTYPE,
+    MATCH_BRIEF,
+    MATCH_RANKS,
     Buffers,
     Context,
     Params,
@@ -17,5 +19,6 @@ from .sift3d import (  # noqa: F401
     pair_offsets,
     exported_symbols,
     fetch_results,
+    match,
     run_extract,
 )

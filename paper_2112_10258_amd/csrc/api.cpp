@@ -868,6 +868,12 @@ int run_step(const sift3d_plan *plan, const Step &stp, const float *d_in, void *
 
 }  // namespace
 
+namespace s3d {
+// Nearest-neighbour matching launcher (match.hip).
+hipError_t launch_match(int kind, const void *a, int n_a, const void *b, int n_b, int row_elems, int32_t *idx,
+                        int32_t *d1, int32_t *d2, hipStream_t st);
+}  // namespace s3d
+
 extern "C" {
 
 int sift3d_default_params(sift3d_params *p)
@@ -1167,6 +1173,26 @@ int sift3d_extract(const sift3d_plan *plan, const float *d_vol, void *d_ws, size
     if (rc != SIFT3D_OK) return rc;
     return sift3d_describe(plan, d_ws, ws_bytes, d_kp, d_count, kp_capacity, d_siftrank, d_brief, d_rrief,
                            stream);
+}
+
+int sift3d_match(int kind, const void *d_a, int n_a, const void *d_b, int n_b, int row_elems, int32_t *d_idx,
+                 int32_t *d_d1, int32_t *d_d2, void *stream)
+{
+    if (n_a < 0 || n_b < 0) return SIFT3D_E_ARG;
+    if (kind == SIFT3D_MATCH_BRIEF) {
+        if (row_elems < 1 || row_elems > kMaxPairs / 64) return SIFT3D_E_ARG;
+    } else if (kind == SIFT3D_MATCH_RANKS) {
+        if (row_elems < 64 || row_elems > kMaxPairs || row_elems % 64 != 0) return SIFT3D_E_ARG;
+    } else {
+        return SIFT3D_E_ARG;
+    }
+    if (n_a == 0) return SIFT3D_OK;
+    if (d_a == nullptr || d_idx == nullptr || d_d1 == nullptr || d_d2 == nullptr || (n_b > 0 && d_b == nullptr))
+        return SIFT3D_E_ARG;
+    if (reinterpret_cast<uintptr_t>(d_a) % 4 != 0 || reinterpret_cast<uintptr_t>(d_b) % 4 != 0) return SIFT3D_E_ARG;
+    const hipError_t e = launch_match(kind, d_a, n_a, d_b, n_b, row_elems, d_idx, d_d1, d_d2,
+                                      static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }
 
 const char *sift3d_error_string(int code)

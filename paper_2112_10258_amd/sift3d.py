@@ -141,6 +141,7 @@ def _load():
         "sift3d_server_stats": (i, [_vp, P(ServerCounters)]),
         "sift3d_server_clock": (ctypes.c_double, []),
         "sift3d_server_destroy": (i, [_vp]),
+        "sift3d_match": (i, [i, _vp, i, _vp, i, i, _vp, _vp, _vp, _vp]),
         "sift3d_error_string": (ctypes.c_char_p, [i]),
         "sift3d_last_hip_error": (i, []),
     }
@@ -176,6 +177,28 @@ def _stream(stream) -> int:
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+MATCH_BRIEF = 0
+MATCH_RANKS = 1
+
+
+def match(a, b, kind: int, stream=None):
+    """Nearest row of b for every row of a (sift3d_match): device tensors
+    [n][words] int64 (BRIEF, kind MATCH_BRIEF) or [n][m] uint8 (ranks, kind
+    MATCH_RANKS). Returns (idx, d1, d2) int32 device tensors of length n_a."""
+    import torch
+    assert a.is_cuda and b.is_cuda and a.dim() == 2 and b.dim() == 2 and a.shape[1] == b.shape[1]
+    a = a.contiguous()
+    b = b.contiguous()
+    n_a, n_b = a.shape[0], b.shape[0]
+    idx = torch.empty(n_a, dtype=torch.int32, device=a.device)
+    d1 = torch.empty(n_a, dtype=torch.int32, device=a.device)
+    d2 = torch.empty(n_a, dtype=torch.int32, device=a.device)
+    _check(_load().sift3d_match(int(kind), _vp(a.data_ptr()), n_a, _vp(b.data_ptr() if n_b else None), n_b,
+                                int(a.shape[1]), _vp(idx.data_ptr()), _vp(d1.data_ptr()), _vp(d2.data_ptr()),
+                                _vp(_stream(stream))), "sift3d_match")
+    return idx, d1, d2
 
 
 def default_params(**overrides) -> Params:

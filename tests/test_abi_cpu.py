@@ -108,3 +108,16 @@ def test_struct_layouts_match_the_header(tmp_path):
     assert int(got["sift3d_keypoint"]) == S.KEYPOINT_DTYPE.itemsize
     for f in S.KEYPOINT_DTYPE.names:
         assert int(got[f"sift3d_keypoint.{f}"]) == S.KEYPOINT_DTYPE.fields[f][1], f
+
+
+def test_match_argument_checks():
+    """sift3d_match validates kind, row length and sizes on the host (no launch)."""
+    import paper_2112_10258_amd as S
+    lib = S.sift3d._load()
+    null = None
+    assert lib.sift3d_match(0, null, 0, null, 5, 4, null, null, null, null) == 0     # n_a = 0: nothing to do
+    assert lib.sift3d_match(2, null, 1, null, 1, 4, null, null, null, null) == -1    # kind
+    assert lib.sift3d_match(0, null, 1, null, 1, 5, null, null, null, null) == -1    # 5 BRIEF words
+    assert lib.sift3d_match(1, null, 1, null, 1, 100, null, null, null, null) == -1  # ranks not a multiple of 64
+    assert lib.sift3d_match(1, null, 1, null, 1, 64, null, null, null, null) == -1   # null pointers
+    assert lib.sift3d_match(1, null, -1, null, 1, 64, null, null, null, null) == -1  # negative size

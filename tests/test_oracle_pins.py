@@ -455,3 +455,39 @@ def test_x_mirror(small_case):
     perm = np.array([8 * ((e // 8) ^ 1) + ((e % 8) ^ 1) for e in range(64)])
     for i, key in enumerate(keys):
         np.testing.assert_allclose(d2["hist"][m[key]], desc["hist"][i][perm], rtol=1e-11, atol=1e-13)
+
+
+# ------------------------------------------------------------------ matching (descriptor consumer)
+def test_match_nn_hand_values():
+    # Hamming on one word: A = 1011b against B = {0001b, 1111b, 1011b, 0011b}:
+    # distances 2, 1, 0, 1 -> nearest 2 at 0, second-smallest 1
+    A = np.array([[0b1011]], dtype=np.uint64)
+    B = np.array([[0b0001], [0b1111], [0b1011], [0b0011]], dtype=np.uint64)
+    idx, d1, d2 = O.match_nn(A, B, 0)
+    assert (idx[0], d1[0], d2[0]) == (2, 0, 1)
+    # squared distance of rank vectors: (0,1,2,3) vs (1,0,2,3) -> 2, vs (3,2,1,0) -> 20,
+    # vs (0,1,2,3) -> 0 at index 2 and again at index 3 (the lower index wins, d2 = 0)
+    A = np.array([[0, 1, 2, 3]], dtype=np.uint8)
+    B = np.array([[1, 0, 2, 3], [3, 2, 1, 0], [0, 1, 2, 3], [0, 1, 2, 3]], dtype=np.uint8)
+    idx, d1, d2 = O.match_nn(A, B, 1)
+    assert (idx[0], d1[0], d2[0]) == (2, 0, 0)
+    idx, d1, d2 = O.match_nn(A, B[:2], 1)
+    assert (idx[0], d1[0], d2[0]) == (0, 2, 20)
+
+
+def test_match_nn_edge_cases_and_self_match():
+    big = 2 ** 31 - 1
+    A = np.array([[5, 6, 7, 8]], dtype=np.uint8)
+    idx, d1, d2 = O.match_nn(A, A[:0], 1)
+    assert (idx[0], d1[0], d2[0]) == (-1, big, big)
+    idx, d1, d2 = O.match_nn(A, A, 1)
+    assert (idx[0], d1[0], d2[0]) == (0, 0, big)
+    # distinct permutations matched against themselves: each finds itself at 0;
+    # against a shuffled copy: the shuffle's inverse
+    rng = np.random.default_rng(7)
+    R = np.array([rng.permutation(64) for _ in range(40)], dtype=np.uint8)
+    idx, d1, _ = O.match_nn(R, R, 1)
+    assert np.array_equal(idx, np.arange(40)) and np.all(d1 == 0)
+    perm = rng.permutation(40)
+    idx, _, _ = O.match_nn(R, R[perm], 1)
+    assert np.array_equal(perm[idx], np.arange(40))
