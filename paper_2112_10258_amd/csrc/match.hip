@@ -6,10 +6,12 @@
 //   ranks (SIFT-Rank, RRIEF): rows of m uint8 ranks, distance = squared
 //          Euclidean distance = |a|^2 + |b|^2 - 2 a.b, the dot product from
 //          unsigned 8-bit dot4 instructions on 32-bit words; exact integers.
-// One thread owns one row of A (held in registers); B streams through LDS
-// in tiles that every thread reads in the same order (broadcast reads), so
-// each thread sees B in index order and keeps the lowest index among equal
-// distances.
+// A workgroup owns 64 rows of A, one per lane, held in registers; B streams
+// through LDS in tiles, and wavefront w of the four scans the w-th quarter
+// of every tile (broadcast reads), in index order. The four partial results
+// of a row are merged at the end in a fixed order: the smallest distance
+// with the lowest index wins, and the second-smallest distance is the
+// smaller of the winner's own second and the other quarters' best.
 #include <climits>
 #include <cstdint>
 
@@ -19,6 +21,7 @@ namespace s3d {
 namespace {
 
 constexpr int kMatchThreads = 256;
+constexpr int kMatchWaves = kMatchThreads / 64;   // B quarters per row of A
 constexpr int kMatchLdsWords = 8192;   // 32 KB of B rows per tile
 
 struct MatchArgs {
@@ -50,7 +53,9 @@ __global__ void __launch_bounds__(kMatchThreads) match_kernel(const MatchArgs a)
     constexpr int TILE = kMatchLdsWords / (W + (KIND == 1 ? 1 : 0));   // rows of B per tile
     __shared__ uint32_t tb[TILE * W];
     __shared__ int tn[KIND == 1 ? TILE : 1];                            // |b|^2 of the tile's rows
-    const int i = blockIdx.x * kMatchThreads + threadIdx.x;
+    __shared__ int pidx[kMatchWaves][64], pd1[kMatchWaves][64], pd2[kMatchWaves][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
     const bool live = i < a.n_a;
     uint32_t ra[W];
     int na = 0;
@@ -75,8 +80,11 @@ __global__ void __launch_bounds__(kMatchThreads) match_kernel(const MatchArgs a)
             }
         }
         __syncthreads();
+        // this wavefront's quarter of the tile
+        const int q = (rows + kMatchWaves - 1) / kMatchWaves;
+        const int r0 = wave * q, r1 = min(rows, r0 + q);
         if (live) {
-            for (int r = 0; r < rows; ++r) {
+            for (int r = r0; r < r1; ++r) {
                 int d;
                 if constexpr (KIND == 0) {
                     d = 0;
@@ -92,17 +100,33 @@ __global__ void __launch_bounds__(kMatchThreads) match_kernel(const MatchArgs a)
             }
         }
     }
-    if (live) {
-        a.idx[i] = best.idx;
-        a.d1[i] = best.d1;
-        a.d2[i] = best.d2;
+    pidx[wave][lane] = best.idx;
+    pd1[wave][lane] = best.d1;
+    pd2[wave][lane] = best.d2;
+    __syncthreads();
+    if (wave == 0 && live) {
+        // winner: smallest distance, lowest index among equal ones (each
+        // quarter's index is already its lowest at that distance)
+        int wb = 0;
+        for (int w = 1; w < kMatchWaves; ++w) {
+            const bool better = pd1[w][lane] < pd1[wb][lane] ||
+                                (pd1[w][lane] == pd1[wb][lane] && pidx[w][lane] >= 0 &&
+                                 (pidx[wb][lane] < 0 || pidx[w][lane] < pidx[wb][lane]));
+            if (better) wb = w;
+        }
+        int d2 = pd2[wb][lane];
+        for (int w = 0; w < kMatchWaves; ++w)
+            if (w != wb) d2 = min(d2, pd1[w][lane]);
+        a.idx[i] = pidx[wb][lane];
+        a.d1[i] = pd1[wb][lane];
+        a.d2[i] = d2;
     }
 }
 
 template <int KIND, int W>
 void launch_w(const MatchArgs &m, hipStream_t st)
 {
-    const int grid = (m.n_a + kMatchThreads - 1) / kMatchThreads;
+    const int grid = (m.n_a + 63) / 64;
     hipLaunchKernelGGL((match_kernel<KIND, W>), dim3(grid), dim3(kMatchThreads), 0, st, m);
 }
 
