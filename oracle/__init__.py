@@ -18,6 +18,8 @@ order of the paper (Carluer et al., arXiv 2112.10258):
 5. Descriptors: upright SIFT-Rank (Related Work: 2x2x2 spatial x 8
    orientation bins, ranked), BRIEF and RRIEF with any of the five point-pair
    methods and a Gaussian patch pre-blur (Section 3.2.3).
+6. Beside the path: nearest-neighbour matching of descriptors (Section 3.3)
+   and the uniform-filter approximation of the Gaussian blur (Related Work).
 
 Readings where the paper is silent are listed in the design notes; each is
 named here where it is applied (R-numbers).
@@ -374,6 +376,42 @@ def match_nn(A: np.ndarray, B: np.ndarray, kind: int):
         if nb > 1:
             d2[i] = np.min(np.delete(d, j))
     return idx, d1, d2
+
+
+def box_half_width(sigma: float, passes: int) -> int:
+    """Half-width h of the uniform filter (width 2h+1) whose `passes`-fold
+    repetition stands in for a Gaussian of standard deviation sigma (Related
+    Work: the scale space can also be built from uniform 1D filters; R24).
+    A width-w uniform filter has variance (w^2 - 1)/12, so the ideal width
+    of one of m equal passes is sqrt(12 sigma^2 / m + 1); h is the nearest
+    integer to (that width - 1) / 2."""
+    if sigma < 0 or passes < 1:
+        raise ValueError("sigma >= 0 and passes >= 1")
+    return int(math.floor((math.sqrt(12.0 * sigma * sigma / passes + 1.0) - 1.0) / 2.0 + 0.5))
+
+
+def box_axis(vol: np.ndarray, h: int, axis: int) -> np.ndarray:
+    """One clamp-to-edge uniform pass along axis (0 = x, 1 = y, 2 = z of a
+    [z,y,x] array): each output is the mean of the 2h+1 samples centred on
+    it, indices outside the volume clamped to the nearest edge (R24)."""
+    v = _f64(vol)
+    a = {0: 2, 1: 1, 2: 0}[axis]
+    n = v.shape[a]
+    acc = np.zeros_like(v)
+    for j in range(-h, h + 1):
+        acc += np.take(v, np.clip(np.arange(n) + j, 0, n - 1), axis=a)
+    return acc / (2 * h + 1)
+
+
+def box_blur(vol: np.ndarray, h: int, passes: int) -> np.ndarray:
+    """Uniform-filter approximation of a separable Gaussian blur (R24):
+    `passes` uniform passes of half-width h along x, then along y, then
+    along z."""
+    v = _f64(vol)
+    for axis in (0, 1, 2):
+        for _ in range(passes):
+            v = box_axis(v, h, axis)
+    return v
 
 
 # ---------------------------------------------------------------- pipeline

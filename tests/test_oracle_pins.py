@@ -491,3 +491,67 @@ def test_match_nn_edge_cases_and_self_match():
     perm = rng.permutation(40)
     idx, _, _ = O.match_nn(R, R[perm], 1)
     assert np.array_equal(perm[idx], np.arange(40))
+
+
+# ------------------------------------------- uniform-filter approximation
+
+
+def test_box_axis_hand_values():
+    # [1, 2, 4] with h = 1, edges clamped: (1+1+2)/3, (1+2+4)/3, (2+4+4)/3
+    v = np.array([1.0, 2.0, 4.0]).reshape(1, 1, 3)
+    assert np.allclose(O.box_axis(v, 1, 0).ravel(), [4 / 3, 7 / 3, 10 / 3], rtol=0, atol=1e-15)
+    # the same line along z and along y
+    assert np.allclose(O.box_axis(v.reshape(3, 1, 1), 1, 2).ravel(), [4 / 3, 7 / 3, 10 / 3], rtol=0, atol=1e-15)
+    assert np.allclose(O.box_axis(v.reshape(1, 3, 1), 1, 1).ravel(), [4 / 3, 7 / 3, 10 / 3], rtol=0, atol=1e-15)
+    # h = 0 is the identity
+    x = rnd((4, 5, 6), 1)
+    assert np.array_equal(O.box_blur(x, 0, 3), x)
+
+
+def test_box_blur_equals_scipy_uniform_filter():
+    # scipy's uniform filter with mode 'nearest' is the clamp-to-edge mean;
+    # ragged dims, one of them shorter than the filter
+    x = rnd((5, 9, 13), 2)
+    for h, m in ((1, 1), (2, 3), (4, 2), (3, 4)):
+        ref = x.copy()
+        for ax in (2, 1, 0):   # x, y, z of a [z,y,x] array
+            for _ in range(m):
+                ref = ndi.uniform_filter1d(ref, 2 * h + 1, axis=ax, mode="nearest")
+        assert np.allclose(O.box_blur(x, h, m), ref, rtol=0, atol=1e-12), (h, m)
+
+
+def test_box_impulse_response_and_moments():
+    # an interior impulse gives the separable product of the m-fold
+    # self-convolution of the uniform kernel, with mass 1 and per-axis
+    # variance m h (h + 1) / 3 (the uniform law's variance (w^2 - 1)/12, m times)
+    h, m, n = 2, 3, 41
+    v = np.zeros((n, n, n))
+    c = n // 2
+    v[c, c, c] = 1.0
+    out = O.box_blur(v, h, m)
+    k = np.ones(2 * h + 1) / (2 * h + 1)
+    p1 = np.array([1.0])
+    for _ in range(m):
+        p1 = np.convolve(p1, k)
+    prof = np.zeros(n)
+    prof[c - m * h:c + m * h + 1] = p1
+    assert np.allclose(out, prof[:, None, None] * prof[None, :, None] * prof[None, None, :], rtol=0, atol=1e-15)
+    assert abs(out.sum() - 1.0) < 1e-12
+    idx = np.arange(n) - c
+    for ax in range(3):
+        marg = out.sum(axis=tuple(a for a in range(3) if a != ax))
+        assert abs((marg * idx).sum()) < 1e-12
+        assert abs((marg * idx * idx).sum() - m * h * (h + 1) / 3) < 1e-12
+
+
+def test_box_half_width_values():
+    # ideal width sqrt(12 sigma^2 / m + 1), h = round((width - 1) / 2)
+    assert O.box_half_width(2.0, 1) == 3      # width 7 exactly: variance (49 - 1)/12 = 4
+    assert O.box_half_width(1.6, 3) == 1      # sqrt(11.24) = 3.353 -> 1.18
+    assert O.box_half_width(3.09, 3) == 3     # sqrt(39.19) = 6.260 -> 2.63
+    assert O.box_half_width(0.0, 3) == 0
+    # constants and linear ramps pass through the interior unchanged
+    ramp = np.broadcast_to(np.arange(30.0)[None, None, :], (3, 4, 30)).copy()
+    out = O.box_blur(ramp, 2, 3)
+    assert np.allclose(out[:, :, 6:24], ramp[:, :, 6:24], rtol=0, atol=1e-12)
+    assert np.allclose(O.box_blur(np.full((6, 7, 8), 2.5), 3, 2), 2.5, rtol=0, atol=1e-14)
