@@ -252,6 +252,18 @@ def large_volume_roofline(stream, reps):
     out = octave0_roofline(plan, passes, pass_ms, "config4")
     out["workload"] = "config4: 512x512x384 smoothed noise + 4000 blobs"
     out["ms_per_extraction"] = round(ms, 4)
+    # uniform-filter approximation of the largest increment (sigma 3.09,
+    # three passes per axis) on the same volume, beside the Gaussian pass
+    # that computes that level (blur + DoG)
+    box_out, box_tmp = torch.empty_like(dvol), torch.empty_like(dvol)
+    h = S.box_half_width(3.09, 3)
+    S.box_blur(dvol, h, 3, box_out, box_tmp, stream)
+    box_ms = time_calls(lambda: S.box_blur(dvol, h, 3, box_out, box_tmp, stream), reps, stream)
+    g5 = [i for i, p in enumerate(passes) if p[0] == 0 and p[1] == 5]
+    out["box"] = {"sigma": 3.09, "passes": 3, "half_width": h, "ms": round(box_ms, 4),
+                  "algorithmic_gb_per_s": round(3 * 8 * dvol.numel() / (box_ms * 1e-3) / 1e9, 1),
+                  "gaussian_level_pass_ms": round(pass_ms[g5[0]], 4) if g5 else None}
+    del box_out, box_tmp
     del buf, plan, dvol
     torch.cuda.empty_cache()
     return out
@@ -566,12 +578,14 @@ def main():
         log(f"[bench]   pass o={o} G{lev} r={r} sub={sub}: {t * 1e3:.2f} us, {b / t / 1e6:.0f} GB/s algorithmic")
 
     roofline = octave0_roofline(plan, passes, pass_ms, args.workload)
-    large = None
+    large = box = None
     if not args.no_large and args.workload != "config4":
         del buf
         torch.cuda.empty_cache()
         large = large_volume_roofline(stream, max(3, reps // 4))
+        box = large.pop("box")
         log(f"[bench] roofline 512x512x384: {large}")
+        log(f"[bench] box blur 512x512x384: {box}")
 
     match = match_throughput(stream)
     log(f"[bench] match: {match}")
@@ -621,6 +635,7 @@ def main():
         "batch": batch,
         "serve": serve,
         "match": match,
+        "box": box,
         "cpu_baseline": cpu,
         "paper_context": "paper: 1.4 s CPU, 0.2 s GPU per 145x174x145 volume (~3000 keypoints, hardware unnamed)",
     }

@@ -357,7 +357,6 @@ double sift3d_server_clock(void);
  */
 int sift3d_server_destroy(sift3d_server *srv);
 
-/* Static description of an error code. */
 /*
  * Nearest-neighbour matching of descriptors (keypoints are matched by their
  * descriptors, Section 3.3). For every row i of A: d_idx[i] = the index of
@@ -380,6 +379,33 @@ int sift3d_server_destroy(sift3d_server *srv);
 int sift3d_match(int kind, const void *d_a, int n_a, const void *d_b, int n_b, int row_elems, int32_t *d_idx,
                  int32_t *d_d1, int32_t *d_d2, void *stream);
 
+/*
+ * Uniform-filter approximation of a Gaussian blur (Related Work: the
+ * Gaussian scale space can also be generated with separable uniform 1D
+ * filters). Along x, then y, then z, `passes` uniform passes of width
+ * 2*half_width+1 are applied; an output is the mean of the 2*half_width+1
+ * samples centred on it, indices outside the volume clamped to the nearest
+ * edge (each pass sees the volume's edges). FP32, each sum taken in index
+ * order. d_in, d_out and d_tmp are distinct device buffers of nx*ny*nz
+ * floats ([z][y][x], x fastest) owned by the caller; d_out receives the
+ * result and d_tmp is overwritten. 1 <= passes <= 4, 0 <= half_width <= 8,
+ * passes * half_width <= 28. Stream-ordered, allocates nothing.
+ * SIFT3D_E_ARG for a bad size, count or pointer.
+ */
+int sift3d_box_blur(const float *d_in, float *d_out, float *d_tmp, int nx, int ny, int nz, int half_width,
+                    int passes, void *stream);
+
+/*
+ * Half-width of the uniform filter whose `passes`-fold repetition stands in
+ * for a Gaussian of standard deviation sigma: a width-w uniform filter has
+ * variance (w*w - 1)/12, so one of m equal passes ideally has width
+ * sqrt(12 sigma^2 / m + 1); *half_width is the integer nearest to
+ * (that width - 1) / 2 (halves round up). Host only. SIFT3D_E_ARG for
+ * sigma < 0, passes < 1 or a null pointer.
+ */
+int sift3d_box_half_width(double sigma, int passes, int *half_width);
+
+/* Static description of an error code. */
 const char *sift3d_error_string(int code);
 
 /* hipError_t of the last failing HIP call made by the library on this thread. */

@@ -15,6 +15,8 @@ from .sift3d import (  # noqa: F401
     Plan,
     Server,
     Sift3dError,
+    box_blur,
+    box_half_width,
     default_params,
     pair_offsets,
     exported_symbols,

@@ -872,6 +872,9 @@ namespace s3d {
 // Nearest-neighbour matching launcher (match.hip).
 hipError_t launch_match(int kind, const void *a, int n_a, const void *b, int n_b, int row_elems, int32_t *idx,
                         int32_t *d1, int32_t *d2, hipStream_t st);
+// Uniform-filter blur launcher (box.hip).
+hipError_t launch_box(const float *in, float *out, float *tmp, int nx, int ny, int nz, int h, int passes,
+                      hipStream_t st);
 }  // namespace s3d
 
 extern "C" {
@@ -1193,6 +1196,28 @@ int sift3d_match(int kind, const void *d_a, int n_a, const void *d_b, int n_b, i
     const hipError_t e = launch_match(kind, d_a, n_a, d_b, n_b, row_elems, d_idx, d_d1, d_d2,
                                       static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
+}
+
+int sift3d_box_blur(const float *d_in, float *d_out, float *d_tmp, int nx, int ny, int nz, int half_width,
+                    int passes, void *stream)
+{
+    if (d_in == nullptr || d_out == nullptr || d_tmp == nullptr) return SIFT3D_E_ARG;
+    if (d_in == d_out || d_in == d_tmp || d_out == d_tmp) return SIFT3D_E_ARG;
+    if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny > (1LL << 30)) return SIFT3D_E_ARG;
+    if (passes < 1 || passes > 4 || half_width < 0 || half_width > 8 || passes * half_width > 28) return SIFT3D_E_ARG;
+    const hipError_t e = launch_box(d_in, d_out, d_tmp, nx, ny, nz, half_width, passes,
+                                    static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
+}
+
+int sift3d_box_half_width(double sigma, int passes, int *half_width)
+{
+    if (half_width == nullptr || !(sigma >= 0.0) || passes < 1) return SIFT3D_E_ARG;
+    const double w = std::sqrt(12.0 * sigma * sigma / passes + 1.0);
+    const double h = std::floor((w - 1.0) / 2.0 + 0.5);
+    if (h > 1e9) return SIFT3D_E_ARG;
+    *half_width = (int)h;
+    return SIFT3D_OK;
 }
 
 const char *sift3d_error_string(int code)

@@ -142,6 +142,8 @@ def _load():
         "sift3d_server_clock": (ctypes.c_double, []),
         "sift3d_server_destroy": (i, [_vp]),
         "sift3d_match": (i, [i, _vp, i, _vp, i, i, _vp, _vp, _vp, _vp]),
+        "sift3d_box_blur": (i, [_vp, _vp, _vp, i, i, i, i, i, _vp]),
+        "sift3d_box_half_width": (i, [ctypes.c_double, i, P(i)]),
         "sift3d_error_string": (ctypes.c_char_p, [i]),
         "sift3d_last_hip_error": (i, []),
     }
@@ -199,6 +201,30 @@ def match(a, b, kind: int, stream=None):
                                 int(a.shape[1]), _vp(idx.data_ptr()), _vp(d1.data_ptr()), _vp(d2.data_ptr()),
                                 _vp(_stream(stream))), "sift3d_match")
     return idx, d1, d2
+
+
+def box_half_width(sigma: float, passes: int) -> int:
+    """Half-width of the uniform filter whose `passes`-fold repetition stands
+    in for a Gaussian of standard deviation sigma (sift3d_box_half_width)."""
+    h = ctypes.c_int()
+    _check(_load().sift3d_box_half_width(float(sigma), int(passes), ctypes.byref(h)), "sift3d_box_half_width")
+    return h.value
+
+
+def box_blur(vol, half_width: int, passes: int, out=None, tmp=None, stream=None):
+    """Uniform-filter blur of a float32 [z,y,x] device tensor (sift3d_box_blur):
+    `passes` clamp-to-edge passes of width 2*half_width+1 along x, y, then z.
+    Returns `out` (allocated when None); `tmp` is scratch of the same size."""
+    import torch
+    assert vol.is_cuda and vol.dtype == torch.float32 and vol.dim() == 3 and vol.is_contiguous()
+    nz, ny, nx = vol.shape
+    if out is None:
+        out = torch.empty_like(vol)
+    if tmp is None:
+        tmp = torch.empty_like(vol)
+    _check(_load().sift3d_box_blur(_vp(vol.data_ptr()), _vp(out.data_ptr()), _vp(tmp.data_ptr()), nx, ny, nz,
+                                   int(half_width), int(passes), _vp(_stream(stream))), "sift3d_box_blur")
+    return out
 
 
 def default_params(**overrides) -> Params:

@@ -121,3 +121,31 @@ def test_match_argument_checks():
     assert lib.sift3d_match(1, null, 1, null, 1, 100, null, null, null, null) == -1  # ranks not a multiple of 64
     assert lib.sift3d_match(1, null, 1, null, 1, 64, null, null, null, null) == -1   # null pointers
     assert lib.sift3d_match(1, null, -1, null, 1, 64, null, null, null, null) == -1  # negative size
+
+
+def test_box_half_width_host_function_matches_oracle():
+    import paper_2112_10258_amd as S
+    for m in (1, 2, 3, 4):
+        for sigma in (0.0, 0.5, 0.95, 1.2263, 1.6, 2.0, 2.4525, 3.09, 5.0, 8.0):
+            assert S.box_half_width(sigma, m) == O.box_half_width(sigma, m), (sigma, m)
+    for sigma, m in ((-1.0, 3), (1.0, 0)):
+        with pytest.raises(S.Sift3dError) as ei:
+            S.box_half_width(sigma, m)
+        assert ei.value.code == -1
+
+
+def test_box_blur_argument_checks():
+    """Refused before any device call: null or aliased buffers, empty dims,
+    pass counts outside 1..4, half-widths outside 0..8, reach above 28."""
+    import paper_2112_10258_amd.sift3d as S
+    lib = S._load()
+    a, b, c = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    bad = [
+        (None, b, c, 8, 8, 8, 1, 3), (a, None, c, 8, 8, 8, 1, 3), (a, b, None, 8, 8, 8, 1, 3),
+        (a, a, c, 8, 8, 8, 1, 3), (a, b, b, 8, 8, 8, 1, 3), (a, b, a, 8, 8, 8, 1, 3),
+        (a, b, c, 0, 8, 8, 1, 3), (a, b, c, 8, -1, 8, 1, 3), (a, b, c, 8, 8, 0, 1, 3),
+        (a, b, c, 8, 8, 8, 1, 0), (a, b, c, 8, 8, 8, 1, 5), (a, b, c, 8, 8, 8, -1, 3),
+        (a, b, c, 8, 8, 8, 8, 4), (a, b, c, 8, 8, 8, 15, 2), (a, b, c, 8, 8, 8, 9, 1), (a, b, c, 1 << 16, 1 << 15, 1, 1, 1),
+    ]
+    for args in bad:
+        assert lib.sift3d_box_blur(*args, None) == -1, args
