@@ -388,8 +388,8 @@ int sift3d_match(int kind, const void *d_a, int n_a, const void *d_b, int n_b, i
  * edge (each pass sees the volume's edges). FP32, each sum taken in index
  * order. d_in, d_out and d_tmp are distinct device buffers of nx*ny*nz
  * floats ([z][y][x], x fastest) owned by the caller; d_out receives the
- * result and d_tmp is overwritten. 1 <= passes <= 4, 0 <= half_width <= 8,
- * passes * half_width <= 28. Stream-ordered, allocates nothing.
+ * result and d_tmp is overwritten. nx*ny <= 2^30, nz <= 2^30,
+ * 1 <= passes <= 4, 0 <= half_width <= 8, passes * half_width <= 28. Stream-ordered, allocates nothing.
  * SIFT3D_E_ARG for a bad size, count or pointer.
  */
 int sift3d_box_blur(const float *d_in, float *d_out, float *d_tmp, int nx, int ny, int nz, int half_width,

@@ -1203,7 +1203,8 @@ int sift3d_box_blur(const float *d_in, float *d_out, float *d_tmp, int nx, int n
 {
     if (d_in == nullptr || d_out == nullptr || d_tmp == nullptr) return SIFT3D_E_ARG;
     if (d_in == d_out || d_in == d_tmp || d_out == d_tmp) return SIFT3D_E_ARG;
-    if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny > (1LL << 30)) return SIFT3D_E_ARG;
+    // positions along an axis stay far from int overflow (tile start + 120)
+    if (nx < 1 || ny < 1 || nz < 1 || nz > (1 << 30) || (long long)nx * ny > (1LL << 30)) return SIFT3D_E_ARG;
     if (passes < 1 || passes > 4 || half_width < 0 || half_width > 8 || passes * half_width > 28) return SIFT3D_E_ARG;
     const hipError_t e = launch_box(d_in, d_out, d_tmp, nx, ny, nz, half_width, passes,
                                     static_cast<hipStream_t>(stream));

@@ -135,7 +135,8 @@ def test_box_half_width_host_function_matches_oracle():
 
 
 def test_box_blur_argument_checks():
-    """Refused before any device call: null or aliased buffers, empty dims,
+    """Refused before any device call: null or aliased buffers, empty or
+    oversized dims,
     pass counts outside 1..4, half-widths outside 0..8, reach above 28."""
     import paper_2112_10258_amd.sift3d as S
     lib = S._load()
@@ -145,7 +146,7 @@ def test_box_blur_argument_checks():
         (a, a, c, 8, 8, 8, 1, 3), (a, b, b, 8, 8, 8, 1, 3), (a, b, a, 8, 8, 8, 1, 3),
         (a, b, c, 0, 8, 8, 1, 3), (a, b, c, 8, -1, 8, 1, 3), (a, b, c, 8, 8, 0, 1, 3),
         (a, b, c, 8, 8, 8, 1, 0), (a, b, c, 8, 8, 8, 1, 5), (a, b, c, 8, 8, 8, -1, 3),
-        (a, b, c, 8, 8, 8, 8, 4), (a, b, c, 8, 8, 8, 15, 2), (a, b, c, 8, 8, 8, 9, 1), (a, b, c, 1 << 16, 1 << 15, 1, 1, 1),
+        (a, b, c, 8, 8, 8, 8, 4), (a, b, c, 8, 8, 8, 15, 2), (a, b, c, 8, 8, 8, 9, 1), (a, b, c, 1 << 16, 1 << 15, 1, 1, 1), (a, b, c, 1, 1, (1 << 30) + 1, 1, 1),
     ]
     for args in bad:
         assert lib.sift3d_box_blur(*args, None) == -1, args
