@@ -216,12 +216,18 @@ def box_blur(vol, half_width: int, passes: int, out=None, tmp=None, stream=None)
     `passes` clamp-to-edge passes of width 2*half_width+1 along x, y, then z.
     Returns `out` (allocated when None); `tmp` is scratch of the same size."""
     import torch
-    assert vol.is_cuda and vol.dtype == torch.float32 and vol.dim() == 3 and vol.is_contiguous()
+    if not (vol.is_cuda and vol.dtype == torch.float32 and vol.dim() == 3 and vol.is_contiguous()):
+        raise ValueError("box_blur: vol must be a contiguous float32 [z,y,x] device tensor")
     nz, ny, nx = vol.shape
     if out is None:
         out = torch.empty_like(vol)
     if tmp is None:
         tmp = torch.empty_like(vol)
+    for name, t in (("out", out), ("tmp", tmp)):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == vol.numel()):
+            raise ValueError(f"box_blur: {name} must be a contiguous float32 device tensor of vol's size")
+    if len({vol.data_ptr(), out.data_ptr(), tmp.data_ptr()}) != 3:
+        raise ValueError("box_blur: vol, out and tmp must be distinct buffers")
     _check(_load().sift3d_box_blur(_vp(vol.data_ptr()), _vp(out.data_ptr()), _vp(tmp.data_ptr()), nx, ny, nz,
                                    int(half_width), int(passes), _vp(_stream(stream))), "sift3d_box_blur")
     return out

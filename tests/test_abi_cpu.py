@@ -150,3 +150,11 @@ def test_box_blur_argument_checks():
     ]
     for args in bad:
         assert lib.sift3d_box_blur(*args, None) == -1, args
+
+
+def test_box_blur_binding_rejects_host_tensors():
+    import torch
+
+    import paper_2112_10258_amd as S
+    with pytest.raises(ValueError):
+        S.box_blur(torch.zeros(4, 5, 6), 1, 3)

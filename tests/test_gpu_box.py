@@ -83,3 +83,21 @@ def test_box_blur_full_size_sampled():
         blk = vol[z0:z + reach + 1, y0:y + reach + 1, x0:x + reach + 1]
         ref = O.box_blur(blk, h, m)[z - z0, y - y0, x - x0]
         assert abs(float(g[z, y, x]) - ref) <= tol, (x, y, z)
+
+
+def test_box_blur_binding_checks_buffers():
+    """Wrong-sized, wrong-typed or aliased out/tmp buffers are refused on the
+    host, before any launch."""
+    import torch
+
+    import paper_2112_10258_amd as S
+    vol = torch.zeros(8, 9, 10, device="cuda")
+    with pytest.raises(ValueError):
+        S.box_blur(vol, 1, 3, out=torch.empty(8, 9, 9, device="cuda"))
+    with pytest.raises(ValueError):
+        S.box_blur(vol, 1, 3, tmp=torch.empty(8, 9, 10, device="cuda", dtype=torch.float64))
+    with pytest.raises(ValueError):
+        S.box_blur(vol, 1, 3, out=vol)
+    o = torch.empty_like(vol)
+    with pytest.raises(ValueError):
+        S.box_blur(vol, 1, 3, out=o, tmp=o)
