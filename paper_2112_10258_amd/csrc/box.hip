@@ -92,25 +92,41 @@ __global__ void __launch_bounds__(kBoxThreads) box_axis_kernel(const BoxArgs a)
     }
     __syncthreads();
 
+    // Each wavefront takes a contiguous quarter of the pass's positions on
+    // every line and slides a register window of the 2H+1 (clamped) taps
+    // along it: one LDS read per output for the incoming tap, the sum still
+    // taken over the window in index order.
     float *s = buf + lane * pitch;
     for (int k = 1; k <= a.passes; ++k) {
-        const int lo = max(k * H, -p0) + wave, hi = min(E - k * H, n - p0);
+        const int lo = max(k * H, -p0), hi = min(E - k * H, n - p0);
+        const int chunk = (hi - lo + 3) >> 2;
+        const int c0 = lo + wave * chunk;
+        const int len = min(chunk, hi - c0);   // positions of this wavefront (may be <= 0)
         float o[kBoxPerLane];
+        if (len > 0) {
+            const int pb = p0 + c0;            // its first axis position
+            float win[2 * H + 1];
 #pragma unroll
-        for (int q = 0; q < kBoxPerLane; ++q) {
-            const int i = lo + 4 * q;
-            if (i < hi) {
-                const int p = p0 + i;
-                float acc = 0.f;
+            for (int j = 0; j < 2 * H + 1; ++j) win[j] = s[min(max(pb - H + j, 0), n - 1) - p0];
 #pragma unroll
-                for (int j = -H; j <= H; ++j) acc += s[min(max(p + j, 0), n - 1) - p0];
-                o[q] = acc * a.inv_w;
+            for (int q = 0; q < kBoxPerLane; ++q) {
+                if (q < len) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int j = 0; j < 2 * H + 1; ++j) acc += win[j];
+                    o[q] = acc * a.inv_w;
+#pragma unroll
+                    for (int j = 0; j < 2 * H; ++j) win[j] = win[j + 1];
+                    // the next tap; after the last output this reads at most
+                    // local index E, the row's padding slot, and is unused
+                    win[2 * H] = s[min(max(pb + q + 1 + H, 0), n - 1) - p0];
+                }
             }
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kBoxPerLane; ++q)
-            if (lo + 4 * q < hi) s[lo + 4 * q] = o[q];
+            if (q < len) s[c0 + q] = o[q];
         __syncthreads();
     }
 
