@@ -555,3 +555,121 @@ def test_box_half_width_values():
     out = O.box_blur(ramp, 2, 3)
     assert np.allclose(out[:, :, 6:24], ramp[:, :, 6:24], rtol=0, atol=1e-12)
     assert np.allclose(O.box_blur(np.full((6, 7, 8), 2.5), 3, 2), 2.5, rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------------------ describe() and detect() wiring
+# The pins above call the descriptor primitives directly. These go through
+# describe() and detect(), so that the choice of level (G_s of octave o),
+# SIFT-Rank half-width (R_s) and pair table (scale s), the pre-blur taps and
+# the input-space position are each fixed by a value a slip would change.
+
+def _sigma_s(s):
+    # keypoint scale of level s in its octave's voxels: sigma0 * 2^(s/S)
+    return 1.6 * 2.0 ** (s / 3.0)
+
+
+def _levels(n_oct, make):
+    """G_levels[o][i] = make(o, i) for i = 0..S+2."""
+    return [[make(o, i) for i in range(6)] for o in range(n_oct)]
+
+
+def _kps(rows):
+    k = np.zeros(len(rows), dtype=O.KEYPOINT_DTYPE)
+    for j, (o, s, x, y, z) in enumerate(rows):
+        k[j]["octave"], k[j]["scale"], k[j]["x"], k[j]["y"], k[j]["z"] = o, s, x, y, z
+    return k
+
+
+def test_describe_takes_level_radius_and_pair_scale_of_each_keypoint():
+    # Every level G_i of octave o is a ramp along x with its own slope a(o, i).
+    # On a ramp (away from the edges) SIFT-Rank puts |a| (R + 1/2)^3 into the
+    # +x (or -x) orientation bin of each spatial bin, with R the half-width of
+    # the keypoint's scale: 5, 6, 7 for s = 1, 2, 3 (ceil(2 sigma_s)). The
+    # pre-blur leaves a ramp unchanged, so BRIEF gives d_i = a (o1 - o2)_x with
+    # the offsets of the keypoint's own scale. A wrong level, octave, radius
+    # or pair table changes one of these numbers.
+    n = 80
+    slope = {(o, i): (0.3 + 0.1 * i + 0.05 * o) * (-1.0) ** i for o in range(2) for i in range(6)}
+    G = _levels(2, lambda o, i: _ramp(n, 0, slope[(o, i)]))
+    rows = [(o, s, 40, 40, 40) for o in range(2) for s in (1, 2, 3)]
+    kps = _kps(rows)
+    draws = P.pair_draws(1, 256)
+    p = O.Params()
+    out = O.describe(G, kps, draws, p)
+    z = draws.reshape(-1, 2, 3)
+    for j, (o, s, _, _, _) in enumerate(rows):
+        a = slope[(o, s)]
+        R = {1: 5, 2: 6, 3: 7}[s]
+        assert R == math.ceil(2.0 * _sigma_s(s))
+        bo = 1 if a > 0 else 0
+        want = np.zeros(64)
+        for bs in range(8):
+            want[8 * bs + bo] = abs(a) * (R + 0.5) ** 3
+        np.testing.assert_allclose(out["hist"][j], want, rtol=1e-13, atol=1e-12)
+        # method 3 at this scale: o1 = round(sigma_s z1), o2 = round(sigma_s (z1 + z2))
+        o1 = np.floor(_sigma_s(s) * z[:, 0, 0] + 0.5)
+        o2 = np.floor(_sigma_s(s) * (z[:, 0, 0] + z[:, 1, 0]) + 0.5)
+        assert max(np.abs(o1).max(), np.abs(o2).max()) + 3 < 40
+        np.testing.assert_allclose(out["diff"][j], a * (o1 - o2), rtol=0, atol=1e-12)
+
+
+def _draws_for_offsets(o1, o2, s):
+    """Method-3 draws (z1, z2) whose scale-s offsets are exactly o1 and o2."""
+    sig = _sigma_s(s)
+    z1 = np.asarray(o1, dtype=np.float64) / sig
+    z2 = (np.asarray(o2, dtype=np.float64) - np.asarray(o1, dtype=np.float64)) / sig
+    return np.stack([z1, z2], axis=1)
+
+
+def test_describe_preblur_weights_from_an_impulse():
+    # G_s holds one impulse of height A(o, s) at the keypoint. Pair i has p1 at
+    # offset (a, b, c) from it, |a|, |b|, |c| <= 3 = ceil(3 * 0.95), and p2 far
+    # away, so d_i = B(p1) = A(o, s) w_a w_b w_c with w the pre-blur taps of
+    # sigma_b = 0.95 (exp(-t^2 / (2 sigma_b^2)) normalised over t = -3..3).
+    # Unequal (a, b, c) catch a stencil that reuses one axis's index; a wrong
+    # sigma_b, level or octave changes every d_i.
+    n, c0 = 48, 24
+    rng = np.random.default_rng(11)
+    o1 = rng.integers(-3, 4, (64, 3))
+    o1[:8] = [[1, 2, 3], [-3, 0, 2], [0, 0, 0], [3, 3, 3], [-1, -2, 0], [2, -3, 1], [0, 1, -2], [-3, -3, 3]]
+    o2 = np.tile([[15, -15, 15]], (64, 1))
+    amp = {(o, i): 1.0 + 0.25 * i + 2.0 * o for o in range(2) for i in range(6)}
+
+    def impulse(o, i):
+        g = np.zeros((n, n, n))
+        g[c0, c0, c0] = amp[(o, i)]
+        return g
+
+    G = _levels(2, impulse)
+    t = np.arange(-3, 4)
+    w = np.exp(-t * t / (2 * 0.95 ** 2))
+    w /= w.sum()
+    p = O.Params(brief_n=64)
+    for o in range(2):
+        for s in (1, 2, 3):
+            draws = _draws_for_offsets(o1, o2, s)
+            np.testing.assert_array_equal(O.pair_offsets(draws, p, s)[:, 0], o1)
+            out = O.describe(G, _kps([(o, s, c0, c0, c0)]), draws, p)
+            want = amp[(o, s)] * w[3 - o1[:, 0]] * w[3 - o1[:, 1]] * w[3 - o1[:, 2]]
+            np.testing.assert_allclose(out["diff"][0], want, rtol=1e-13, atol=0)
+            assert np.all(out["diff"][0] > 0)
+
+
+@pytest.mark.parametrize("sb,o,s", [(3.5, 0, 2), (5.5, 1, 1), (7.0, 1, 2)])
+def test_detect_input_space_position_and_sigma_exact(sb, o, s):
+    # A blob centred on a voxel centre of octave o is found at that voxel; its
+    # input-space position is 2^o x + (2^o - 1)/2, the centre of the 2^o-wide
+    # block of input voxels the octave voxel averages, which is the blob centre
+    # itself. sigma = sigma0 2^(s/S) 2^o.
+    p = O.Params(n_octaves=2, min_dim=8)
+    n = 96 if o == 1 else 64
+    c = (n // 2) * 1.0 + (0.5 if o == 1 else 0.0)
+    octs = O.pyramid(_blob(n, c, sb), p)
+    k = O.detect([oc.D for oc in octs], p)
+    hit = k[(k["octave"] == o) & (k["scale"] == s) & (np.abs(k["xf"] - c) < 1.5)
+            & (np.abs(k["yf"] - c) < 1.5) & (np.abs(k["zf"] - c) < 1.5)]
+    assert len(hit) == 1
+    h = hit[0]
+    assert (float(h["xf"]), float(h["yf"]), float(h["zf"])) == (c, c, c)
+    assert int(h["x"]) * 2 ** o + (2 ** o - 1) / 2 == c
+    assert float(h["sigma"]) == pytest.approx(_sigma_s(s) * 2 ** o, rel=1e-7)
