@@ -6,7 +6,15 @@ A step is one whole extraction (Gaussian/DoG pyramid with sub-sampling,
 descriptors) of one synthetic volume already resident in HBM. Prints one
 JSON line on stdout; diagnostics go to stderr.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config4]
+
+The headline workload is the 512x512x384 volume (config 4), the largest
+single-volume configuration, whose levels do not fit the last-level cache.
+Each timed step runs the pyramid launches one by one through the library's
+step entry point (the same kernels, grids and order as sift3d_build_pyramid),
+records a HIP event on the launch stream after each, then detection and the
+descriptors: the per-launch durations of the roofline come from the timed
+steps themselves.
 """
 from __future__ import annotations
 
@@ -81,29 +89,13 @@ def read_traffic(workload):
     return None if w is None else w.get("hbm_bytes_per_launch")
 
 
-def octave0_grids(shape_xyz):
-    """Grid sizes (threads) of a solo octave-0 level pass: fused, xy, z."""
-    nx, ny, nz = shape_xyz
-    cdiv = lambda a, b: (a + b - 1) // b  # noqa: E731
-    tiles = cdiv(nx, 64) * cdiv(ny, 16)
-    planes = 4   # planes per xy block, as the plan picks them
-    while planes > 1 and tiles * cdiv(nz, planes) < 1024:
-        planes //= 2
-    return {"xy": tiles * cdiv(nz, planes) * 256, "z": cdiv(nx, 32) * cdiv(ny, 8) * cdiv(nz, 16) * 256}
-
-
-def summarize_pmc(fetch_dir, write_dir, workloads, out_path, reps):
+def summarize_pmc(fetch_dir, write_dir, workload, out_path):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of two rocprofv3 --pmc runs
-    of this script (with --copy-calibration) -> bytes per octave-0 level pass
-    G_1..G_5, scaled by what the same counters read for a 1 GiB device copy.
-
-    Level i of octave 0 (default parameters: radii 4, 5, 6, 8, 10) runs on the
-    fused pass when the octave has >= 24M voxels, or >= 2M voxels and radius
-    <= 8 (the plan's rule); its dispatches are blur_level_kernel<R, true, *>
-    at the largest grid of that instantiation. Otherwise it is the xy + z
-    pair launched alone, at the octave-0 grids of those kernels. The counter
-    runs use --pmc-passes reps, whose last dispatches are the octave-0 passes
-    launched alone, reps times each."""
+    of this script (--copy-calibration --pmc-steps N) -> bytes per octave-0
+    level launch G_1..G_5, scaled by what the same counters read for a 1 GiB
+    device copy. The octave-0 launch of radius R is the blur_level_kernel<R,
+    true, ...> dispatch with the largest grid (default parameters: radii 4, 5,
+    6, 8, 10; on 512x512x384 every octave-0 level runs on the fused pass)."""
     import csv
     import glob
     import re
@@ -133,7 +125,7 @@ def summarize_pmc(fetch_dir, write_dir, workloads, out_path, reps):
     f_factor, w_factor = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
     calib = {"bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
              "fetch_factor": round(f_factor, 4), "write_factor": round(w_factor, 4)}
-    out = {"what": "bytes beyond L2 (TCC FETCH_SIZE + WRITE_SIZE) per octave-0 level pass G_1..G_5, "
+    out = {"what": "bytes beyond L2 (TCC FETCH_SIZE + WRITE_SIZE) per octave-0 level launch G_1..G_5, "
                    "scaled by the counters' reading on a plain 1 GiB device copy",
            "kernel_source_sha256_16": kernel_source_hash(), "workloads": {}}
     if os.path.exists(out_path):
@@ -143,60 +135,61 @@ def summarize_pmc(fetch_dir, write_dir, workloads, out_path, reps):
                 out["workloads"] = old.get("workloads", {})
         except ValueError:
             pass
-    fused_re = re.compile(r"^blur_level_kernel<(\d+), (true|false)")
+    fused_re = re.compile(r"^blur_level_kernel<(\d+), true")
 
-    def fused_sel(rs, R):
-        # the --pmc-passes runs end with the octave-0 passes: the last reps
-        # dispatches of this instantiation
-        ds = [v for k, g, v in rs if (m := fused_re.match(k)) and int(m.group(1)) == R and m.group(2) == "true"]
-        return ds[-reps:]
+    def octave0(rs, R):
+        ds = [(g, v) for k, g, v in rs if (m := fused_re.match(k)) and int(m.group(1)) == R]
+        if not ds:
+            return []
+        gmax = max(g for g, _ in ds)
+        return [v for g, v in ds if g == gmax]
 
-    for wl, shape in workloads.items():
-        n = int(np.prod(shape))
-        grids = octave0_grids(shape)
-        levels = []
-        for i, R in enumerate((4, 5, 6, 8, 10), start=1):
-            fused = n >= (24 << 20) or (n >= (2 << 20) and R <= 8)
-            if fused:
-                f, w = fused_sel(fr, R), fused_sel(wr, R)
-                kern = f"blur_level_kernel<{R}>"
-            else:
-                f = [sum(v) for v in zip(*[[v for k, g, v in fr if k.startswith(kn) and g == grids[key]][-reps:]
-                                           for kn, key in (("blur_xy_kernel", "xy"), ("blur_z_kernel", "z"))])]
-                w = [sum(v) for v in zip(*[[v for k, g, v in wr if k.startswith(kn) and g == grids[key]][-reps:]
-                                           for kn, key in (("blur_xy_kernel", "xy"), ("blur_z_kernel", "z"))])]
-                kern = "blur_xy_kernel + blur_z_kernel"
-            if not f or not w:
-                continue
-            levels.append({"level": f"G_{i}", "radius": R, "kernel": kern, "dispatches": len(f),
-                           "fetch_bytes": int(np.mean(f) * 1024 * f_factor),
-                           "write_bytes": int(np.mean(w) * 1024 * w_factor)})
-        if not levels:
+    levels = []
+    for i, R in enumerate((4, 5, 6, 8, 10), start=1):
+        f, w = octave0(fr, R), octave0(wr, R)
+        if not f or not w:
             continue
+        levels.append({"level": f"G_{i}", "radius": R, "kernel": f"blur_level_kernel<{R}, true, ...>",
+                       "dispatches": len(f), "fetch_bytes": int(np.mean(f) * 1024 * f_factor),
+                       "write_bytes": int(np.mean(w) * 1024 * w_factor)})
+    if levels:
         tot = float(np.mean([lv["fetch_bytes"] + lv["write_bytes"] for lv in levels]))
-        out["workloads"][wl] = {"shape_xyz": list(shape), "levels": levels, "hbm_bytes_per_launch": int(tot),
-                                "copy_calibration": calib, "fetch_dir": fetch_dir, "write_dir": write_dir}
-    with open(out_path, "w") as f:
-        json.dump(out, f, indent=1)
-        f.write("\n")
+        out["workloads"][workload] = {"levels": levels, "hbm_bytes_per_launch": int(tot),
+                                      "copy_calibration": calib}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
     print(json.dumps(out, indent=1))
 
 
-def octave0_roofline(plan, passes, pass_ms, workload):
-    """Roofline of the octave-0 level passes G_1..G_{S+2} (blur + DoG +
-    sub-sample): algorithmic bytes per pass over its measured duration."""
-    sel = [i for i, p in enumerate(passes) if p[0] == 0 and p[1] > 0]
-    names = {1: "blur_level_kernel", 2: "blur_compact_kernel", 0: "blur_xy_kernel + blur_z_kernel"}
-    kparts = []
-    for path in (1, 2, 0):
-        lv = [f"G_{passes[i][1]}" for i in sel if passes[i][5] == path]
-        if lv:
-            kparts.append(names[path] + " (" + ", ".join(lv) + ")")
-    bytes_per_launch = sum(passes[i][4] for i in sel) / len(sel)
-    dur_ms = sum(pass_ms[i] for i in sel) / len(sel)
+KIND_NAMES = {0: "blur_level_kernel", 1: "blur_xy_kernel", 2: "blur_z_kernel", 3: "blur_compact_kernel"}
+
+
+def launch_roofline(steps_info, launch_ms, workload):
+    """Roofline of the octave-0 level launches G_1..G_{S+2} of the schedule
+    (blur + DoG, the sub-sample on G_S, and the BRIEF pre-blurred level where
+    the launch writes it): algorithmic bytes per launch over the launch's
+    average duration in the timed steps."""
+    sel = [i for i, st in enumerate(steps_info)
+           if st["octaves"] == (0, 0) and st["levels"][0] >= 1 and st["kind"] != 1]
+    kinds = sorted({steps_info[i]["kind"] for i in sel})
+    names = ", ".join(KIND_NAMES[k] for k in kinds)
+    per = []
+    for i in sel:
+        ms = launch_ms[i]
+        # a two-launch level: its xy half's time counts with its z half
+        if steps_info[i]["kind"] == 2 and i > 0 and steps_info[i - 1]["kind"] == 1:
+            ms += launch_ms[i - 1]
+        per.append({"levels": "G_%d" % steps_info[i]["levels"][0] if steps_info[i]["levels"][0] ==
+                    steps_info[i]["levels"][1] else "G_%d..G_%d" % steps_info[i]["levels"],
+                    "radius": steps_info[i]["max_r"], "kernel": KIND_NAMES[steps_info[i]["kind"]],
+                    "pb": steps_info[i]["pb"], "bytes": steps_info[i]["bytes"], "us": round(ms * 1e3, 2),
+                    "frac": round(steps_info[i]["bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    bytes_per_launch = sum(p["bytes"] for p in per) / len(per)
+    dur_ms = sum(p["us"] for p in per) / len(per) / 1e3
     achieved = bytes_per_launch / (dur_ms * 1e-3) / 1e9
     return {
-        "kernel": " + ".join(kparts) + ": octave-0 pyramid level passes (blur + DoG + sub-sample)",
+        "kernel": f"{names}: octave-0 level launches G_1..G_5 (blur + DoG + sub-sample + BRIEF pre-blur)",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -205,7 +198,84 @@ def octave0_roofline(plan, passes, pass_ms, workload):
         "traffic": read_traffic(workload),
         "bytes_per_launch": int(bytes_per_launch),
         "avg_launch_us": round(dur_ms * 1e3, 3),
+        "launches": per,
     }
+
+
+def measure_plain(name, steps, warmup, kw, stream, stage_reps=10, vol=None):
+    """K timed whole extractions of one volume resident in HBM (instrumented
+    steps), then a separate stage breakdown. Returns (result dict, context for
+    later use)."""
+    import torch
+
+    import paper_2112_10258_amd as S
+    from gen import phantoms as P
+    if vol is None:
+        vol = make_volume(name)
+    nz, ny, nx = vol.shape
+    cap = 1 << 17
+    ctx = S.Context(S.default_params(**kw), P.pair_draws())
+    plan = S.Plan(ctx, (nx, ny, nz), cap)
+    buf = S.Buffers(plan)
+    dvol = torch.from_numpy(vol).cuda()
+    steps_info = plan.pyramid_steps()
+    nl = len(steps_info)
+
+    def step(evs=None):
+        if evs is not None:
+            evs[0].record(stream)
+        for i in range(nl):
+            plan.pyramid_step(i, dvol, buf.ws, stream)
+            if evs is not None:
+                evs[i + 1].record(stream)
+        plan.detect(buf.ws, buf.kp, buf.count, stream)
+        plan.describe(buf.ws, buf.kp, buf.count, buf.siftrank, buf.brief, buf.rrief, stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    count = int(buf.count.item())
+    log(f"[bench] {name}: {plan.n_octaves} octaves, {nl} pyramid launches, "
+        f"workspace {plan.workspace_bytes / 2**20:.1f} MiB, {count} keypoints")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nl + 1)] for _ in range(steps)]
+    t_s = torch.cuda.Event(enable_timing=True)
+    t_e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_s.record(stream)
+    for k in range(steps):
+        step(evs[k])
+    t_e.record(stream)
+    t_e.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = t_s.elapsed_time(t_e) / steps
+    launch_ms = [float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)])) for i in range(nl)]
+    log(f"[bench] {name}: {steps} steps {ms_step:.4f} ms/step (events), wall {wall * 1e3 / steps:.4f} ms/step")
+    for i, (st, ms) in enumerate(zip(steps_info, launch_ms)):
+        gbs = st["bytes"] / (ms * 1e-3) / 1e9 if st["bytes"] else 0.0
+        log(f"[bench]   launch {i} {KIND_NAMES[st['kind']]} octaves {st['octaves']} levels {st['levels']} "
+            f"r<={st['max_r']} pb={st['pb']}: {ms * 1e3:.2f} us, {gbs:.0f} GB/s algorithmic")
+    roofline = launch_roofline(steps_info, launch_ms, name)
+    st_pyr = time_calls(lambda: plan.build_pyramid(dvol, buf.ws, stream), stage_reps, stream)
+    st_det = time_calls(lambda: plan.detect(buf.ws, buf.kp, buf.count, stream), stage_reps, stream)
+    st_sr = time_calls(lambda: plan.describe(buf.ws, buf.kp, buf.count, siftrank=buf.siftrank, stream=stream),
+                       stage_reps, stream)
+    st_br = time_calls(lambda: plan.describe(buf.ws, buf.kp, buf.count, brief=buf.brief, rrief=buf.rrief,
+                                             stream=stream), stage_reps, stream)
+    log("[bench] %s stages ms: pyramid %.4f detect %.4f siftrank %.4f brief+rrief %.4f"
+        % (name, st_pyr, st_det, st_sr, st_br))
+    res = {
+        "volumes_per_s": round(1000.0 / ms_step, 2),
+        "ms_per_step": round(ms_step, 4),
+        "voxels_per_s": round(nx * ny * nz * 1000.0 / ms_step, 1),
+        "shape_xyz": [nx, ny, nz], "octaves": plan.n_octaves, "keypoints": count,
+        "pyramid_launches": nl,
+        "stages_ms": {"pyramid": round(st_pyr, 4), "detect": round(st_det, 4), "siftrank": round(st_sr, 4),
+                      "brief_rrief": round(st_br, 4)},
+        "roofline": roofline,
+    }
+    return res, (ctx, plan, buf, dvol, vol)
 
 
 def match_throughput(stream, n=16384, reps=5):
@@ -226,46 +296,6 @@ def match_throughput(stream, n=16384, reps=5):
         S.match(a, b, kind, stream)
         ms = time_calls(lambda: S.match(a, b, kind, stream), reps, stream)
         out[name] = {"ms": round(ms, 4), "g_pairs_per_s": round(n * n / (ms * 1e-3) / 1e9, 2)}
-    return out
-
-
-def large_volume_roofline(stream, reps):
-    """The same roofline on the 512x512x384 volume (config 4), whose levels
-    do not fit the last-level cache: the fused pass against HBM."""
-    import torch
-
-    import paper_2112_10258_amd as S
-    from gen import phantoms as P
-    vol = P.config4()
-    nz, ny, nx = vol.shape
-    ctx = S.Context(S.default_params(), P.pair_draws())
-    plan = S.Plan(ctx, (nx, ny, nz), 1 << 17)
-    buf = S.Buffers(plan)
-    dvol = torch.from_numpy(vol).cuda()
-    for _ in range(2):
-        S.run_extract(plan, dvol, buf, stream=stream)
-    torch.cuda.synchronize()
-    ms = time_calls(lambda: S.run_extract(plan, dvol, buf, stream=stream), 3, stream)
-    passes = plan.pyramid_passes()
-    pass_ms = [time_calls(lambda i=i: plan.pyramid_pass(i, dvol, buf.ws, stream), reps, stream)
-               if p[0] == 0 else 0.0 for i, p in enumerate(passes)]
-    out = octave0_roofline(plan, passes, pass_ms, "config4")
-    out["workload"] = "config4: 512x512x384 smoothed noise + 4000 blobs"
-    out["ms_per_extraction"] = round(ms, 4)
-    # uniform-filter approximation of the largest increment (sigma 3.09,
-    # three passes per axis) on the same volume, beside the Gaussian pass
-    # that computes that level (blur + DoG)
-    box_out, box_tmp = torch.empty_like(dvol), torch.empty_like(dvol)
-    h = S.box_half_width(3.09, 3)
-    S.box_blur(dvol, h, 3, box_out, box_tmp, stream)
-    box_ms = time_calls(lambda: S.box_blur(dvol, h, 3, box_out, box_tmp, stream), reps, stream)
-    g5 = [i for i, p in enumerate(passes) if p[0] == 0 and p[1] == 5]
-    out["box"] = {"sigma": 3.09, "passes": 3, "half_width": h, "ms": round(box_ms, 4),
-                  "algorithmic_gb_per_s": round(3 * 8 * dvol.numel() / (box_ms * 1e-3) / 1e9, 1),
-                  "gaussian_level_pass_ms": round(pass_ms[g5[0]], 4) if g5 else None}
-    del box_out, box_tmp
-    del buf, plan, dvol
-    torch.cuda.empty_cache()
     return out
 
 
@@ -450,40 +480,64 @@ def serve_vs_plain(n_req, rate, pool_per_class, n_streams, max_inflight, max_bat
     }
 
 
-def cpu_baseline(vol, kw, budget_s):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(vol4, budget_s):
+    """The FP64 oracle, as it stands, timed on this host: one full extraction
+    (pyramid, detection, SIFT-Rank, BRIEF, RRIEF) of the 512x512x384 volume on
+    all threads, and of the 145x174x145 phantom on one thread and on all."""
     import oracle as O
     from gen import phantoms as P
-    from tests.helpers import oracle_params
-    import paper_2112_10258_amd as S
-    p = oracle_params(S.default_params(**kw))
+    p = O.Params()
     draws = P.pair_draws()
+    threads = O.max_threads()
+    out = {"cpu_model": cpu_model(), "threads": threads}
+    t0 = time.perf_counter()
+    O.extract(vol4, p, draws)
+    t4 = time.perf_counter() - t0
+    out["config4_all_threads_s"] = round(t4, 2)
+    vol2 = P.config2()
     n, t0 = 0, time.perf_counter()
     while True:
-        O.extract(vol, p, draws)
+        O.extract(vol2, p, draws)
         n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or n >= 50:
+        if time.perf_counter() - t0 >= max(1.0, budget_s / 4) or n >= 20:
             break
-    return n, el, O.max_threads()
+    out["config2_all_threads_volumes_per_s"] = round(n / (time.perf_counter() - t0), 3)
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.extract(vol2, p, draws)
+        out["config2_one_thread_volumes_per_s"] = round(1.0 / (time.perf_counter() - t0), 3)
+    finally:
+        O.set_threads(threads)
+    return t4, threads, out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="config4", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pass-reps", type=int, default=20)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
-    ap.add_argument("--no-large", action="store_true", help="skip the 512x512x384 roofline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the config-2, box-filter and matching extras")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB on the device a few times (reference dispatch for counter runs)")
-    ap.add_argument("--pmc-passes", type=int, default=0,
-                    help="counter runs: after the warm-up, launch each octave-0 level pass this many times and exit")
+    ap.add_argument("--pmc-steps", type=int, default=0,
+                    help="counter runs: after the warm-up, run this many plain steps and exit")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit (no GPU)")
     ap.add_argument("--pyramid-mode", type=int, default=None, choices=[0, 1, 2, 3],
@@ -497,9 +551,7 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     args = ap.parse_args()
     if args.summarize_pmc:
-        shapes = {"config2": (145, 174, 145), "config4": (512, 512, 384)}
-        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], {args.workload: shapes[args.workload]},
-                      PMC_SUMMARY, args.pmc_passes or 3)
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, PMC_SUMMARY)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); volumes are independent, "
@@ -509,7 +561,6 @@ def main():
     import torch
 
     import paper_2112_10258_amd as S
-    from gen import phantoms as P
 
     if args.copy_calibration:
         a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -523,72 +574,47 @@ def main():
     desc, kw = WORKLOADS[args.workload]
     extra = {} if args.pyramid_mode is None else {"pyramid_mode": args.pyramid_mode}
     kw = dict(kw, **extra)
-    log(f"[bench] workload {args.workload}: {desc}")
-    vol = make_volume(args.workload)
-    nz, ny, nx = vol.shape
-    cap = 1 << 17
-    ctx = S.Context(S.default_params(**kw), P.pair_draws())
-    plan = S.Plan(ctx, (nx, ny, nz), cap)
-    buf = S.Buffers(plan)
-    dvol = torch.from_numpy(vol).cuda()
     stream = torch.cuda.current_stream()
-
-    def step():
-        S.run_extract(plan, dvol, buf, stream=stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    if args.pmc_passes:
-        passes = plan.pyramid_passes()
-        for i, p in enumerate(passes):
-            if p[0] == 0 and p[1] > 0:
-                for _ in range(args.pmc_passes):
-                    plan.pyramid_pass(i, dvol, buf.ws, stream)
-        torch.cuda.synchronize()
-        log(f"[bench] octave-0 level passes launched {args.pmc_passes} times each for the counters")
+    log(f"[bench] workload {args.workload}: {desc}")
+    if args.pmc_steps:
+        _, (ctx, plan, buf, dvol, _) = measure_plain(args.workload, args.pmc_steps, args.warmup, kw, stream,
+                                                     stage_reps=1)
+        log(f"[bench] {args.pmc_steps} plain steps for the counters")
         return
-    count = int(buf.count.item())
-    log(f"[bench] {plan.n_octaves} octaves, workspace {plan.workspace_bytes / 2**20:.1f} MiB, {count} keypoints")
+    head, (ctx, plan, buf, dvol, vol) = measure_plain(args.workload, args.steps, args.warmup, kw, stream)
+    log(f"[bench] roofline: { {k: v for k, v in head['roofline'].items() if k != 'launches'} }")
 
-    # timed region: K whole steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ms_step = time_calls(step, args.steps, stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    value = 1000.0 / ms_step
-    log(f"[bench] {args.steps} steps: {ms_step:.4f} ms/step (events), wall {wall * 1e3 / args.steps:.4f} ms/step")
+    box = None
+    if not args.no_extra and args.workload == "config4":
+        # uniform-filter approximation of the largest increment (sigma 3.09,
+        # three passes per axis) on the same volume, beside the Gaussian launch
+        # that computes that level
+        box_out, box_tmp = torch.empty_like(dvol), torch.empty_like(dvol)
+        h = S.box_half_width(3.09, 3)
+        S.box_blur(dvol, h, 3, box_out, box_tmp, stream)
+        box_ms = time_calls(lambda: S.box_blur(dvol, h, 3, box_out, box_tmp, stream), 10, stream)
+        g5 = [lv["us"] for lv in head["roofline"]["launches"] if lv["levels"] == "G_5"]
+        box = {"sigma": 3.09, "passes": 3, "half_width": h, "ms": round(box_ms, 4),
+               "algorithmic_gb_per_s": round(3 * 8 * dvol.numel() / (box_ms * 1e-3) / 1e9, 1),
+               "gaussian_level_launch_ms": round(g5[0] / 1e3, 4) if g5 else None}
+        log(f"[bench] box blur: {box}")
+        del box_out, box_tmp
+    del ctx, plan, buf, dvol
+    torch.cuda.empty_cache()
 
-    # stage and pass breakdown (separate, after the timed region)
-    reps = args.pass_reps
-    st_pyr = time_calls(lambda: plan.build_pyramid(dvol, buf.ws, stream), reps, stream)
-    st_det = time_calls(lambda: plan.detect(buf.ws, buf.kp, buf.count, stream), reps, stream)
-    st_sr = time_calls(lambda: plan.describe(buf.ws, buf.kp, buf.count, siftrank=buf.siftrank, stream=stream),
-                       reps, stream)
-    st_br = time_calls(lambda: plan.describe(buf.ws, buf.kp, buf.count, brief=buf.brief, rrief=buf.rrief,
-                                             stream=stream), reps, stream)
-    passes = plan.pyramid_passes()
-    pass_ms = []
-    for i in range(len(passes)):
-        pass_ms.append(time_calls(lambda i=i: plan.pyramid_pass(i, dvol, buf.ws, stream), reps, stream))
-    log("[bench] stages ms: pyramid %.4f detect %.4f siftrank %.4f brief+rrief %.4f"
-        % (st_pyr, st_det, st_sr, st_br))
-    for (o, lev, r, sub, b, fused, vv), t in zip(passes, pass_ms):
-        log(f"[bench]   pass o={o} G{lev} r={r} sub={sub}: {t * 1e3:.2f} us, {b / t / 1e6:.0f} GB/s algorithmic")
-
-    roofline = octave0_roofline(plan, passes, pass_ms, args.workload)
-    large = box = None
-    if not args.no_large and args.workload != "config4":
-        del buf
+    extras = {}
+    if not args.no_extra and args.workload != "config2":
+        c2, keep = measure_plain("config2", 50, 5, dict(WORKLOADS["config2"][1], **extra), stream)
+        c2["roofline"].pop("launches", None)
+        c2["note"] = "levels of 14.6 MB sit in the 256 MB last-level cache: algorithmic GB/s, not HBM"
+        extras["config2"] = c2
+        del keep
         torch.cuda.empty_cache()
-        large = large_volume_roofline(stream, max(3, reps // 4))
-        box = large.pop("box")
-        log(f"[bench] roofline 512x512x384: {large}")
-        log(f"[bench] box blur 512x512x384: {box}")
 
-    match = match_throughput(stream)
-    log(f"[bench] match: {match}")
+    match = None
+    if not args.no_extra:
+        match = match_throughput(stream)
+        log(f"[bench] match: {match}")
 
     batch = None
     if not args.no_batch:
@@ -604,34 +630,37 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        n, el, cores = cpu_baseline(vol, kw, args.cpu_seconds)
-        cpu = {"value": round(n / el, 4), "unit": "volumes/s", "cores": cores, "kind": "oracle",
-               "sample": f"{n} full extraction(s) of the {args.workload} volume (pyramid, detection, "
-                         f"SIFT-Rank, BRIEF, RRIEF) in FP64, {el:.1f} s"}
-        log(f"[bench] oracle: {n} volumes in {el:.2f} s on {cores} threads")
+        if args.workload == "config4":
+            t4, cores, info = cpu_baseline(vol, args.cpu_seconds)
+            cpu = {"value": round(1.0 / t4, 4), "unit": "volumes/s", "cores": cores, "kind": "oracle",
+                   "sample": f"one full FP64 extraction (pyramid, detection, SIFT-Rank, BRIEF, RRIEF) of the "
+                             f"512x512x384 volume on {cores} threads, {t4:.1f} s; config 2 on 1 thread and on all",
+                   **info}
+        log(f"[bench] oracle: {cpu}")
 
-    vox = nx * ny * nz
+    nz, ny, nx = vol.shape
     out = {
-        "metric": "volumes/s (plain path, one volume per call)",
-        "value": round(value, 2),
+        "metric": "volumes/s & achieved HBM GB/s, batched vs plain at oracle match; p50/p99 latency",
+        "value": head["volumes_per_s"],
         "unit": "volumes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (pyramid, detection); f64 accumulation (descriptors)",
+        "dtype": "f32",
+        "dtype_note": "pyramid, DoG and detection in f32; descriptor sums in f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "shape_xyz": [nx, ny, nz], "octaves": plan.n_octaves,
-                   "keypoints": count, "descriptors": ["siftrank64", "brief256", "rrief256"],
+        "config": {"workload": args.workload, "what": desc, "shape_xyz": [nx, ny, nz],
+                   "octaves": head["octaves"], "keypoints": head["keypoints"],
+                   "descriptors": ["siftrank64", "brief256", "rrief256"], "path": "plain, one volume per call",
                    "parallelism": "single GPU"},
-        "voxels_per_s": round(vox * value, 1),
-        "stages_ms": {"pyramid": round(st_pyr, 4), "detect": round(st_det, 4), "siftrank": round(st_sr, 4),
-                      "brief_rrief": round(st_br, 4)},
-        "roofline": roofline,
-        "roofline_large_volume": large,
+        "voxels_per_s": head["voxels_per_s"],
+        "stages_ms": head["stages_ms"],
+        "roofline": head["roofline"],
+        "extra_workloads": extras or None,
         "batch": batch,
         "serve": serve,
         "match": match,

@@ -217,6 +217,28 @@ int sift3d_pyramid_pass(const sift3d_plan *plan, int pass, const float *d_vol, v
                         void *stream);
 
 /*
+ * The launches of sift3d_build_pyramid, exposed so that a caller can time
+ * each one on its stream (the same kernels, grids and order; running steps
+ * 0 .. count-1 in order is sift3d_build_pyramid). A launch may hold the
+ * passes of several levels, octaves and volumes that are ready together.
+ *   info[0] = kind: 0 = fused streaming pass, 1 = xy half and 2 = z half of
+ *             the two-launch pass, 3 = compact pass;
+ *   info[1] = level passes in it; info[2] = stand-alone BRIEF pre-blurs in it;
+ *   info[3] = largest tap radius; info[4], info[5] = lowest and highest
+ *             octave; info[6], info[7] = lowest and highest level index i of
+ *             the G_i it writes (-1 if none); info[8] = 1 if its level
+ *             passes also write the BRIEF pre-blurred levels of their source.
+ *   *bytes = algorithmic HBM bytes of the levels the launch completes (0
+ *             for an xy half): 4 per voxel read and per voxel written (G,
+ *             D, sub-sampled G_0 of the next octave, pre-blurred level).
+ * SIFT3D_E_ARG for a bad step index or a null plan or output.
+ */
+int sift3d_pyramid_step_count(const sift3d_plan *plan, int *n_steps);
+int sift3d_pyramid_step_info(const sift3d_plan *plan, int step, int info[9], size_t *bytes);
+int sift3d_pyramid_step(const sift3d_plan *plan, int step, const float *d_vol, void *d_ws, size_t ws_bytes,
+                        void *stream);
+
+/*
  * 4D extremum detection (Section 3.2.2, 4D Peak Detection): for every
  * octave, scale s = 1..S and interior voxel v (1 <= x <= nx-2, same for y,
  * z) keep v if |D_s(v)| > dog_threshold and the sum over its 80 neighbours

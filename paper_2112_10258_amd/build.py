@@ -1,6 +1,10 @@
 """Build libsift3d.so (gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2112_10258_amd.build [--jobs N]
+Usage: python -m paper_2112_10258_amd.build [--jobs N] [--incremental]
+
+--incremental recompiles only the sources whose object is older than the
+source or any header in csrc/ or include/ (a developer shortcut; the default
+compiles everything).
 """
 from __future__ import annotations
 
@@ -36,10 +40,23 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 8, verbose: bool = True) -> str:
+def _stale(src: str) -> bool:
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    deps += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(jobs: int = 8, verbose: bool = True, incremental: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    todo = [s for s in SOURCES if _stale(s)] if incremental else list(SOURCES)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -54,6 +71,7 @@ def build(jobs: int = 8, verbose: bool = True) -> str:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=8)
+    ap.add_argument("--incremental", action="store_true")
     args = ap.parse_args()
-    build(args.jobs)
+    build(args.jobs, incremental=args.incremental)
     sys.exit(0)

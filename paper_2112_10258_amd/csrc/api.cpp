@@ -762,9 +762,11 @@ int make_plan(sift3d_ctx *ctx, int n, const int *dims, int kp_capacity, sift3d_p
     pl->block_off_off = off;
     off += align256((size_t)nblk * sizeof(int));
     for (DUnit &u : pl->units) {
-        u.masks = (long long)off;
+        u.masks = (long long)(off - pl->row_count_off);
         off += align256((size_t)u.rows * u.words * sizeof(unsigned long long));
     }
+    pl->det_scratch_off = pl->row_count_off;
+    pl->det_scratch_bytes = off - pl->row_count_off;
     pl->ws_bytes = off;
 
     // level passes
@@ -866,6 +868,11 @@ int run_step(const sift3d_plan *plan, const Step &stp, const float *d_in, void *
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }
 
+}  // namespace
+
+namespace {
+int run_detect(const sift3d_plan *plan, char *ws, char *scr, sift3d_keypoint *d_kp, int kp_capacity, int *d_count,
+               hipStream_t stream);
 }  // namespace
 
 namespace s3d {
@@ -1103,14 +1110,87 @@ int sift3d_pyramid_pass(const sift3d_plan *plan, int pass, const float *d_vol, v
     return run_step(plan, Step{2, {t}, plan->solo_z[t], 1, z_blocks(g), L.r, false, 0}, d_vol, d_ws, st);
 }
 
+int sift3d_pyramid_step_count(const sift3d_plan *plan, int *n_steps)
+{
+    if (plan == nullptr || n_steps == nullptr) return SIFT3D_E_ARG;
+    *n_steps = (int)plan->sched.size();
+    return SIFT3D_OK;
+}
+
+int sift3d_pyramid_step_info(const sift3d_plan *plan, int step, int info[9], size_t *bytes)
+{
+    if (plan == nullptr || step < 0 || step >= (int)plan->sched.size()) return SIFT3D_E_ARG;
+    const Step &stp = plan->sched[step];
+    int n_level = 0, n_pre = 0, omin = 1 << 30, omax = -1, lmin = 1 << 30, lmax = -1, rmax = 0;
+    size_t b = 0;
+    for (int t : stp.tasks) {
+        const Task &k = plan->tasks[t];
+        const bool completes = stp.type != 1;   // an xy launch completes no level
+        if (k.kind == 0) {
+            const BlurLaunch &L = plan->blur[k.pass];
+            const VolPlan &vp = plan->vols[L.vol];
+            const size_t n = vp.oct[L.octave].n;
+            ++n_level;
+            omin = std::min(omin, L.octave);
+            omax = std::max(omax, L.octave);
+            lmin = std::min(lmin, L.dst_idx);
+            lmax = std::max(lmax, L.dst_idx);
+            rmax = std::max(rmax, L.r);
+            if (completes) {
+                b += 8 * n + (L.dog ? 4 * n : 0);
+                if (L.sub_octave >= 0) b += 4 * vp.oct[L.sub_octave].n;
+                if (stp.type == 0 && stp.pb) b += 4 * n;   // the BRIEF pre-blurred level written alongside
+            }
+        } else {
+            ++n_pre;
+            omin = std::min(omin, k.octave);
+            omax = std::max(omax, k.octave);
+            rmax = std::max(rmax, plan->brief_rb);
+            if (completes) b += 8 * plan->vols[k.vol].oct[k.octave].n;
+        }
+    }
+    if (info != nullptr) {
+        info[0] = stp.type;
+        info[1] = n_level;
+        info[2] = n_pre;
+        info[3] = rmax;
+        info[4] = omax >= 0 ? omin : -1;
+        info[5] = omax;
+        info[6] = lmax >= 0 ? lmin : -1;
+        info[7] = lmax;
+        info[8] = stp.type == 0 && stp.pb ? 1 : 0;
+    }
+    if (bytes != nullptr) *bytes = b;
+    return SIFT3D_OK;
+}
+
+int sift3d_pyramid_step(const sift3d_plan *plan, int step, const float *d_vol, void *d_ws, size_t ws_bytes,
+                        void *stream)
+{
+    int rc = check_ws(plan, d_ws, ws_bytes);
+    if (rc != SIFT3D_OK) return rc;
+    if (d_vol == nullptr || step < 0 || step >= (int)plan->sched.size()) return SIFT3D_E_ARG;
+    return run_step(plan, plan->sched[step], d_vol, d_ws, static_cast<hipStream_t>(stream));
+}
+
 int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_keypoint *d_kp, int kp_capacity,
                   int *d_count, void *stream)
 {
     int rc = check_ws(plan, d_ws, ws_bytes);
     if (rc != SIFT3D_OK) return rc;
     if (d_count == nullptr || kp_capacity < 0 || (kp_capacity > 0 && d_kp == nullptr)) return SIFT3D_E_ARG;
-    const sift3d_params &p = plan->ctx->p;
     char *ws = static_cast<char *>(d_ws);
+    return run_detect(plan, ws, ws + plan->det_scratch_off, d_kp, kp_capacity, d_count, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+int run_detect(const sift3d_plan *plan, char *ws, char *scr, sift3d_keypoint *d_kp, int kp_capacity, int *d_count,
+               hipStream_t stream)
+{
+    const sift3d_params &p = plan->ctx->p;
     DetLaunch a{};
     a.units = plan->d_units;
     a.vols = plan->d_vols;
@@ -1122,17 +1202,22 @@ int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_k
     a.thr = p.dog_threshold;
     a.votes = p.votes;
     a.ws = ws;
-    a.row_count = reinterpret_cast<int *>(ws + plan->row_count_off);
-    a.block_sum = reinterpret_cast<int *>(ws + plan->block_sum_off);
-    a.block_off = reinterpret_cast<int *>(ws + plan->block_off_off);
+    a.scr = scr;
+    a.row_count = reinterpret_cast<int *>(scr + (plan->row_count_off - plan->det_scratch_off));
+    a.block_sum = reinterpret_cast<int *>(scr + (plan->block_sum_off - plan->det_scratch_off));
+    a.block_off = reinterpret_cast<int *>(scr + (plan->block_off_off - plan->det_scratch_off));
     a.counts = d_count;
     a.kp = d_kp;
     a.cap = kp_capacity;
     if (a.n_units <= kInlineUnits)
         for (int u = 0; u < a.n_units; ++u) a.inl[u] = plan->units[u];
-    const hipError_t e = launch_detect(a, static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_detect(a, stream);
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }
+
+}  // namespace
+
+extern "C" {
 
 int sift3d_describe(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes, const sift3d_keypoint *d_kp,
                     const int *d_count, int kp_capacity, uint8_t *d_siftrank, uint64_t *d_brief, uint8_t *d_rrief,

@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(256) detect_tile_kernel(const DetLaunch a)
     const int u = last_le(a.n_units, [&](int i) { return (long long)unit_at<INL>(a, i).tile_block0; }, blockIdx.x);
     const DUnit &un = unit_at<INL>(a, u);
     const float *D = unit_D(a, un);
-    unsigned long long *masks = reinterpret_cast<unsigned long long *>(a.ws + un.masks);
+    unsigned long long *masks = reinterpret_cast<unsigned long long *>(a.scr + un.masks);
     const int local = blockIdx.x - un.tile_block0;
     const int txi = local % un.tiles_x;
     const int rest = local / un.tiles_x;
@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(kRowBlock) row_count_kernel(const DetLaunch a)
         if (rp.valid) {
             const DUnit &un = unit_at<INL>(a, rp.u);
             const unsigned long long *w =
-                reinterpret_cast<const unsigned long long *>(a.ws + un.masks) + (g - un.row_base) * un.words;
+                reinterpret_cast<const unsigned long long *>(a.scr + un.masks) + (g - un.row_base) * un.words;
             for (int q = 0; q < un.words; ++q) c += __popcll(w[q]);
         }
         a.row_count[g] = c;
@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(kRowBlock) emit_rows_kernel(const DetLaunch a)
     const long long r = g - un.row_base;
     const long long nxy = (long long)un.nx * un.ny;
     const float *Ds = unit_D(a, un) + un.lstride * rp.s;
-    const unsigned long long *mw = reinterpret_cast<const unsigned long long *>(a.ws + un.masks) + r * un.words;
+    const unsigned long long *mw = reinterpret_cast<const unsigned long long *>(a.scr + un.masks) + r * un.words;
     for (int q = 0; q < un.words && idx < a.cap; ++q) {
         unsigned long long w = mw[q];
         while (w != 0ull && idx < a.cap) {

@@ -112,7 +112,7 @@ struct DZJob {
 struct DUnit {
     long long g0;         // workspace byte offset of G_0 (levels G, D, B follow at lstride)
     long long b1;         // workspace byte offset of the BRIEF level of s = 1 (B_s at (s-1) lstride)
-    long long masks;      // workspace byte offset of the keypoint bit masks [rows][words]
+    long long masks;      // byte offset of the keypoint bit masks [rows][words] in the detection scratch
     long long row_base;   // first global detection row of the unit
     long long rows;       // S * (nz-2) * (ny-2)
     long long lstride;    // floats between consecutive levels
@@ -217,7 +217,8 @@ struct DetLaunch {
     int rows_per_block;
     float thr;
     int votes;
-    char *ws;
+    char *ws;                 // pyramid workspace (the D levels are read from it)
+    char *scr;                // detection scratch: row counts, block sums and offsets, masks
     int *row_count;           // [total_rows]
     int *block_sum;           // [n_blocks]
     int *block_off;           // [n_blocks]
@@ -315,7 +316,8 @@ struct sift3d_plan {
     int n_vol, cap, S;
     std::vector<s3d::VolPlan> vols;
     size_t in_elems;                    // floats of the packed input
-    size_t row_count_off, block_sum_off, block_off_off;
+    size_t row_count_off, block_sum_off, block_off_off;   // workspace byte offsets
+    size_t det_scratch_off, det_scratch_bytes;            // detection scratch area of the workspace
     size_t ws_bytes;
     long long total_rows;
     int tile_blocks;

@@ -131,6 +131,9 @@ def _load():
         "sift3d_pyramid_pass_count": (i, [_vp, P(i)]),
         "sift3d_pyramid_pass_info": (i, [_vp, i, P(i), P(sz)]),
         "sift3d_pyramid_pass": (i, [_vp, i, _vp, _vp, sz, _vp]),
+        "sift3d_pyramid_step_count": (i, [_vp, P(i)]),
+        "sift3d_pyramid_step_info": (i, [_vp, i, P(i), P(sz)]),
+        "sift3d_pyramid_step": (i, [_vp, i, _vp, _vp, sz, _vp]),
         "sift3d_ctx_params": (i, [_vp, P(Params)]),
         "sift3d_server_create": (i, [_vp, P(ServerConfig), P(_vp)]),
         "sift3d_server_footprint": (i, [_vp, i, i, i, P(sz)]),
@@ -378,6 +381,27 @@ class Plan:
     def pyramid_pass(self, i, vol, ws, stream=None):
         _check(_load().sift3d_pyramid_pass(self.handle, i, _vp(_ptr(vol)), _vp(ws.data_ptr()), ws.numel(),
                                            _vp(_stream(stream))), "sift3d_pyramid_pass")
+
+    def pyramid_steps(self):
+        """Launches of build_pyramid, in order: dicts with kind (0 fused, 1 xy, 2 z,
+        3 compact), level passes, pre-blurs, max radius, octave and level ranges,
+        pb flag and the algorithmic bytes of the levels it completes."""
+        lib = _load()
+        n = ctypes.c_int()
+        _check(lib.sift3d_pyramid_step_count(self.handle, ctypes.byref(n)), "sift3d_pyramid_step_count")
+        out = []
+        for i in range(n.value):
+            info = (ctypes.c_int * 9)()
+            b = ctypes.c_size_t()
+            _check(lib.sift3d_pyramid_step_info(self.handle, i, info, ctypes.byref(b)), "sift3d_pyramid_step_info")
+            out.append({"kind": info[0], "level_passes": info[1], "preblurs": info[2], "max_r": info[3],
+                        "octaves": (info[4], info[5]), "levels": (info[6], info[7]), "pb": info[8],
+                        "bytes": b.value})
+        return out
+
+    def pyramid_step(self, i, vol, ws, stream=None):
+        _check(_load().sift3d_pyramid_step(self.handle, i, _vp(_ptr(vol)), _vp(ws.data_ptr()), ws.numel(),
+                                           _vp(_stream(stream))), "sift3d_pyramid_step")
 
     def detect(self, ws, kp, count, stream=None):
         _check(_load().sift3d_detect(self.handle, _vp(ws.data_ptr()), ws.numel(), _vp(_ptr(kp)), self.capacity,

@@ -95,3 +95,52 @@ def unpack_bits(words: np.ndarray, n: int) -> np.ndarray:
     for i in range(n):
         out[..., i] = ((w[..., i // 64] >> np.uint64(i % 64)) & np.uint64(1)) == 1
     return out
+
+
+def stagewise_check(g, p, label, ref=None, draws=None, say=print):
+    """The binding stage-wise contract on one extraction `g` (gpu_extract
+    output or the same keys): every G and D level against the oracle's
+    pyramid `ref` (from the input; skipped if None), B_s against the oracle's
+    blur of the GPU's own G_s, detection of the oracle on the GPU's D levels
+    bit-identical, descriptors of the oracle on the GPU's G levels identical
+    up to the near-tie margins. Returns the oracle keypoints."""
+    from gen import phantoms as P
+    if draws is None:
+        draws = P.pair_draws()
+    if ref is not None:
+        assert g["n_octaves"] == len(ref), label
+        worst = 0.0
+        for o, oc in enumerate(ref):
+            for i, lev in enumerate(oc.G):
+                e = level_rel_err(g["G"][o][i], lev)
+                assert e <= LEVEL_RTOL, (label, "G", o, i, e)
+                worst = max(worst, e)
+            for i, lev in enumerate(oc.D):
+                e = level_rel_err(g["D"][o][i], lev)
+                assert e <= LEVEL_RTOL, (label, "D", o, i, e)
+                worst = max(worst, e)
+        say(f"{label}: levels within {LEVEL_RTOL} (worst {worst:.2e})")
+    if "B" in g:
+        for o, Gs in enumerate(g["G"]):
+            for s in range(1, p.scales + 1):
+                e = level_rel_err(g["B"][o][s - 1], O.blur(Gs[s].astype(np.float64), p.brief_blur, p.trunc))
+                assert e <= LEVEL_RTOL, (label, "B", o, s, e)
+    want = O.detect([[d.astype(np.float64) for d in Ds] for Ds in g["D"]], p)
+    got = g["keypoints"]
+    assert g["count"] == len(want), label
+    assert kp_keys(got) == kp_keys(want), label
+    assert np.array_equal(got["polarity"], want["polarity"]), label
+    assert np.array_equal(got["dog"], want["dog"].astype(np.float32)), label
+    d = O.describe([[x.astype(np.float64) for x in Gs] for Gs in g["G"]], got, draws, p)
+    for i in range(len(got)):
+        h = d["hist"][i]
+        assert rank_mismatch_excused(h, g["siftrank"][i], d["siftrank"][i], MARGIN * max(h.max(), 1e-300)), \
+            (label, "siftrank", i)
+        assert rank_mismatch_excused(d["diff"][i], g["rrief"][i], d["rrief"][i], MARGIN), (label, "rrief", i)
+    gb = unpack_bits(g["brief"], p.brief_n)
+    ob = unpack_bits(d["brief"], p.brief_n)
+    assert np.all(np.abs(d["diff"][gb != ob]) < MARGIN), (label, "brief")
+    sr_rows = int(np.sum(np.any(g["siftrank"] != d["siftrank"], axis=1)))
+    say(f"{label}: {len(got)} keypoints identical; descriptors within the margins "
+        f"(siftrank rows differing {sr_rows}, brief bits differing {int((gb != ob).sum())})")
+    return want

@@ -1,26 +1,30 @@
 """Parity at full workload sizes, in the launch configuration the benchmark
-times, on outputs the oracle can compute one by one.
+times.
 
-512x512x384 (fused streaming passes and xy + z launches on octaves 0 and 1,
-compact passes below):
-  - G_i at sampled voxels (volume corners, faces and random interior) equals
-    the oracle's blur of the GPU's own G_{i-1} (the input for G_0 of octave
-    0) evaluated at that voxel, within 1e-5 of the level's max;
-  - G_0 of octave o > 0 at sampled voxels equals the mean of the GPU's
-    2x2x2 block of G_S of octave o-1;
+512x512x384 (config 4: fused streaming passes on octave 0, whose levels hold
+100M voxels; every tile seam and slab join of the bench launches included):
+  - every voxel of every G level equals the oracle's blur of the GPU's own
+    previous level (the input for G_0 of octave 0), within 1e-5 of the
+    level's max; G_0 of octave o > 0 equals the oracle's 2x2x2 mean of the
+    GPU's G_S of octave o-1;
   - every D_i equals G_i - G_{i+1} rounded to float32, bit for bit;
+  - every pre-blurred level B_s equals the oracle's blur of the GPU's G_s;
   - the oracle's detection on the GPU's D levels gives the same keypoints;
-  - descriptors of a sample of keypoints match the oracle on the GPU's G
+  - the descriptors of every keypoint match the oracle's on the GPU's G
     levels under the near-tie margins.
-The 32-volume batch (each axis U{96..192}) gives every volume the plain
-path's results bit for bit.
+Config 3 (32 volumes, each axis U{96..192}, one batch plan): four of the
+volumes against the oracle (end-to-end levels, stage-wise detection and
+descriptors), and every volume equal to the plain path bit for bit.
+Config 5's two largest shapes (192x224x192 and 256^3) on the plain path
+against the oracle, stage-wise and end to end.
 """
 import numpy as np
 import pytest
 
 import oracle as O
 from gen import phantoms as P
-from tests.helpers import LEVEL_RTOL, MARGIN, kp_keys, oracle_params, rank_mismatch_excused, unpack_bits
+from tests.helpers import (LEVEL_RTOL, MARGIN, detection_margin, gpu_extract, kp_keys, level_rel_err,
+                           oracle_params, rank_mismatch_excused, stagewise_check, unpack_bits)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,31 +33,7 @@ def _say(msg):
     print(f"[fullsize] {msg}", flush=True)
 
 
-def _points(dims, n_random, rng):
-    nx, ny, nz = dims
-    pts = {(x, y, z) for x in (0, nx - 1) for y in (0, ny - 1) for z in (0, nz - 1)}
-    pts |= {(nx // 2, ny // 2, 0), (0, ny // 2, nz // 2), (nx // 2, 0, nz // 2), (nx - 1, ny // 3, nz - 2)}
-    for _ in range(n_random):
-        pts.add((int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))))
-    return sorted(pts)
-
-
-def _blur_at(src, sigma, trunc, pts):
-    """Oracle blur of src evaluated at each point, from its clamped (2r+1)^3
-    neighbourhood (the x, y and z passes of the centre voxel read nothing else)."""
-    r = int(np.ceil(trunc * sigma))
-    nz, ny, nx = src.shape
-    out = []
-    for x, y, z in pts:
-        zi = np.clip(np.arange(z - r, z + r + 1), 0, nz - 1)
-        yi = np.clip(np.arange(y - r, y + r + 1), 0, ny - 1)
-        xi = np.clip(np.arange(x - r, x + r + 1), 0, nx - 1)
-        blk = src[np.ix_(zi, yi, xi)].astype(np.float64)
-        out.append(O.blur(blk, sigma, trunc)[r, r, r])
-    return np.array(out)
-
-
-def test_config4_sampled_parity():
+def test_config4_whole_level_parity():
     import torch
 
     import paper_2112_10258_amd as S
@@ -65,8 +45,8 @@ def test_config4_sampled_parity():
     cap = 1 << 17
     plan = S.Plan(ctx, (nx, ny, nz), cap)
     buf = S.Buffers(plan)
-    passes = plan.pyramid_passes()
-    assert any(p[5] == 1 for p in passes if p[0] == 0), "octave 0 is expected on the fused pass"
+    steps = plan.pyramid_steps()
+    assert all(st["kind"] == 0 for st in steps if st["octaves"] == (0, 0)), "octave 0 runs on the fused pass"
     dvol = torch.from_numpy(vol).cuda()
     S.run_extract(plan, dvol, buf)
     torch.cuda.synchronize()
@@ -75,34 +55,27 @@ def test_config4_sampled_parity():
     assert 0 < res["count"] <= cap
     p = oracle_params(gp)
     sig0, incs = O.level_increments(p)
-    rng = np.random.default_rng(44)
     Sn = gp.scales
-    G_keep = []
-    D_all = []
+    G_keep, D_all = [], []
     for o in range(plan.n_octaves):
         dims = plan.octave_dims(o)
-        pts = _points(dims, 40, rng)
-        idx = tuple(np.array(pts).T[::-1])   # (z, y, x) index arrays
         G = [plan.level(buf.ws, o, 0, i).cpu().numpy() for i in range(Sn + 3)]
-        if o == 0:
-            ref = _blur_at(vol, sig0, p.trunc, pts)
-        else:
-            prev = G_keep[o - 1][Sn]
-            ref = np.array([prev[2 * z:2 * z + 2, 2 * y:2 * y + 2, 2 * x:2 * x + 2].astype(np.float64).mean()
-                            for x, y, z in pts])
-        err = np.abs(G[0][idx] - ref).max() / np.abs(G[0]).max()
-        assert err <= LEVEL_RTOL, (o, 0, err)
-        worst = err
+        ref = O.blur(vol, sig0, p.trunc) if o == 0 else O.subsample(G_keep[o - 1][Sn])
+        errs = [level_rel_err(G[0], ref)]
+        del ref
         for i in range(1, Sn + 3):
-            ref = _blur_at(G[i - 1], incs[i - 1], p.trunc, pts)
-            err = np.abs(G[i][idx].astype(np.float64) - ref).max() / np.abs(G[i]).max()
-            assert err <= LEVEL_RTOL, (o, i, err)
-            worst = max(worst, err)
+            errs.append(level_rel_err(G[i], O.blur(G[i - 1], incs[i - 1], p.trunc)))
+        assert max(errs) <= LEVEL_RTOL, (o, errs)
         D = [plan.level(buf.ws, o, 1, i).cpu().numpy() for i in range(Sn + 2)]
         for i in range(Sn + 2):
             assert np.array_equal(D[i], G[i] - G[i + 1]), (o, i)
-        _say(f"octave {o} dims {dims}: {len(pts)} points per level, worst rel err {worst:.2e}; D exact")
-        # keep what the descriptors (G_1..G_S) and the next octave's G_0 check (G_S) need
+        berrs = []
+        for s in range(1, Sn + 1):
+            B = plan.level(buf.ws, o, 2, s).cpu().numpy()
+            berrs.append(level_rel_err(B, O.blur(G[s], p.brief_blur, p.trunc)))
+        assert max(berrs) <= LEVEL_RTOL, (o, berrs)
+        _say(f"octave {o} dims {dims}: every voxel of G_0..G_{Sn + 2} within {max(errs):.2e}, "
+             f"B_1..B_{Sn} within {max(berrs):.2e}; D exact")
         G_keep.append([G[s] if 1 <= s <= Sn else None for s in range(Sn + 3)])
         D_all.append(D)
         del G
@@ -114,18 +87,76 @@ def test_config4_sampled_parity():
     assert np.array_equal(got["dog"], want["dog"].astype(np.float32))
     _say(f"detection on the GPU's D levels: {len(got)} keypoints identical")
     del D_all
-    sel = np.unique(np.linspace(0, len(got) - 1, min(len(got), 240)).astype(int))
-    ks = got[sel]
     G64 = [[None if g is None else g.astype(np.float64) for g in Gs] for Gs in G_keep]
-    d = O.describe(G64, ks, P.pair_draws(), p)
-    for j, i in enumerate(sel):
-        h = d["hist"][j]
-        assert rank_mismatch_excused(h, res["siftrank"][i], d["siftrank"][j], MARGIN * max(h.max(), 1e-300)), i
-        assert rank_mismatch_excused(d["diff"][j], res["rrief"][i], d["rrief"][j], MARGIN), i
-    gb = unpack_bits(res["brief"][sel], p.brief_n)
+    d = O.describe(G64, got, P.pair_draws(), p)
+    for i in range(len(got)):
+        h = d["hist"][i]
+        assert rank_mismatch_excused(h, res["siftrank"][i], d["siftrank"][i], MARGIN * max(h.max(), 1e-300)), i
+        assert rank_mismatch_excused(d["diff"][i], res["rrief"][i], d["rrief"][i], MARGIN), i
+    gb = unpack_bits(res["brief"], p.brief_n)
     ob = unpack_bits(d["brief"], p.brief_n)
     assert np.all(np.abs(d["diff"][gb != ob]) < MARGIN)
-    _say(f"descriptors of {len(sel)} sampled keypoints match; brief bits differing {int((gb != ob).sum())}")
+    sr_rows = int(np.sum(np.any(res["siftrank"] != d["siftrank"], axis=1)))
+    _say(f"descriptors of all {len(got)} keypoints match (siftrank rows differing {sr_rows}, "
+         f"brief bits differing {int((gb != ob).sum())})")
+
+
+def _batch_volume(plan, buf, v, draws):
+    """gpu_extract-style dict of volume v of a batch plan."""
+    import paper_2112_10258_amd as S
+    gp = plan.ctx.params
+    g = S.fetch_results(plan, buf, v)
+    no = plan.volumes[v]["n_octaves"]
+    g["n_octaves"] = no
+    g["params"] = gp
+    g["G"] = [[plan.level(buf.ws, o, 0, i, v).cpu().numpy() for i in range(gp.scales + 3)] for o in range(no)]
+    g["D"] = [[plan.level(buf.ws, o, 1, i, v).cpu().numpy() for i in range(gp.scales + 2)] for o in range(no)]
+    g["B"] = [[plan.level(buf.ws, o, 2, s, v).cpu().numpy() for s in range(1, gp.scales + 1)] for o in range(no)]
+    return g
+
+
+def test_config3_batch_volumes_match_oracle():
+    import torch
+
+    import paper_2112_10258_amd as S
+    vols = P.config3()
+    shapes = [(v.shape[2], v.shape[1], v.shape[0]) for v in vols]
+    pick = [0, 9, 20, 31]
+    _say(f"case=config3 batch of {len(vols)} volumes, oracle on volumes {pick}")
+    cap = 1 << 14
+    draws = P.pair_draws()
+    ctx = S.Context(S.default_params(), draws)
+    bplan = S.Plan(ctx, shapes, cap, batch=True)
+    bbuf = S.Buffers(bplan)
+    S.run_extract(bplan, bplan.pack_volumes(vols), bbuf)
+    torch.cuda.synchronize()
+    p = oracle_params(ctx.params)
+    for v in pick:
+        g = _batch_volume(bplan, bbuf, v, draws)
+        assert g["count"] <= cap
+        ref = O.pyramid(vols[v], p)
+        want = stagewise_check(g, p, f"config3 volume {v} {shapes[v]}", ref=ref, say=_say)
+        e2e = O.detect([oc.D for oc in ref], p)
+        a, b = set(kp_keys(want)), set(kp_keys(e2e))
+        for key in a ^ b:
+            o, s_, z, y, x = key
+            assert detection_margin(ref[o].D, s_, x, y, z, p.dog_threshold) < MARGIN, (v, key)
+
+
+@pytest.mark.parametrize("shape", [(192, 224, 192), (256, 256, 256)])
+def test_config5_large_shapes_match_oracle(shape):
+    vol = P.noise_blob_volume(shape, 5000 + shape[0])
+    _say(f"case=config5 shape_xyz={shape} plain path")
+    g = gpu_extract(vol, cap=1 << 15)
+    p = oracle_params(g["params"])
+    ref = O.pyramid(vol, p)
+    want = stagewise_check(g, p, f"config5 {shape}", ref=ref, say=_say)
+    e2e = O.detect([oc.D for oc in ref], p)
+    a, b = set(kp_keys(want)), set(kp_keys(e2e))
+    for key in a ^ b:
+        o, s_, z, y, x = key
+        assert detection_margin(ref[o].D, s_, x, y, z, p.dog_threshold) < MARGIN, key
+    _say(f"config5 {shape}: end-to-end keypoints {len(b)}, differing {len(a ^ b)} (all within the margin)")
 
 
 def test_config3_batch_equals_plain_at_full_size():

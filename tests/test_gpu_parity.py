@@ -141,11 +141,37 @@ def test_end_to_end_keypoints(name):
     kref = want[[kp_keys(want).index(c) for c in common]]
     kgpu_idx = [kp_keys(g["keypoints"]).index(c) for c in common]
     d = O.describe([oc.G for oc in ref], kref, P.pair_draws(), p)
-    sr_rows = int(np.sum(np.any(g["siftrank"][kgpu_idx] != d["siftrank"], axis=1)))
+    # BRIEF/RRIEF: the GPU's d_i comes from its pre-blurred levels B, the
+    # oracle's from blur(G_ref). B is a positive average (weights sum to 1), so
+    # |B_gpu - B_ref| <= beta + delta with delta = max|G_gpu - G_ref| on that
+    # level and beta = max|B_gpu - blur(G_gpu)|; hence |d_gpu - d_ref| <= 2
+    # (beta + delta): a bit may flip only where |d_ref| is below that, and a
+    # rank may move only past differences within twice that.
+    bound = {}
+    for o in range(len(ref)):
+        for s_ in range(1, p.scales + 1):
+            delta = float(np.abs(g["G"][o][s_].astype(np.float64) - ref[o].G[s_]).max())
+            beta = float(np.abs(g["B"][o][s_ - 1] - O.blur(g["G"][o][s_].astype(np.float64), p.brief_blur,
+                                                            p.trunc)).max())
+            bound[(o, s_)] = 2.0 * (beta + delta) * (1 + 1e-6) + 1e-12
     gb = unpack_bits(g["brief"][kgpu_idx], p.brief_n)
     ob = unpack_bits(d["brief"], p.brief_n)
+    flips = 0
+    for j, c in enumerate(common):
+        b_ = bound[(c[0], c[1])]
+        fl = gb[j] != ob[j]
+        assert np.all(np.abs(d["diff"][j][fl]) <= b_), (name, c)
+        flips += int(fl.sum())
+        assert rank_mismatch_excused(d["diff"][j], g["rrief"][kgpu_idx[j]], d["rrief"][j], 2 * b_), (name, c)
+    # SIFT-Rank: a sample whose gradient component is within the level error
+    # of zero moves its whole magnitude to the neighbouring octant bin, so no
+    # margin bounds the histograms end to end; the share of rows that differ
+    # at all is bounded instead (5%).
+    sr_rows = int(np.sum(np.any(g["siftrank"][kgpu_idx] != d["siftrank"], axis=1)))
     print(f"[parity] {name} end-to-end: gpu {len(a)} oracle {len(b)} common {len(common)}; "
-          f"siftrank rows differing {sr_rows}/{len(common)}; brief bits differing {int((gb != ob).sum())}")
+          f"siftrank rows differing {sr_rows}/{len(common)}; brief bits differing {flips} "
+          f"(all within 2(beta+delta) <= {max(bound.values()):.2e})")
+    assert sr_rows <= 0.05 * len(common), (name, sr_rows, len(common))
 
 
 def test_determinism_bitwise():
