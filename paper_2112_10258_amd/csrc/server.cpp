@@ -2,24 +2,28 @@
 // one GPU.
 //
 // Requests arrive one at a time (sift3d_server_submit). A scheduler thread
-// admits them in arrival order. When the request at the head of the queue
-// is admitted, up to max_batch - 1 later requests of the same shape that are
-// already waiting join it (the group size is rounded down to a power of
-// two); the group runs as one batch extraction, so each pyramid, detection
-// and descriptor launch covers all of its volumes. A group is admitted as
-// soon as two resources allow it:
-//   - an in-flight slot (at most max_inflight groups on the device), and
-//   - device memory: the group needs a batch slot of its (shape, size), i.e.
-//     the packed input, the workspace of the batch plan and the keypoint and
-//     descriptor buffers of its requests. Batch slots are cached per (shape,
-//     size); a new one is allocated while the total stays within hbm_budget,
-//     after evicting idle slots of other kinds if needed, and a group that
-//     does not fit is shrunk before it waits.
-// Groups are spread over n_streams streams, so the kernels of different
-// groups run side by side. Completion is detected by polling an event per
-// group; the keypoint counts travel back with it in pinned host memory. A
-// batch slot stays with its group (the results live there) until the client
-// has released every ticket of the group.
+// admits them in arrival order under the policy of server_policy.h: the
+// head of the queue runs together with up to max_batch - 1 later requests of
+// its shape (a power-of-two group), as one batch extraction, so each
+// pyramid, detection and descriptor launch covers every volume of the group.
+// A group runs on a slot: one device allocation holding the packed input,
+// the batch plan's workspace and the keypoint and descriptor buffers of its
+// requests, cached per (shape, group size) and kept by the group until the
+// client has released every ticket of it. At most max_inflight groups are on
+// the device, spread over n_streams streams so their kernels overlap.
+//
+// The scheduler holds the server mutex only while it applies releases,
+// decides admissions and publishes results. Frees, allocations, launches
+// and completion polls run outside it, so clients' submit, result and
+// release calls never wait behind device work. Plans are created by
+// submit (the first request of a shape plans every group size) under a
+// mutex of their own.
+//
+// Each slot captures its batch extraction into a HIP graph when it is
+// created (one graph per size class and slot); a group then launches the
+// input copies, one graph and the copy of the counts. If capture is not
+// possible, the slot launches the extraction directly: the kernels are the
+// same either way.
 //
 // A batch plan gives each volume exactly the results of a one-volume plan
 // (same kernels, same arithmetic), so a request's result does not depend on
@@ -27,11 +31,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <array>
 #include <chrono>
 #include <condition_variable>
 #include <cstdint>
-#include <deque>
 #include <map>
 #include <mutex>
 #include <new>
@@ -40,12 +42,13 @@
 #include <utility>
 #include <vector>
 
+#include "server_policy.h"
 #include "sift3d.h"
 
 namespace {
 
-using Shape = std::array<int, 3>;
-using Kind = std::pair<Shape, int>;   // (shape, volumes per batch)
+using s3d::serve::Kind;
+using s3d::serve::Shape;
 
 double now_s()
 {
@@ -58,9 +61,10 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // A device allocation for one group of n requests of one shape.
 struct Slot {
     Kind kind;
+    size_t bytes;
+    double last_use;
     sift3d_plan *plan;      // the (shape, n) batch plan, owned by the server's plan cache
     char *mem;              // one device allocation
-    size_t bytes;
     float *in;              // packed input: volume i at in_off[i]
     std::vector<size_t> in_off;
     size_t vol_bytes;
@@ -72,15 +76,14 @@ struct Slot {
     uint64_t *br;           // [n][cap][brief_n/64]
     uint8_t *rr;            // [n][cap][brief_n]
     int *h_count;           // pinned host copy of count
+    hipGraphExec_t graph;   // the captured batch extraction (nullptr: launch directly)
     int holders;            // requests of the group not yet released
-    double last_use;
 };
 
 struct Request {
     int64_t id;
     const float *vol;
     Shape shape;
-    size_t footprint;       // bytes of a lone slot of its shape
     int state;              // 0 pending, 1 on the device, 2 done, 3 failed
     int rc;
     int hip_error;
@@ -91,15 +94,25 @@ struct Request {
     double t_submit, t_start, t_done;
 };
 
-// A group on the device.
+enum { kPending = 0, kRunning = 1, kDone = 2, kFailed = 3 };
+
+// A group on the device (scheduler-only).
 struct Group {
     Slot *slot;
     std::vector<Request *> reqs;
     int stream;
     hipEvent_t ev;
+    double t_start;
 };
 
-enum { kPending = 0, kRunning = 1, kDone = 2, kFailed = 3 };
+// A group decided under the lock, started outside it.
+struct Start {
+    s3d::serve::Admission<Slot> adm;
+    std::vector<Request *> reqs;
+    Group g{};
+    int rc = SIFT3D_OK;
+    int hip_error = 0;
+};
 
 }  // namespace
 
@@ -109,26 +122,28 @@ struct sift3d_server {
     int device;
     int brief_n;
     std::vector<hipStream_t> streams;
-    std::vector<int> stream_load;
+    std::vector<int> stream_load;       // scheduler-only
+
+    // plans and slot sizes per kind (plan_mu); never held together with mu
+    std::mutex plan_mu;
+    std::map<Kind, sift3d_plan *> plans;
 
     // shared with client threads (guarded by mu)
     std::mutex mu;
     std::condition_variable cv_work;   // scheduler: new request, release or stop
     std::condition_variable cv_done;   // clients: a request finished
-    std::deque<Request *> pending;
     std::unordered_map<int64_t, Request *> reqs;
     std::vector<Slot *> to_release;    // slots whose group is fully released
-    std::map<Kind, sift3d_plan *> plans;
+    std::map<Kind, size_t> kind_bytes; // slot bytes per kind (0: cannot be planned)
+    s3d::serve::Policy<Slot> *policy = nullptr;
     int64_t next_id = 1;
+    int64_t work_gen = 0;              // bumped by every submission, release and stop
     bool stop = false;
     sift3d_server_counters stats{};
 
     // scheduler-only state
     std::vector<Group> running;
-    std::map<Kind, std::vector<Slot *>> idle;
     std::vector<hipEvent_t> free_events;
-    size_t allocated = 0;
-    size_t idle_bytes = 0;             // part of `allocated` in idle (evictable) slots
 
     std::thread thread;
 };
@@ -141,24 +156,6 @@ size_t outputs_bytes(int cap, int brief_n)
            align256((size_t)cap * (brief_n / 8)) + align256((size_t)cap * brief_n);
 }
 
-// The (shape, n) batch plan, created on first use. Caller holds mu.
-int get_plan(sift3d_server *sv, const Kind &k, sift3d_plan **out)
-{
-    auto it = sv->plans.find(k);
-    if (it != sv->plans.end()) {
-        *out = it->second;
-        return SIFT3D_OK;
-    }
-    std::vector<int> dims;
-    for (int i = 0; i < k.second; ++i) dims.insert(dims.end(), k.first.begin(), k.first.end());
-    sift3d_plan *p = nullptr;
-    const int rc = sift3d_plan_create_batch(sv->ctx, k.second, dims.data(), sv->cfg.kp_capacity, &p);
-    if (rc != SIFT3D_OK) return rc;
-    sv->plans[k] = p;
-    *out = p;
-    return SIFT3D_OK;
-}
-
 // Device bytes of a slot for `plan` (n volumes).
 size_t slot_bytes(const sift3d_server *sv, const sift3d_plan *plan, int n)
 {
@@ -168,15 +165,67 @@ size_t slot_bytes(const sift3d_server *sv, const sift3d_plan *plan, int n)
            (size_t)n * outputs_bytes(sv->cfg.kp_capacity, sv->brief_n);
 }
 
-void free_slot(sift3d_server *sv, Slot *s)
+// Plans of every group size (powers of two up to max_batch) of a shape, and
+// their slot sizes; returns the rc of the lone plan. Takes plan_mu only.
+int ensure_plans(sift3d_server *sv, const Shape &shape, std::vector<std::pair<Kind, size_t>> &sizes)
 {
+    std::lock_guard<std::mutex> lk(sv->plan_mu);
+    int rc_lone = SIFT3D_OK;
+    for (int n = 1; n <= sv->cfg.max_batch; n *= 2) {
+        const Kind k{shape, n};
+        auto it = sv->plans.find(k);
+        sift3d_plan *p = it == sv->plans.end() ? nullptr : it->second;
+        if (p == nullptr) {
+            std::vector<int> dims;
+            for (int i = 0; i < n; ++i) dims.insert(dims.end(), shape.begin(), shape.end());
+            const int rc = sift3d_plan_create_batch(sv->ctx, n, dims.data(), sv->cfg.kp_capacity, &p);
+            if (rc != SIFT3D_OK) {
+                p = nullptr;
+                if (n == 1) rc_lone = rc;
+            } else {
+                sv->plans[k] = p;
+            }
+        }
+        sizes.emplace_back(k, p ? slot_bytes(sv, p, n) : 0);
+        if (n == 1 && p == nullptr) break;
+    }
+    return rc_lone;
+}
+
+sift3d_plan *find_plan(sift3d_server *sv, const Kind &k)
+{
+    std::lock_guard<std::mutex> lk(sv->plan_mu);
+    auto it = sv->plans.find(k);
+    return it == sv->plans.end() ? nullptr : it->second;
+}
+
+void free_slot(Slot *s)
+{
+    if (s->graph != nullptr) (void)hipGraphExecDestroy(s->graph);
     (void)hipFree(s->mem);
     (void)hipHostFree(s->h_count);
-    sv->allocated -= s->bytes;
     delete s;
 }
 
-Slot *new_slot(sift3d_server *sv, const Kind &k, sift3d_plan *plan, size_t bytes)
+// Capture the slot's batch extraction into a graph on stream st (which must
+// not be capturing already). Leaves s->graph null if capture fails.
+void capture_slot(sift3d_server *sv, Slot *s, hipStream_t st)
+{
+    s->graph = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return;
+    const int rc = sift3d_extract(s->plan, s->in, s->ws, s->ws_bytes, s->kp, sv->cfg.kp_capacity, s->count, s->sr,
+                                  s->br, s->rr, st);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc == SIFT3D_OK && e == hipSuccess && g != nullptr) {
+        hipGraphExec_t x = nullptr;
+        if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess) s->graph = x;
+    }
+    if (g != nullptr) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+}
+
+Slot *new_slot(sift3d_server *sv, const Kind &k, sift3d_plan *plan, size_t bytes, hipStream_t st)
 {
     const int n = k.second;
     Slot *s = new (std::nothrow) Slot();
@@ -184,6 +233,7 @@ Slot *new_slot(sift3d_server *sv, const Kind &k, sift3d_plan *plan, size_t bytes
     s->kind = k;
     s->plan = plan;
     s->bytes = bytes;
+    s->graph = nullptr;
     if (hipMalloc((void **)&s->mem, bytes) != hipSuccess) {
         delete s;
         return nullptr;
@@ -215,42 +265,8 @@ Slot *new_slot(sift3d_server *sv, const Kind &k, sift3d_plan *plan, size_t bytes
     s->br = nb > 0 ? reinterpret_cast<uint64_t *>(p) : nullptr;
     p += align256((size_t)n * cap * (nb / 8));
     s->rr = nb > 0 ? reinterpret_cast<uint8_t *>(p) : nullptr;
-    sv->allocated += bytes;
-    ++sv->stats.slot_allocations;
-    if (sv->allocated > sv->stats.peak_allocated) sv->stats.peak_allocated = sv->allocated;
+    capture_slot(sv, s, st);
     return s;
-}
-
-// A slot of kind k: an idle one, a new one within the budget, or a new one
-// after evicting idle slots of other kinds (least recently used first).
-// nullptr: not now (wait for a release), or the plan could not be made.
-Slot *acquire_slot(sift3d_server *sv, const Kind &k)
-{
-    auto it = sv->idle.find(k);
-    if (it != sv->idle.end() && !it->second.empty()) {
-        Slot *s = it->second.back();
-        it->second.pop_back();
-        sv->idle_bytes -= s->bytes;
-        return s;
-    }
-    sift3d_plan *plan = nullptr;
-    if (get_plan(sv, k, &plan) != SIFT3D_OK) return nullptr;
-    const size_t need = slot_bytes(sv, plan, k.second);
-    const size_t budget = sv->cfg.hbm_budget;
-    if (need > budget) return nullptr;
-    while (sv->allocated + need > budget) {
-        Slot *oldest = nullptr;
-        std::vector<Slot *> *from = nullptr;
-        for (auto &kv : sv->idle)
-            for (Slot *s : kv.second)
-                if (oldest == nullptr || s->last_use < oldest->last_use) oldest = s, from = &kv.second;
-        if (oldest == nullptr) return nullptr;
-        from->erase(std::find(from->begin(), from->end(), oldest));
-        sv->idle_bytes -= oldest->bytes;
-        free_slot(sv, oldest);
-        ++sv->stats.slot_evictions;
-    }
-    return new_slot(sv, k, plan, need);
 }
 
 int pick_stream(const sift3d_server *sv)
@@ -261,28 +277,36 @@ int pick_stream(const sift3d_server *sv)
     return best;
 }
 
-// Launch a group on its slot: copy the volumes into the packed input, run
-// the batch extraction, bring the counts back. false: launch failed (the
-// requests are marked failed, the slot goes back to the pool).
-bool start_group(sift3d_server *sv, Group &g)
+// Outside the lock: free the evicted slots, get the group's slot and launch
+// the input copies, the extraction and the copy of the counts, then an
+// event. On failure the slot is kept out of the pool until its stream has
+// drained (st.rc != OK; the slot is returned in st.g.slot, or null).
+void start_group(sift3d_server *sv, Start &st)
 {
-    Slot *s = g.slot;
+    for (Slot *s : st.adm.evict) free_slot(s);
+    Group &g = st.g;
     g.stream = pick_stream(sv);
-    hipStream_t st = sv->streams[g.stream];
-    const double t = now_s();
-    for (size_t i = 0; i < g.reqs.size(); ++i) {
-        Request *r = g.reqs[i];
-        r->slot = s;
-        r->index = (int)i;
-        r->stream = g.stream;
-        r->t_start = t;
+    hipStream_t hs = sv->streams[g.stream];
+    Slot *s = st.adm.reuse;
+    if (s == nullptr) {
+        sift3d_plan *plan = find_plan(sv, st.adm.kind);
+        s = plan ? new_slot(sv, st.adm.kind, plan, st.adm.new_bytes, hs) : nullptr;
+        if (s == nullptr) {
+            st.rc = SIFT3D_E_HIP;
+            st.hip_error = (int)hipErrorOutOfMemory;
+            g.slot = nullptr;
+            return;
+        }
     }
+    g.slot = s;
+    g.reqs = st.reqs;
+    g.t_start = now_s();
     if (sv->free_events.empty()) {
         hipEvent_t ev;
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) sv->free_events.push_back(ev);
     }
-    int rc = SIFT3D_OK;
     hipError_t e = hipSuccess;
+    int rc = SIFT3D_OK;
     if (sv->free_events.empty()) {
         rc = SIFT3D_E_HIP;
         e = hipErrorOutOfMemory;
@@ -291,70 +315,45 @@ bool start_group(sift3d_server *sv, Group &g)
         sv->free_events.pop_back();
     }
     for (size_t i = 0; rc == SIFT3D_OK && i < g.reqs.size(); ++i) {
-        e = hipMemcpyAsync(s->in + s->in_off[i], g.reqs[i]->vol, s->vol_bytes, hipMemcpyDeviceToDevice, st);
+        e = hipMemcpyAsync(s->in + s->in_off[i], g.reqs[i]->vol, s->vol_bytes, hipMemcpyDeviceToDevice, hs);
         if (e != hipSuccess) rc = SIFT3D_E_HIP;
     }
     if (rc == SIFT3D_OK) {
-        rc = sift3d_extract(s->plan, s->in, s->ws, s->ws_bytes, s->kp, sv->cfg.kp_capacity, s->count, s->sr, s->br,
-                            s->rr, st);
-        if (rc != SIFT3D_OK) e = (hipError_t)sift3d_last_hip_error();
+        if (s->graph != nullptr) {
+            e = hipGraphLaunch(s->graph, hs);
+            if (e != hipSuccess) rc = SIFT3D_E_HIP;
+        } else {
+            rc = sift3d_extract(s->plan, s->in, s->ws, s->ws_bytes, s->kp, sv->cfg.kp_capacity, s->count, s->sr,
+                                s->br, s->rr, hs);
+            if (rc != SIFT3D_OK) e = (hipError_t)sift3d_last_hip_error();
+        }
     }
     if (rc == SIFT3D_OK) {
-        e = hipMemcpyAsync(s->h_count, s->count, g.reqs.size() * sizeof(int), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipEventRecord(g.ev, st);
+        e = hipMemcpyAsync(s->h_count, s->count, g.reqs.size() * sizeof(int), hipMemcpyDeviceToHost, hs);
+        if (e == hipSuccess) e = hipEventRecord(g.ev, hs);
         if (e != hipSuccess) rc = SIFT3D_E_HIP;
     }
     if (rc != SIFT3D_OK) {
-        for (Request *r : g.reqs) {
-            r->rc = rc;
-            r->hip_error = (int)e;
-            r->state = kFailed;
-            r->slot = nullptr;
-            r->t_done = now_s();
-            ++sv->stats.failed;
-        }
+        // work already enqueued may still use the slot: drain the stream
+        // before the slot can go back to the pool
+        (void)hipStreamSynchronize(hs);
         if (g.ev != nullptr) sv->free_events.push_back(g.ev);
-        s->last_use = now_s();
-        sv->idle[s->kind].push_back(s);
-        sv->idle_bytes += s->bytes;
-        return false;
+        g.ev = nullptr;
+        st.rc = rc;
+        st.hip_error = (int)e;
+        return;
     }
-    for (Request *r : g.reqs) r->state = kRunning;
-    s->holders = (int)g.reqs.size();
     ++sv->stream_load[g.stream];
-    return true;
 }
 
-// The head request and up to max_batch - 1 later pending requests of its
-// shape, size rounded down to a power of two. A group that passes over
-// waiting requests of other shapes must leave room for a lone slot for each
-// of them next to the memory already held and its own slot: a client that
-// consumes results in submission order may keep the group's slot until it
-// has received those requests' results, so they must never wait for it.
-std::vector<Request *> form_group(sift3d_server *sv)
+void fail_request(sift3d_server *sv, Request *r, int rc, int hip_error)
 {
-    std::vector<Request *> grp;
-    const Shape shape = sv->pending.front()->shape;
-    for (Request *r : sv->pending) {
-        if (r->shape == shape) grp.push_back(r);
-        if ((int)grp.size() == sv->cfg.max_batch) break;
-    }
-    size_t n = 1;
-    while (n * 2 <= grp.size()) n *= 2;
-    const size_t held = sv->allocated - sv->idle_bytes;
-    for (; n > 1; n /= 2) {
-        // lone slots of the requests passed over, up to the group's last member
-        size_t skipped = 0;
-        for (Request *r : sv->pending) {
-            if (r == grp[n - 1]) break;
-            if (r->shape != shape) skipped += r->footprint;
-        }
-        sift3d_plan *plan = nullptr;
-        if (get_plan(sv, Kind{shape, (int)n}, &plan) != SIFT3D_OK) continue;
-        if (held + slot_bytes(sv, plan, (int)n) + skipped <= sv->cfg.hbm_budget) break;
-    }
-    grp.resize(n);
-    return grp;
+    r->rc = rc;
+    r->hip_error = hip_error;
+    r->state = kFailed;
+    r->slot = nullptr;
+    r->t_done = now_s();
+    ++sv->stats.failed;
 }
 
 void scheduler(sift3d_server *sv)
@@ -362,84 +361,107 @@ void scheduler(sift3d_server *sv)
     (void)hipSetDevice(sv->device);
     std::unique_lock<std::mutex> lk(sv->mu);
     for (;;) {
-        // slots of fully released groups go back to the pool
-        for (Slot *s : sv->to_release) {
-            s->last_use = now_s();
-            sv->idle[s->kind].push_back(s);
-            sv->idle_bytes += s->bytes;
-        }
+        const int64_t gen = sv->work_gen;
+        // under the lock: released slots back to the pool, then admissions
+        for (Slot *s : sv->to_release) sv->policy->add_idle(s, now_s());
         sv->to_release.clear();
+        std::vector<Start> starts;
+        while ((int)(sv->running.size() + starts.size()) < sv->cfg.max_inflight) {
+            Start st;
+            if (!sv->policy->admit(st.adm)) break;
+            for (int64_t id : st.adm.reqs) st.reqs.push_back(sv->reqs.at(id));
+            starts.push_back(std::move(st));
+        }
+        if (sv->stop) {
+            // requests not yet admitted are cancelled; those on the device finish
+            bool any = false;
+            for (const s3d::serve::Waiting &w : sv->policy->pending) {
+                fail_request(sv, sv->reqs.at(w.id), SIFT3D_E_ARG, 0);
+                any = true;
+            }
+            sv->policy->pending.clear();
+            if (any) sv->cv_done.notify_all();
+        }
+        const bool stopping = sv->stop;
+        lk.unlock();
 
-        // completions
-        bool finished = false;
+        // outside the lock: launches and completion polls
+        for (Start &st : starts) start_group(sv, st);
+        std::vector<std::pair<Group, hipError_t>> finished;
         for (size_t i = 0; i < sv->running.size();) {
-            Group &g = sv->running[i];
-            const hipError_t q = hipEventQuery(g.ev);
+            const hipError_t q = hipEventQuery(sv->running[i].ev);
             if (q == hipErrorNotReady) {
                 ++i;
                 continue;
             }
+            finished.emplace_back(sv->running[i], q);
+            sv->running[i] = sv->running.back();
+            sv->running.pop_back();
+        }
+        for (auto &f : finished) {
+            --sv->stream_load[f.first.stream];
+            sv->free_events.push_back(f.first.ev);
+        }
+
+        lk.lock();
+        // publish
+        bool notify = false;
+        for (Start &st : starts) {
+            if (st.rc != SIFT3D_OK) {
+                for (Request *r : st.reqs) fail_request(sv, r, st.rc, st.hip_error);
+                if (st.g.slot != nullptr)
+                    sv->policy->add_idle(st.g.slot, now_s());
+                else if (st.adm.reuse == nullptr)
+                    sv->policy->drop(st.adm.new_bytes);   // the reservation was not allocated
+                notify = true;
+            } else {
+                for (size_t i = 0; i < st.reqs.size(); ++i) {
+                    Request *r = st.reqs[i];
+                    r->slot = st.g.slot;
+                    r->index = (int)i;
+                    r->stream = st.g.stream;
+                    r->t_start = st.g.t_start;
+                    r->state = kRunning;
+                }
+                st.g.slot->holders = (int)st.reqs.size();
+                if (st.adm.reuse == nullptr) {
+                    ++sv->stats.slot_allocations;
+                    sv->stats.peak_allocated = std::max(sv->stats.peak_allocated, sv->policy->allocated());
+                }
+                sv->running.push_back(st.g);
+            }
+            sv->stats.slot_evictions += (int64_t)st.adm.evict.size();
+            ++sv->stats.groups;
+            sv->stats.grouped_requests += (int64_t)st.reqs.size();
+        }
+        for (auto &f : finished) {
             const double t = now_s();
-            for (size_t j = 0; j < g.reqs.size(); ++j) {
-                Request *r = g.reqs[j];
+            for (size_t j = 0; j < f.first.reqs.size(); ++j) {
+                Request *r = f.first.reqs[j];
                 r->t_done = t;
-                if (q == hipSuccess) {
-                    r->count = g.slot->h_count[j];
+                if (f.second == hipSuccess) {
+                    r->count = f.first.slot->h_count[j];
                     r->state = kDone;
                     ++sv->stats.completed;
                 } else {
                     r->rc = SIFT3D_E_HIP;
-                    r->hip_error = (int)q;
+                    r->hip_error = (int)f.second;
                     r->state = kFailed;
                     ++sv->stats.failed;
                 }
             }
-            --sv->stream_load[g.stream];
-            sv->free_events.push_back(g.ev);
-            sv->running[i] = sv->running.back();
-            sv->running.pop_back();
-            finished = true;
-        }
-
-        // admissions, in arrival order; a group that does not fit is shrunk
-        while (!sv->pending.empty() && (int)sv->running.size() < sv->cfg.max_inflight) {
-            std::vector<Request *> grp = form_group(sv);
-            Slot *s = nullptr;
-            while (!grp.empty()) {
-                s = acquire_slot(sv, Kind{grp[0]->shape, (int)grp.size()});
-                if (s != nullptr) break;
-                grp.resize(grp.size() / 2);
-            }
-            if (s == nullptr) break;  // memory frees up when a held slot is released
-            for (Request *r : grp) sv->pending.erase(std::find(sv->pending.begin(), sv->pending.end(), r));
-            Group g{s, grp, 0, nullptr};
-            if (start_group(sv, g))
-                sv->running.push_back(g);
-            else
-                finished = true;
-            ++sv->stats.groups;
-            sv->stats.grouped_requests += (int64_t)grp.size();
+            notify = true;
         }
         sv->stats.in_flight = 0;
         for (const Group &g : sv->running) sv->stats.in_flight += (int)g.reqs.size();
-        sv->stats.pending = (int)sv->pending.size();
-        sv->stats.allocated = sv->allocated;
-        if (finished) sv->cv_done.notify_all();
-
-        if (sv->stop) {
-            // requests not yet admitted are cancelled; those on the device finish
-            for (Request *r : sv->pending) {
-                r->rc = SIFT3D_E_ARG;
-                r->state = kFailed;
-                r->t_done = now_s();
-                ++sv->stats.failed;
-            }
-            if (!sv->pending.empty()) sv->cv_done.notify_all();
-            sv->pending.clear();
-            if (sv->running.empty()) break;
-        }
+        sv->stats.pending = (int)sv->policy->pending.size();
+        sv->stats.allocated = sv->policy->allocated();
+        if (notify) sv->cv_done.notify_all();
+        if (stopping && sv->running.empty()) break;
+        if (sv->work_gen != gen || !starts.empty() || !finished.empty()) continue;   // new work arrived meanwhile
         if (sv->running.empty()) {
-            sv->cv_work.wait(lk);
+            // idle until a submission, a release or stop: nothing pending can start before one
+            sv->cv_work.wait(lk, [&] { return sv->work_gen != gen; });
         } else {
             // poll the device; new submissions and releases wake us early
             sv->cv_work.wait_for(lk, std::chrono::microseconds(20));
@@ -480,6 +502,11 @@ int sift3d_server_create(sift3d_ctx *ctx, const sift3d_server_config *cfg, sift3
         sv->streams.push_back(st);
         sv->stream_load.push_back(0);
     }
+    // the policy reads slot sizes that submit recorded (under mu)
+    sv->policy = new s3d::serve::Policy<Slot>(cfg->hbm_budget, cfg->max_batch, [sv](const Kind &k) {
+        auto it = sv->kind_bytes.find(k);
+        return it == sv->kind_bytes.end() ? (size_t)0 : it->second;
+    });
     sv->stats.hbm_budget = cfg->hbm_budget;
     sv->thread = std::thread(scheduler, sv);
     *out = sv;
@@ -490,11 +517,14 @@ int sift3d_server_footprint(sift3d_server *sv, int nx, int ny, int nz, size_t *b
 {
     if (sv == nullptr || bytes == nullptr) return SIFT3D_E_ARG;
     if (nx < 1 || ny < 1 || nz < 1) return SIFT3D_E_ARG;
-    std::lock_guard<std::mutex> lk(sv->mu);
-    sift3d_plan *plan = nullptr;
-    const int rc = get_plan(sv, Kind{Shape{nx, ny, nz}, 1}, &plan);
+    std::vector<std::pair<Kind, size_t>> sizes;
+    const int rc = ensure_plans(sv, Shape{nx, ny, nz}, sizes);
     if (rc != SIFT3D_OK) return rc;
-    *bytes = slot_bytes(sv, plan, 1);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (auto &ks : sizes) sv->kind_bytes.insert(ks);
+    }
+    *bytes = sizes[0].second;
     return SIFT3D_OK;
 }
 
@@ -516,12 +546,12 @@ int sift3d_server_submit(sift3d_server *sv, const float *d_vol, int nx, int ny, 
         r->id = sv->next_id++;
         r->vol = d_vol;
         r->shape = Shape{nx, ny, nz};
-        r->footprint = fp;
         r->state = kPending;
         r->rc = SIFT3D_OK;
         r->t_submit = now_s();
         sv->reqs[r->id] = r;
-        sv->pending.push_back(r);
+        sv->policy->pending.push_back(s3d::serve::Waiting{r->id, r->shape, fp});
+        ++sv->work_gen;
         ++sv->stats.submitted;
         *ticket = r->id;
     }
@@ -565,18 +595,24 @@ int sift3d_server_fetch(sift3d_server *sv, int64_t ticket, sift3d_keypoint *h_kp
     const int rc = sift3d_server_result(sv, ticket, 1, &res);
     if (rc != SIFT3D_OK) return rc;
     if (res.status != SIFT3D_OK) return res.status;
-    // the slot cannot be reused before the client releases this ticket
+    // the slot cannot be reused before the client releases this ticket; the
+    // copies go on the request's stream, and an event after them is the
+    // only thing waited for (not the groups enqueued behind them)
     hipStream_t st = sv->streams[res.stream];
     const size_t n = (size_t)std::min(res.count, res.capacity), bn = (size_t)sv->brief_n;
-    hipError_t e = hipSuccess;
-    if (h_kp && n) e = hipMemcpyAsync(h_kp, res.d_kp, n * sizeof(sift3d_keypoint), hipMemcpyDeviceToHost, st);
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess && h_kp && n)
+        e = hipMemcpyAsync(h_kp, res.d_kp, n * sizeof(sift3d_keypoint), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && h_siftrank && n)
         e = hipMemcpyAsync(h_siftrank, res.d_siftrank, n * 64, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && h_brief && n && bn)
         e = hipMemcpyAsync(h_brief, res.d_brief, n * bn / 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && h_rrief && n && bn)
         e = hipMemcpyAsync(h_rrief, res.d_rrief, n * bn, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipEventRecord(ev, st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev);
+    if (ev != nullptr) (void)hipEventDestroy(ev);
     return e == hipSuccess ? SIFT3D_OK : SIFT3D_E_HIP;
 }
 
@@ -590,6 +626,7 @@ int sift3d_server_release(sift3d_server *sv, int64_t ticket)
         Request *r = it->second;
         if (r->state != kDone && r->state != kFailed) return SIFT3D_E_ARG;
         if (r->slot != nullptr && --r->slot->holders == 0) sv->to_release.push_back(r->slot);
+        ++sv->work_gen;
         sv->reqs.erase(it);
         delete r;
     }
@@ -613,6 +650,7 @@ int sift3d_server_destroy(sift3d_server *sv)
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->stop = true;
+        ++sv->work_gen;
     }
     sv->cv_work.notify_one();
     sv->thread.join();
@@ -624,10 +662,11 @@ int sift3d_server_destroy(sift3d_server *sv)
         if (s != nullptr && std::find(held.begin(), held.end(), s) == held.end()) held.push_back(s);
         delete kv.second;
     }
-    for (Slot *s : held) free_slot(sv, s);
-    for (Slot *s : sv->to_release) free_slot(sv, s);
-    for (auto &kv : sv->idle)
-        for (Slot *s : kv.second) free_slot(sv, s);
+    for (Slot *s : held) free_slot(s);
+    for (Slot *s : sv->to_release) free_slot(s);
+    for (auto &kv : sv->policy->idle())
+        for (Slot *s : kv.second) free_slot(s);
+    delete sv->policy;
     for (hipEvent_t ev : sv->free_events) (void)hipEventDestroy(ev);
     for (hipStream_t st : sv->streams) (void)hipStreamDestroy(st);
     for (auto &kv : sv->plans) sift3d_plan_destroy(kv.second);
