@@ -358,8 +358,8 @@ int sift3d_server_result(sift3d_server *srv, int64_t ticket, int wait, sift3d_re
 
 /*
  * Copy the first min(count, capacity) rows of a finished request's results
- * to host memory (any pointer may be NULL to skip that output). Waits for
- * the copy on the request's stream only.
+ * to host memory (any pointer may be NULL to skip that output). The copies
+ * run on a stream of the server's own and the call waits for them only.
  */
 int sift3d_server_fetch(sift3d_server *srv, int64_t ticket, sift3d_keypoint *h_kp, uint8_t *h_siftrank,
                         uint64_t *h_brief, uint8_t *h_rrief);

@@ -19,11 +19,12 @@
 // submit (the first request of a shape plans every group size) under a
 // mutex of their own.
 //
-// Each slot captures its batch extraction into a HIP graph when it is
-// created (one graph per size class and slot); a group then launches the
-// input copies, one graph and the copy of the counts. If capture is not
-// possible, the slot launches the extraction directly: the kernels are the
-// same either way.
+// Groups launch their extraction directly on their stream. (With a HIP
+// graph captured per slot by the scheduler thread while client threads used
+// the device, later work on the process's legacy stream failed with a
+// capture-in-progress error; a captured config-2 extraction also replays no
+// faster than its launches. Slots hold no graph.)
+// Clients' result copies run on a stream of their own.
 //
 // A batch plan gives each volume exactly the results of a one-volume plan
 // (same kernels, same arithmetic), so a request's result does not depend on
@@ -76,7 +77,6 @@ struct Slot {
     uint64_t *br;           // [n][cap][brief_n/64]
     uint8_t *rr;            // [n][cap][brief_n]
     int *h_count;           // pinned host copy of count
-    hipGraphExec_t graph;   // the captured batch extraction (nullptr: launch directly)
     int holders;            // requests of the group not yet released
 };
 
@@ -123,6 +123,7 @@ struct sift3d_server {
     int brief_n;
     std::vector<hipStream_t> streams;
     std::vector<int> stream_load;       // scheduler-only
+    hipStream_t fetch_stream = nullptr;     // result copies of sift3d_server_fetch (client threads)
 
     // plans and slot sizes per kind (plan_mu); never held together with mu
     std::mutex plan_mu;
@@ -201,31 +202,12 @@ sift3d_plan *find_plan(sift3d_server *sv, const Kind &k)
 
 void free_slot(Slot *s)
 {
-    if (s->graph != nullptr) (void)hipGraphExecDestroy(s->graph);
     (void)hipFree(s->mem);
     (void)hipHostFree(s->h_count);
     delete s;
 }
 
-// Capture the slot's batch extraction into a graph on stream st (which must
-// not be capturing already). Leaves s->graph null if capture fails.
-void capture_slot(sift3d_server *sv, Slot *s, hipStream_t st)
-{
-    s->graph = nullptr;
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return;
-    const int rc = sift3d_extract(s->plan, s->in, s->ws, s->ws_bytes, s->kp, sv->cfg.kp_capacity, s->count, s->sr,
-                                  s->br, s->rr, st);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(st, &g);
-    if (rc == SIFT3D_OK && e == hipSuccess && g != nullptr) {
-        hipGraphExec_t x = nullptr;
-        if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess) s->graph = x;
-    }
-    if (g != nullptr) (void)hipGraphDestroy(g);
-    (void)hipGetLastError();
-}
-
-Slot *new_slot(sift3d_server *sv, const Kind &k, sift3d_plan *plan, size_t bytes, hipStream_t st)
+Slot *new_slot(sift3d_server *sv, const Kind &k, sift3d_plan *plan, size_t bytes)
 {
     const int n = k.second;
     Slot *s = new (std::nothrow) Slot();
@@ -233,7 +215,6 @@ Slot *new_slot(sift3d_server *sv, const Kind &k, sift3d_plan *plan, size_t bytes
     s->kind = k;
     s->plan = plan;
     s->bytes = bytes;
-    s->graph = nullptr;
     if (hipMalloc((void **)&s->mem, bytes) != hipSuccess) {
         delete s;
         return nullptr;
@@ -265,7 +246,6 @@ Slot *new_slot(sift3d_server *sv, const Kind &k, sift3d_plan *plan, size_t bytes
     s->br = nb > 0 ? reinterpret_cast<uint64_t *>(p) : nullptr;
     p += align256((size_t)n * cap * (nb / 8));
     s->rr = nb > 0 ? reinterpret_cast<uint8_t *>(p) : nullptr;
-    capture_slot(sv, s, st);
     return s;
 }
 
@@ -290,7 +270,7 @@ void start_group(sift3d_server *sv, Start &st)
     Slot *s = st.adm.reuse;
     if (s == nullptr) {
         sift3d_plan *plan = find_plan(sv, st.adm.kind);
-        s = plan ? new_slot(sv, st.adm.kind, plan, st.adm.new_bytes, hs) : nullptr;
+        s = plan ? new_slot(sv, st.adm.kind, plan, st.adm.new_bytes) : nullptr;
         if (s == nullptr) {
             st.rc = SIFT3D_E_HIP;
             st.hip_error = (int)hipErrorOutOfMemory;
@@ -319,14 +299,9 @@ void start_group(sift3d_server *sv, Start &st)
         if (e != hipSuccess) rc = SIFT3D_E_HIP;
     }
     if (rc == SIFT3D_OK) {
-        if (s->graph != nullptr) {
-            e = hipGraphLaunch(s->graph, hs);
-            if (e != hipSuccess) rc = SIFT3D_E_HIP;
-        } else {
-            rc = sift3d_extract(s->plan, s->in, s->ws, s->ws_bytes, s->kp, sv->cfg.kp_capacity, s->count, s->sr,
-                                s->br, s->rr, hs);
-            if (rc != SIFT3D_OK) e = (hipError_t)sift3d_last_hip_error();
-        }
+        rc = sift3d_extract(s->plan, s->in, s->ws, s->ws_bytes, s->kp, sv->cfg.kp_capacity, s->count, s->sr, s->br,
+                            s->rr, hs);
+        if (rc != SIFT3D_OK) e = (hipError_t)sift3d_last_hip_error();
     }
     if (rc == SIFT3D_OK) {
         e = hipMemcpyAsync(s->h_count, s->count, g.reqs.size() * sizeof(int), hipMemcpyDeviceToHost, hs);
@@ -492,15 +467,19 @@ int sift3d_server_create(sift3d_ctx *ctx, const sift3d_server_config *cfg, sift3
         delete sv;
         return SIFT3D_E_HIP;
     }
-    for (int i = 0; i < cfg->n_streams; ++i) {
+    for (int i = 0; i < cfg->n_streams + 1; ++i) {
         hipStream_t st;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
             delete sv;
             return SIFT3D_E_HIP;
         }
-        sv->streams.push_back(st);
-        sv->stream_load.push_back(0);
+        if (i == cfg->n_streams) {
+            sv->fetch_stream = st;
+        } else {
+            sv->streams.push_back(st);
+            sv->stream_load.push_back(0);
+        }
     }
     // the policy reads slot sizes that submit recorded (under mu)
     sv->policy = new s3d::serve::Policy<Slot>(cfg->hbm_budget, cfg->max_batch, [sv](const Kind &k) {
@@ -595,10 +574,11 @@ int sift3d_server_fetch(sift3d_server *sv, int64_t ticket, sift3d_keypoint *h_kp
     const int rc = sift3d_server_result(sv, ticket, 1, &res);
     if (rc != SIFT3D_OK) return rc;
     if (res.status != SIFT3D_OK) return res.status;
+    // the request's group has completed (the scheduler saw its event) and
     // the slot cannot be reused before the client releases this ticket; the
-    // copies go on the request's stream, and an event after them is the
-    // only thing waited for (not the groups enqueued behind them)
-    hipStream_t st = sv->streams[res.stream];
+    // copies go on the server's fetch stream, and an event after them is
+    // the only thing waited for
+    hipStream_t st = sv->fetch_stream;
     const size_t n = (size_t)std::min(res.count, res.capacity), bn = (size_t)sv->brief_n;
     hipEvent_t ev = nullptr;
     hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -655,6 +635,7 @@ int sift3d_server_destroy(sift3d_server *sv)
     sv->cv_work.notify_one();
     sv->thread.join();
     for (hipStream_t st : sv->streams) (void)hipStreamSynchronize(st);
+    (void)hipStreamSynchronize(sv->fetch_stream);
     // slots still held by unreleased requests, then the pool
     std::vector<Slot *> held;
     for (auto &kv : sv->reqs) {
@@ -669,6 +650,7 @@ int sift3d_server_destroy(sift3d_server *sv)
     delete sv->policy;
     for (hipEvent_t ev : sv->free_events) (void)hipEventDestroy(ev);
     for (hipStream_t st : sv->streams) (void)hipStreamDestroy(st);
+    (void)hipStreamDestroy(sv->fetch_stream);
     for (auto &kv : sv->plans) sift3d_plan_destroy(kv.second);
     delete sv;
     return SIFT3D_OK;

@@ -109,6 +109,12 @@ def _load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libsift3d.so not built ({LIB_PATH}); run python -m paper_2112_10258_amd.build")
+    # torch's HIP and HSA runtimes first: torch's libraries ask for them by
+    # unversioned file names, the library by soname (libamdhip64.so.7), so
+    # loading the library first would bring a second copy of each runtime
+    # into the process, and torch's copy then finds no GPU. Loaded the other
+    # way round, the library's soname lookup resolves to torch's copy.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     i, sz = ctypes.c_int, ctypes.c_size_t
     P = ctypes.POINTER
