@@ -40,6 +40,7 @@ enum {
     SIFT3D_E_WORKSPACE = -3,  /* workspace smaller than the plan needs      */
     SIFT3D_E_HIP = -5,        /* a HIP runtime call failed                  */
     SIFT3D_E_UNSUPPORTED = -6, /* parameter outside what the kernels support */
+    SIFT3D_E_SCRATCH = -7,    /* plan needs more than the static scratch    */
     SIFT3D_PENDING = 1         /* sift3d_server_result: not finished yet   */
 };
 
@@ -252,6 +253,33 @@ int sift3d_pyramid_step(const sift3d_plan *plan, int step, const float *d_vol, v
  */
 int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_keypoint *d_kp,
                   int kp_capacity, int *d_count, void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * detection as sift3d_detect, with the same outputs, but its scratch (row
+ * counts, block sums and offsets, keypoint bit masks) is a static device
+ * array of SIFT3D_DETECT_STATIC_SCRATCH bytes that the library holds on
+ * every GPU it runs on until the process ends, not the workspace's scratch
+ * area. The workspace only needs to hold the pyramid (its first bytes, up
+ * to where the plan's detection scratch would start); ws_bytes may be the
+ * full planned size. The call allocates nothing and issues no memset: the
+ * kernels write every scratch word they read. The array's address on each
+ * device is taken by sift3d_create with that device current, so a context
+ * must have been created on the current device before this call.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (two streams, two threads) race and give wrong results.
+ * SIFT3D_E_SCRATCH if the plan's detection scratch (it grows with the
+ * number of rows, about 12 bytes per 62 voxels of every octave and scale)
+ * exceeds SIFT3D_DETECT_STATIC_SCRATCH (a 512x512x384 volume needs about
+ * 50 MB); SIFT3D_E_ARG / SIFT3D_E_WORKSPACE as for sift3d_detect.
+ */
+#define SIFT3D_DETECT_STATIC_SCRATCH ((size_t)64 << 20)
+int sift3d_detect_static(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_keypoint *d_kp,
+                         int kp_capacity, int *d_count, void *stream);
+
+/* Bytes of detection scratch a plan needs (for sift3d_detect_static). */
+int sift3d_plan_detect_scratch(const sift3d_plan *plan, size_t *bytes);
 
 /*
  * Descriptors of keypoints 0 .. min(d_count[v], kp_capacity) - 1 of every

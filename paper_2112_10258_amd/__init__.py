@@ -5,6 +5,7 @@ Python side only marshals torch tensors and streams into the C ABI
 declared in include/sift3d.h.
 """
 from .sift3d import (  # noqa: F401
+    DETECT_STATIC_SCRATCH,
     KEYPOINT_BYTES,
     KEYPOINT_DTYPE,
     MATCH_BRIEF,

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -16,6 +17,34 @@ using namespace s3d;
 namespace {
 
 thread_local int g_last_hip = 0;
+
+// Detection scratch of the allocation-free entry point (sift3d_detect_static):
+// row counts, block sums and offsets and keypoint bit masks. Every GPU holds
+// its own copy of this array from module load until the process ends. In
+// host code its name is not a device address: the address on each device
+// comes from hipGetSymbolAddress, taken once per device (with that device
+// current) by sift3d_create, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[SIFT3D_DETECT_STATIC_SCRATCH];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (the current device).
+hipError_t static_scratch(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 int hip_fail(hipError_t e)
 {
@@ -918,6 +947,8 @@ int sift3d_create(const sift3d_params *p, const double *pair_draws, int n_draws,
     c->d_offsets = nullptr;
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
+    void *scr = nullptr;
+    if (e == hipSuccess) e = static_scratch(c->device, &scr);   // once per device: the static detection scratch
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e);
@@ -1183,6 +1214,29 @@ int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_k
     return run_detect(plan, ws, ws + plan->det_scratch_off, d_kp, kp_capacity, d_count, static_cast<hipStream_t>(stream));
 }
 
+int sift3d_plan_detect_scratch(const sift3d_plan *plan, size_t *bytes)
+{
+    if (plan == nullptr || bytes == nullptr) return SIFT3D_E_ARG;
+    *bytes = plan->det_scratch_bytes;
+    return SIFT3D_OK;
+}
+
+int sift3d_detect_static(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_keypoint *d_kp,
+                         int kp_capacity, int *d_count, void *stream)
+{
+    if (plan == nullptr || d_ws == nullptr || reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return SIFT3D_E_ARG;
+    if (d_count == nullptr || kp_capacity < 0 || (kp_capacity > 0 && d_kp == nullptr)) return SIFT3D_E_ARG;
+    if (plan->det_scratch_bytes > SIFT3D_DETECT_STATIC_SCRATCH) return SIFT3D_E_SCRATCH;
+    if (ws_bytes < plan->det_scratch_off) return SIFT3D_E_WORKSPACE;     // the pyramid part only
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    void *scr = nullptr;
+    if (e == hipSuccess) e = static_scratch(dev, &scr);
+    if (e != hipSuccess) return hip_fail(e);
+    return run_detect(plan, static_cast<char *>(d_ws), static_cast<char *>(scr), d_kp, kp_capacity, d_count,
+                      static_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"
 
 namespace {
@@ -1315,6 +1369,7 @@ const char *sift3d_error_string(int code)
     case SIFT3D_E_WORKSPACE: return "workspace too small";
     case SIFT3D_E_HIP: return "HIP runtime error";
     case SIFT3D_E_UNSUPPORTED: return "parameter outside the supported range";
+    case SIFT3D_E_SCRATCH: return "detection scratch larger than the static maximum";
     case SIFT3D_PENDING: return "request not finished";
     default: return "unknown error";
     }

@@ -23,7 +23,8 @@ KEYPOINT_DTYPE = np.dtype([
 KEYPOINT_BYTES = 40
 assert KEYPOINT_DTYPE.itemsize == KEYPOINT_BYTES
 
-OK, E_ARG, E_TOO_SMALL, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -5, -6
+OK, E_ARG, E_TOO_SMALL, E_WORKSPACE, E_HIP, E_UNSUPPORTED, E_SCRATCH = 0, -1, -2, -3, -5, -6, -7
+DETECT_STATIC_SCRATCH = 64 << 20     # SIFT3D_DETECT_STATIC_SCRATCH
 PENDING = 1
 
 
@@ -132,6 +133,8 @@ def _load():
         "sift3d_level": (i, [_vp, _vp, i, i, i, i, P(_vp)]),
         "sift3d_build_pyramid": (i, [_vp, _vp, _vp, sz, _vp]),
         "sift3d_detect": (i, [_vp, _vp, sz, _vp, i, _vp, _vp]),
+        "sift3d_detect_static": (i, [_vp, _vp, sz, _vp, i, _vp, _vp]),
+        "sift3d_plan_detect_scratch": (i, [_vp, P(sz)]),
         "sift3d_describe": (i, [_vp, _vp, sz, _vp, _vp, i, _vp, _vp, _vp, _vp]),
         "sift3d_extract": (i, [_vp, _vp, _vp, sz, _vp, i, _vp, _vp, _vp, _vp, _vp]),
         "sift3d_pyramid_pass_count": (i, [_vp, P(i)]),
@@ -412,6 +415,17 @@ class Plan:
     def detect(self, ws, kp, count, stream=None):
         _check(_load().sift3d_detect(self.handle, _vp(ws.data_ptr()), ws.numel(), _vp(_ptr(kp)), self.capacity,
                                      _vp(count.data_ptr()), _vp(_stream(stream))), "sift3d_detect")
+
+    def detect_static(self, ws, kp, count, stream=None):
+        """sift3d_detect with the library's static scratch (allocates nothing)."""
+        _check(_load().sift3d_detect_static(self.handle, _vp(ws.data_ptr()), ws.numel(), _vp(_ptr(kp)),
+                                            self.capacity, _vp(count.data_ptr()), _vp(_stream(stream))),
+               "sift3d_detect_static")
+
+    def detect_scratch_bytes(self):
+        b = ctypes.c_size_t()
+        _check(_load().sift3d_plan_detect_scratch(self.handle, ctypes.byref(b)), "sift3d_plan_detect_scratch")
+        return b.value
 
     def describe(self, ws, kp, count, siftrank=None, brief=None, rrief=None, stream=None):
         _check(_load().sift3d_describe(self.handle, _vp(ws.data_ptr()), ws.numel(), _vp(_ptr(kp)),
