@@ -17,7 +17,9 @@ order of the paper (Carluer et al., arXiv 2112.10258):
    peak/valley values +/-80 (Section 3.2.2, 4D Peak Detection).
 5. Descriptors: upright SIFT-Rank (Related Work: 2x2x2 spatial x 8
    orientation bins, ranked), BRIEF and RRIEF with any of the five point-pair
-   methods and a Gaussian patch pre-blur (Section 3.2.3).
+   methods and a Gaussian patch pre-blur (Section 3.2.3); dominant
+   orientations from a discrete spherical gradient histogram and SIFT-Rank
+   after reorientation (Related Work, 3D SIFT-Rank).
 6. Beside the path: nearest-neighbour matching of descriptors (Section 3.3)
    and the uniform-filter approximation of the Gaussian blur (Related Work).
 
@@ -86,6 +88,10 @@ def _L():
         lib.orc_brief_rrief.argtypes = [dp] + [ctypes.c_int] * 3 + [ip, ctypes.c_long, ip, ctypes.c_int,
                                                                     dp, ctypes.c_int, dp,
                                                                     ctypes.c_void_p, ctypes.c_void_p]
+        lib.orc_orient.argtypes = [dp] + [ctypes.c_int] * 3 + [ip, ctypes.c_long, ctypes.c_int, ctypes.c_double,
+                                                               ctypes.c_int, ip, dp, dp, ctypes.c_void_p, dp]
+        lib.orc_siftrank_frames.argtypes = [dp] + [ctypes.c_int] * 3 + [ip, ctypes.c_long, ctypes.c_int, dp, dp,
+                                                                        ctypes.c_void_p, dp]
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         lib.orc_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -217,6 +223,66 @@ def siftrank(G: np.ndarray, kp_xyz: np.ndarray, R: int):
     if K:
         _L().orc_siftrank(_dp(G), nx, ny, nz, _ip(kp), K, int(R), _dp(hist), rk.ctypes.data)
     return hist, rk
+
+
+ORIENT_TAU = 0.8      # peak threshold relative to the histogram maximum (reading R25)
+ORIENT_KMAX = 4       # frames kept per keypoint
+
+
+def orient(G: np.ndarray, kp_xyz: np.ndarray, R: int, tau: float = ORIENT_TAU, kmax: int = ORIENT_KMAX):
+    """Dominant orientations and oriented SIFT-Rank (Related Work, 3D
+    SIFT-Rank; reading R25, see orc_orient). Returns a dict: nframes [K],
+    frames [K, kmax, 3, 3] (columns e1, e2, e3), hist [K, kmax, 64],
+    rank [K, kmax, 64] uint8, margin [K]."""
+    G = _f64(G)
+    kp = np.ascontiguousarray(kp_xyz, dtype=np.int32).reshape(-1, 3)
+    K = len(kp)
+    nf = np.zeros(K, dtype=np.int32)
+    fr = np.zeros((K, kmax, 3, 3))
+    hist = np.zeros((K, kmax, 64))
+    rk = np.zeros((K, kmax, 64), dtype=np.uint8)
+    mg = np.zeros(K)
+    nz, ny, nx = G.shape
+    if K:
+        _L().orc_orient(_dp(G), nx, ny, nz, _ip(kp), K, int(R), float(tau), int(kmax), _ip(nf), _dp(fr),
+                        _dp(hist), rk.ctypes.data, _dp(mg))
+    return {"nframes": nf, "frames": fr, "hist": hist, "rank": rk, "margin": mg}
+
+
+def siftrank_frames(G: np.ndarray, kp_xyz: np.ndarray, R: int, frames: np.ndarray):
+    """SIFT-Rank of keypoints in given frames [K, 3, 3] (columns = axes):
+    (hist [K,64], rank [K,64] uint8, margin [K]); the identity frame gives
+    the upright descriptor."""
+    G = _f64(G)
+    kp = np.ascontiguousarray(kp_xyz, dtype=np.int32).reshape(-1, 3)
+    K = len(kp)
+    F = np.ascontiguousarray(frames, dtype=np.float64).reshape(K, 9)
+    hist = np.zeros((K, 64))
+    rk = np.zeros((K, 64), dtype=np.uint8)
+    mg = np.zeros(K)
+    nz, ny, nx = G.shape
+    if K:
+        _L().orc_siftrank_frames(_dp(G), nx, ny, nz, _ip(kp), K, int(R), _dp(F), _dp(hist), rk.ctypes.data, _dp(mg))
+    return hist, rk, mg
+
+
+def orientations(G_levels, kps: np.ndarray, p: "Params", tau: float = ORIENT_TAU, kmax: int = ORIENT_KMAX):
+    """orient() for every keypoint on G_s of its octave with the SIFT-Rank
+    window half-width of its scale."""
+    K = len(kps)
+    out = {"nframes": np.zeros(K, dtype=np.int32), "frames": np.zeros((K, kmax, 3, 3)),
+           "hist": np.zeros((K, kmax, 64)), "rank": np.zeros((K, kmax, 64), dtype=np.uint8),
+           "margin": np.zeros(K)}
+    for o, G in enumerate(G_levels):
+        for s in range(1, p.scales + 1):
+            sel = np.nonzero((kps["octave"] == o) & (kps["scale"] == s))[0]
+            if len(sel) == 0:
+                continue
+            xyz = np.stack([kps["x"][sel], kps["y"][sel], kps["z"][sel]], axis=1)
+            r = orient(G[s], xyz, siftrank_radius(p, s), tau, kmax)
+            for k in out:
+                out[k][sel] = r[k]
+    return out
 
 
 def brief_rrief(G: np.ndarray, kp_xyz: np.ndarray, offsets: np.ndarray, wb: np.ndarray):

@@ -300,3 +300,268 @@ void orc_brief_rrief(const double *G, int nx, int ny, int nz, const int *kp, lon
         free(r);
     }
 }
+
+/*
+ * Dominant orientations and oriented SIFT-Rank (Related Work, 3D SIFT-Rank:
+ * dominant peaks of a discrete spherical histogram of gradient directions
+ * give one or more 3x3 rotations per keypoint, and the descriptor is
+ * computed after reorientation). The paper does not spell the histogram
+ * out; the reading taken here:
+ *
+ *   samples   the SIFT-Rank window: offsets d in [-R, R]^3, gradient g by
+ *             central differences at q = clamp(v + d), magnitude |g|;
+ *   bins      the 26 directions n/|n|, n in {-1,0,1}^3 \ {0}, numbered in
+ *             the order (nz, ny, nx) = (-1,-1,-1), (-1,-1,0), ... skipping
+ *             0; a vector goes to the bin of largest n.g/|n| (lowest
+ *             number on ties); zero vectors go nowhere;
+ *   histogram H[b] = sum of |g| over the bin's samples, V[b] = sum of g;
+ *   peaks     b is a peak if H[b] > 0, H[b] >= tau * max H, and for every
+ *             neighbour b' (angle <= 60 degrees: 4 (n.n')^2 >= |n|^2 |n'|^2
+ *             with n.n' > 0) H[b] > H[b'], or H[b] == H[b'] and b < b';
+ *             peaks are taken in decreasing H (lower number first on ties);
+ *   axis 1    e1 = V[b] / |V[b]| of a primary peak;
+ *   axis 2    the same histogram of p = g - (g.e1) e1 (weights |p|, sums
+ *             of p), its peaks in the same order; e2 = the normalised part
+ *             of V2[b] orthogonal to e1 (skipped if zero);
+ *   axis 3    e3 = e1 x e2; the frame is the rotation with columns e1, e2,
+ *             e3; frames are listed primary by primary, secondaries in
+ *             order within each, at most kmax;
+ *   oriented  SIFT-Rank of each frame: every sample's offset and gradient
+ *             in frame coordinates, d' = R^T d and g' = R^T g, then the
+ *             upright rule: spatial bin per axis 0 if d'_k < 0, 1 if > 0,
+ *             half to each if 0; orientation bin [g'_1>0] + 2[g'_2>0] +
+ *             4[g'_3>0]; weight |g|; ranks with ties by index. With the
+ *             identity frame this is the upright descriptor exactly.
+ *
+ * Outputs per keypoint k: nframes[k]; frames[k][f][9] with R[3 i + j] =
+ * component i of axis j; hist/rank[k][f][64]; margin[k] = the smallest of
+ * the relative decision margins: bin choice (best - second best n.g/|n|)
+ * / |g|, peak tests |H[b] - tau max H| / max H and |H[b] - H[b']| / max H
+ * over neighbours, |H[b] - H[b']| / max H of peaks next to each other in
+ * the order, and, per frame, |d'_k| / R and |g'_k| / |g| of every nonzero
+ * sample. A GPU taking the same decisions in another rounding
+ * order can only differ where this margin is tiny.
+ */
+static void orc_dir(int b, int n[3])
+{
+    int q = b < 13 ? b : b + 1;              /* skip the zero vector (index 13 of 27) */
+    n[0] = q % 3 - 1;
+    n[1] = (q / 3) % 3 - 1;
+    n[2] = q / 9 - 1;
+}
+
+/* Bin of vector g (|g| > 0) and the relative margin of the choice. */
+static int orc_dirbin(const double g[3], double *margin)
+{
+    double best = -HUGE_VAL, second = -HUGE_VAL;
+    int arg = -1;
+    for (int b = 0; b < 26; ++b) {
+        int n[3];
+        orc_dir(b, n);
+        double nn = (double)(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        double c = (n[0] * g[0] + n[1] * g[1] + n[2] * g[2]) / sqrt(nn);
+        if (c > best) {
+            second = best;
+            best = c;
+            arg = b;
+        } else if (c > second) {
+            second = c;
+        }
+    }
+    double m = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    double r = (best - second) / m;
+    if (r < *margin) *margin = r;
+    return arg;
+}
+
+static int orc_neighbours(int a, int b)
+{
+    int na[3], nb[3];
+    orc_dir(a, na);
+    orc_dir(b, nb);
+    long d = na[0] * nb[0] + na[1] * nb[1] + na[2] * nb[2];
+    long qa = na[0] * na[0] + na[1] * na[1] + na[2] * na[2];
+    long qb = nb[0] * nb[0] + nb[1] * nb[1] + nb[2] * nb[2];
+    return a != b && d > 0 && 4 * d * d >= qa * qb;
+}
+
+/* Peaks of H in order; returns their count. */
+static int orc_peaks(const double H[26], double tau, int *out, double *margin)
+{
+    double hmax = 0.0;
+    for (int b = 0; b < 26; ++b)
+        if (H[b] > hmax) hmax = H[b];
+    if (!(hmax > 0.0)) return 0;
+    int np = 0;
+    for (int b = 0; b < 26; ++b) {
+        if (!(H[b] > 0.0)) continue;
+        double r = fabs(H[b] - tau * hmax) / hmax;
+        if (r < *margin) *margin = r;
+        if (H[b] < tau * hmax) continue;
+        int peak = 1;
+        for (int c = 0; c < 26; ++c) {
+            if (!orc_neighbours(b, c)) continue;
+            double rc = fabs(H[b] - H[c]) / hmax;
+            if (rc < *margin) *margin = rc;
+            if (!(H[b] > H[c] || (H[b] == H[c] && b < c))) peak = 0;
+        }
+        if (peak) out[np++] = b;
+    }
+    /* decreasing H, lower bin first on ties (insertion sort) */
+    for (int i = 1; i < np; ++i)
+        for (int j = i; j > 0; --j) {
+            int a = out[j - 1], c = out[j];
+            if (H[c] > H[a] || (H[c] == H[a] && c < a)) {
+                out[j - 1] = c;
+                out[j] = a;
+            }
+        }
+    for (int i = 1; i < np; ++i) {
+        double r = fabs(H[out[i - 1]] - H[out[i]]) / hmax;   /* the order of two peaks */
+        if (r < *margin) *margin = r;
+    }
+    return np;
+}
+
+static void orc_sample_grad(const double *G, int nx, int ny, int nz, long qx, long qy, long qz, double g[3])
+{
+    g[0] = 0.5 * (G[VIDX(clampl(qx + 1, 0, nx - 1), qy, qz, nx, ny)] - G[VIDX(clampl(qx - 1, 0, nx - 1), qy, qz, nx, ny)]);
+    g[1] = 0.5 * (G[VIDX(qx, clampl(qy + 1, 0, ny - 1), qz, nx, ny)] - G[VIDX(qx, clampl(qy - 1, 0, ny - 1), qz, nx, ny)]);
+    g[2] = 0.5 * (G[VIDX(qx, qy, clampl(qz + 1, 0, nz - 1), nx, ny)] - G[VIDX(qx, qy, clampl(qz - 1, 0, nz - 1), nx, ny)]);
+}
+
+/* SIFT-Rank histogram of keypoint v in frame F (R[3 i + j] = component i of
+ * axis j): offsets and gradients in frame coordinates, then the upright
+ * binning. Lowers *mg to the smallest |d'_k| / R and |g'_k| / |g|. */
+static void orc_frame_hist(const double *G, int nx, int ny, int nz, long vx, long vy, long vz, int R,
+                           const double *F, double h[64], double *mg)
+{
+    for (int e = 0; e < 64; ++e) h[e] = 0.0;
+    for (int dz = -R; dz <= R; ++dz)
+        for (int dy = -R; dy <= R; ++dy)
+            for (int dx = -R; dx <= R; ++dx) {
+                double g[3];
+                orc_sample_grad(G, nx, ny, nz, clampl(vx + dx, 0, nx - 1), clampl(vy + dy, 0, ny - 1),
+                                clampl(vz + dz, 0, nz - 1), g);
+                double m = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+                double d[3] = {(double)dx, (double)dy, (double)dz};
+                double dp[3], gp[3];
+                for (int j = 0; j < 3; ++j) {
+                    dp[j] = F[0 + j] * d[0] + F[3 + j] * d[1] + F[6 + j] * d[2];
+                    gp[j] = F[0 + j] * g[0] + F[3 + j] * g[1] + F[6 + j] * g[2];
+                    if (dp[j] != 0.0 && fabs(dp[j]) / R < *mg) *mg = fabs(dp[j]) / R;
+                    if (m > 0.0 && gp[j] != 0.0 && fabs(gp[j]) / m < *mg) *mg = fabs(gp[j]) / m;
+                }
+                int bo = (gp[0] > 0.0) + 2 * (gp[1] > 0.0) + 4 * (gp[2] > 0.0);
+                double w[3][2];
+                for (int j = 0; j < 3; ++j) {
+                    w[j][0] = dp[j] < 0.0 ? 1.0 : (dp[j] == 0.0 ? 0.5 : 0.0);
+                    w[j][1] = 1.0 - w[j][0];
+                }
+                for (int bz = 0; bz < 2; ++bz)
+                    for (int by = 0; by < 2; ++by)
+                        for (int bx = 0; bx < 2; ++bx) {
+                            double ws = w[0][bx] * w[1][by] * w[2][bz];
+                            if (ws == 0.0) continue;
+                            h[8 * (bx + 2 * by + 4 * bz) + bo] += m * ws;
+                        }
+            }
+}
+
+/* SIFT-Rank of keypoints in given frames (frames [K][9]); hist [K][64],
+ * rank [K][64], margin [K] as in orc_orient. */
+void orc_siftrank_frames(const double *G, int nx, int ny, int nz, const int *kp, long K, int R,
+                         const double *frames, double *hist, uint8_t *rank, double *margin)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long k = 0; k < K; ++k) {
+        double mg = HUGE_VAL;
+        orc_frame_hist(G, nx, ny, nz, kp[3 * k], kp[3 * k + 1], kp[3 * k + 2], R, frames + 9 * k, hist + 64 * k, &mg);
+        int r[64];
+        orc_rank(hist + 64 * k, 64, r);
+        for (int e = 0; e < 64; ++e) rank[64 * k + e] = (uint8_t)r[e];
+        margin[k] = mg;
+    }
+}
+
+void orc_orient(const double *G, int nx, int ny, int nz, const int *kp, long K, int R, double tau, int kmax,
+                int *nframes, double *frames, double *hist, uint8_t *rank, double *margin)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long k = 0; k < K; ++k) {
+        long vx = kp[3 * k + 0], vy = kp[3 * k + 1], vz = kp[3 * k + 2];
+        double mg = HUGE_VAL;
+        double H[26], V[26][3];
+        for (int b = 0; b < 26; ++b) H[b] = V[b][0] = V[b][1] = V[b][2] = 0.0;
+        /* primary histogram */
+        for (int dz = -R; dz <= R; ++dz)
+            for (int dy = -R; dy <= R; ++dy)
+                for (int dx = -R; dx <= R; ++dx) {
+                    double g[3];
+                    orc_sample_grad(G, nx, ny, nz, clampl(vx + dx, 0, nx - 1), clampl(vy + dy, 0, ny - 1),
+                                    clampl(vz + dz, 0, nz - 1), g);
+                    double m = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+                    if (!(m > 0.0)) continue;
+                    int b = orc_dirbin(g, &mg);
+                    H[b] += m;
+                    V[b][0] += g[0];
+                    V[b][1] += g[1];
+                    V[b][2] += g[2];
+                }
+        int prim[26];
+        int np = orc_peaks(H, tau, prim, &mg);
+        int nf = 0;
+        for (int ip = 0; ip < np && nf < kmax; ++ip) {
+            const double *v = V[prim[ip]];
+            double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            double e1[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
+            double H2[26], V2[26][3];
+            for (int b = 0; b < 26; ++b) H2[b] = V2[b][0] = V2[b][1] = V2[b][2] = 0.0;
+            for (int dz = -R; dz <= R; ++dz)
+                for (int dy = -R; dy <= R; ++dy)
+                    for (int dx = -R; dx <= R; ++dx) {
+                        double g[3];
+                        orc_sample_grad(G, nx, ny, nz, clampl(vx + dx, 0, nx - 1), clampl(vy + dy, 0, ny - 1),
+                                        clampl(vz + dz, 0, nz - 1), g);
+                        double a = g[0] * e1[0] + g[1] * e1[1] + g[2] * e1[2];
+                        double p[3] = {g[0] - a * e1[0], g[1] - a * e1[1], g[2] - a * e1[2]};
+                        double m2 = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+                        if (!(m2 > 0.0)) continue;
+                        int b = orc_dirbin(p, &mg);
+                        H2[b] += m2;
+                        V2[b][0] += p[0];
+                        V2[b][1] += p[1];
+                        V2[b][2] += p[2];
+                    }
+            int sec[26];
+            int ns = orc_peaks(H2, tau, sec, &mg);
+            for (int is = 0; is < ns && nf < kmax; ++is) {
+                const double *w = V2[sec[is]];
+                double a = w[0] * e1[0] + w[1] * e1[1] + w[2] * e1[2];
+                double u[3] = {w[0] - a * e1[0], w[1] - a * e1[1], w[2] - a * e1[2]};
+                double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                if (!(un > 0.0)) continue;
+                double e2[3] = {u[0] / un, u[1] / un, u[2] / un};
+                double e3[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                                e1[0] * e2[1] - e1[1] * e2[0]};
+                double *F = frames + ((size_t)k * kmax + nf) * 9;
+                for (int i = 0; i < 3; ++i) {
+                    F[3 * i + 0] = e1[i];
+                    F[3 * i + 1] = e2[i];
+                    F[3 * i + 2] = e3[i];
+                }
+                ++nf;
+            }
+        }
+        nframes[k] = nf;
+        /* oriented SIFT-Rank per frame */
+        for (int f = 0; f < nf; ++f) {
+            double *h = hist + ((size_t)k * kmax + f) * 64;
+            orc_frame_hist(G, nx, ny, nz, vx, vy, vz, R, frames + ((size_t)k * kmax + f) * 9, h, &mg);
+            int r[64];
+            orc_rank(h, 64, r);
+            for (int e = 0; e < 64; ++e) rank[((size_t)k * kmax + f) * 64 + e] = (uint8_t)r[e];
+        }
+        margin[k] = mg;
+    }
+}

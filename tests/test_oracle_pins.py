@@ -673,3 +673,138 @@ def test_detect_input_space_position_and_sigma_exact(sb, o, s):
     assert (float(h["xf"]), float(h["yf"]), float(h["zf"])) == (c, c, c)
     assert int(h["x"]) * 2 ** o + (2 ** o - 1) / 2 == c
     assert float(h["sigma"]) == pytest.approx(_sigma_s(s) * 2 ** o, rel=1e-7)
+
+
+# ------------------------------------------------------------------ orientation (reading R25)
+def _cube_rotations():
+    """The 24 proper signed permutation matrices (rotations of the cube)."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            Q = np.zeros((3, 3))
+            for i, j in enumerate(perm):
+                Q[i, j] = signs[i]
+            if round(np.linalg.det(Q)) == 1:
+                out.append(Q)
+    return out
+
+
+def _rotate_volume(V, Q):
+    """V'(Q x) = V(x) about the centre voxel of a cubic volume of odd side;
+    volumes are [z, y, x], Q acts on (x, y, z)."""
+    n = V.shape[0]
+    c = (n - 1) // 2
+    idx = np.indices((n, n, n)).reshape(3, -1)          # (z, y, x) of each output voxel
+    xyz = idx[::-1] - c                                  # (x, y, z) relative to the centre
+    src = (Q.T @ xyz).round().astype(int) + c            # x = Q^T x'
+    return V[src[2], src[1], src[0]].reshape(V.shape)
+
+
+def _smooth_cube(n, seed):
+    v = ndi.gaussian_filter(rnd((n, n, n), seed), 2.0, mode="wrap")
+    return v / np.abs(v).max()
+
+
+def test_orientation_identity_frame_is_the_upright_descriptor():
+    G = _smooth_cube(21, 40)
+    kp = np.array([[10, 10, 10], [3, 17, 8], [0, 0, 20]])
+    for R in (5, 6, 7):
+        h0, r0 = O.siftrank(G, kp, R)
+        h1, r1, _ = O.siftrank_frames(G, kp, R, np.repeat(np.eye(3)[None], len(kp), axis=0))
+        assert np.array_equal(h0, h1) and np.array_equal(r0, r1), R
+
+
+def test_orientation_covariant_under_the_24_cube_rotations():
+    """Rotating the volume about the keypoint by a rotation of the cube
+    rotates every frame by it and leaves every oriented descriptor
+    unchanged (the 26 directions and their neighbour relation are closed
+    under these rotations; sums differ only in rounding order)."""
+    n, R = 25, 6
+    c = (n - 1) // 2
+    G = _smooth_cube(n, 41)
+    kp = np.array([[c, c, c]])
+    ref = O.orient(G, kp, R)
+    assert ref["margin"][0] > 1e-9 and ref["nframes"][0] >= 1
+    nf = ref["nframes"][0]
+    for Q in _cube_rotations():
+        got = O.orient(_rotate_volume(G, Q), kp, R)
+        assert got["nframes"][0] == nf
+        for f in range(nf):
+            np.testing.assert_allclose(got["frames"][0, f], Q @ ref["frames"][0, f], atol=1e-12)
+            assert np.array_equal(got["rank"][0, f], ref["rank"][0, f])
+            np.testing.assert_allclose(got["hist"][0, f], ref["hist"][0, f], rtol=1e-12, atol=0)
+
+
+def test_orientation_of_an_axis_aligned_anisotropic_blob():
+    """A Gaussian blob whose axes are the grid axes, shortest along x and
+    longest along z: the gradient histogram peaks at +-x (equal heights by
+    symmetry), the secondary at +-y, so the four frames are (+-x, +-y)."""
+    n = 31
+    c = (n - 1) // 2
+    z, y, x = np.indices((n, n, n)) - c
+    G = np.exp(-(x ** 2 / (2 * 2.0 ** 2) + y ** 2 / (2 * 3.5 ** 2) + z ** 2 / (2 * 5.0 ** 2)))
+    r = O.orient(G, np.array([[c, c, c]]), 7)
+    assert r["nframes"][0] == 4
+    e1 = sorted(tuple(np.round(r["frames"][0, f][:, 0], 9)) for f in range(4))
+    e2 = sorted(tuple(np.round(r["frames"][0, f][:, 1], 9)) for f in range(4))
+    assert e1 == sorted([(-1.0, 0.0, 0.0)] * 2 + [(1.0, 0.0, 0.0)] * 2)
+    assert e2 == sorted([(0.0, -1.0, 0.0), (0.0, 1.0, 0.0)] * 2)
+    for f in range(4):
+        F = r["frames"][0, f]
+        np.testing.assert_allclose(F.T @ F, np.eye(3), atol=1e-12)
+        assert abs(np.linalg.det(F) - 1.0) < 1e-12
+
+
+def test_orientation_of_a_rotated_anisotropic_blob():
+    """A strongly anisotropic blob rotated by a generic rotation: the
+    primary axis is its short axis (up to sign) and the secondary its middle
+    axis, within the bin's averaging error."""
+    n = 41
+    c = (n - 1) // 2
+    a, b, g = 0.4, 0.7, 1.1                                # Euler angles
+    Rz = lambda t: np.array([[np.cos(t), -np.sin(t), 0], [np.sin(t), np.cos(t), 0], [0, 0, 1]])
+    Ry = lambda t: np.array([[np.cos(t), 0, np.sin(t)], [0, 1, 0], [-np.sin(t), 0, np.cos(t)]])
+    Q0 = Rz(a) @ Ry(b) @ Rz(g)
+    z, y, x = np.indices((n, n, n)) - c
+    X = np.stack([x, y, z]).reshape(3, -1).astype(float)
+    U = Q0.T @ X                                           # coordinates along the blob's axes
+    G = np.exp(-(U[0] ** 2 / (2 * 1.5 ** 2) + U[1] ** 2 / (2 * 4.0 ** 2) + U[2] ** 2 / (2 * 8.0 ** 2))).reshape(n, n, n)
+    r = O.orient(G, np.array([[c, c, c]]), 7)
+    assert r["nframes"][0] >= 1
+    F = r["frames"][0, 0]
+    assert abs(F[:, 0] @ Q0[:, 0]) > math.cos(math.radians(10))
+    assert abs(F[:, 1] @ Q0[:, 1]) > math.cos(math.radians(20))
+
+
+def test_orientation_offset_and_power_of_two_scaling_invariance():
+    """Values on a 2^-20 grid: adding 1 and doubling are exact, so the
+    gradients, decisions, frames and descriptors are identical."""
+    G = np.round(_smooth_cube(21, 42) * 2 ** 20) / 2 ** 20
+    kp = np.array([[10, 10, 10], [6, 12, 9]])
+    ref = O.orient(G, kp, 6)
+    for H in (G + 1.0, 2.0 * G):
+        got = O.orient(H, kp, 6)
+        assert np.array_equal(got["nframes"], ref["nframes"])
+        assert np.array_equal(got["frames"], ref["frames"])
+        assert np.array_equal(got["rank"], ref["rank"])
+
+
+@pytest.mark.parametrize("ratio,primaries", [(0.95, 2), (0.85, 2), (0.75, 1), (0.6, 1)])
+def test_orientation_peak_threshold_and_neighbours(ratio, primaries):
+    """Gradient a along x below the keypoint's plane and b along y from it
+    on (6 of the window's 11 planes against 5): H(+y) / H(+x) ~ ratio. +y is
+    90 degrees from +x, so it is not a neighbour and is a second primary
+    exactly when it reaches 0.8 of the maximum; each primary then takes the
+    other direction as its secondary."""
+    n, c = 21, 10
+    z, y, x = np.indices((n, n, n)) - c
+    G = np.where(z < 0, 1.0 * x, ratio * 5 / 6 * y).astype(float)
+    r = O.orient(G, np.array([[c, c, c]]), 5)
+    assert r["nframes"][0] == primaries
+    got = {tuple(np.round(r["frames"][0, f][:, 0], 9)) for f in range(primaries)}
+    want = {(1.0, 0.0, 0.0), (0.0, 1.0, 0.0)} if primaries == 2 else {(1.0, 0.0, 0.0)}
+    assert got == want
+    for f in range(primaries):
+        e1, e2 = r["frames"][0, f][:, 0], r["frames"][0, f][:, 1]
+        assert abs(e1 @ e2) < 1e-12 and set(np.round(np.abs(e1 + e2), 9)) == {0.0, 1.0}
