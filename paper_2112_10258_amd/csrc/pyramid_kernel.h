@@ -99,12 +99,20 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
 {
     constexpr int TX = kBlurTX, NY = kBlurNY, NT = blur_threads(TY);
     constexpr int M = 2 * R + 1;
+    constexpr int LR = M + 1;                       // y-ring length: even, so two staging buffers alternate in step
     constexpr int RB = PB ? kFusedPreR : 0;         // pre-blur radius
     constexpr int MB = 2 * RB + 1;
     constexpr int BH = TY + 2 * RB;                 // pre-blur rows of the x pass
     static_assert(!PB || (DOG && R >= kFusedPreR), "the pre-blur rides on level passes with a halo >= its radius");
     constexpr int AWL = TX + 2 * R;                 // staged width
-    constexpr int AW = (AWL + 3) & ~3;              // LDS row pitch (16-byte rows)
+    // LDS row pitches, both 16 (mod 32) floats. The x pass reads A and
+    // writes B as float4, 16 lanes at a time covering two rows two apart;
+    // the y pass reads B one row per half-wavefront, the halves two rows
+    // apart. A pitch of 16 (mod 32) puts those two rows in disjoint halves
+    // of the 64 LDS banks, so none of these accesses conflict.
+    constexpr int AW = AWL + ((16 - AWL % 32) + 32) % 32;
+    constexpr int BW = 48;
+    static_assert(AW % 32 == 16 && AW >= AWL && BW % 32 == 16 && BW >= TX, "LDS pitches");
     constexpr int AH = TY + 2 * R;                  // staged height
     constexpr int AE = AH * AWL;
     constexpr int KL = (AE + NT - 1) / NT;          // staged elements per thread
@@ -113,12 +121,12 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
     static_assert(NY == 2, "sub-sampling pairs rows inside a thread");
     // staging tile plus one dummy slot per unused staging lane (branch-free writes)
     __shared__ __align__(16) float A[AH * AW + KL * NT - AE];
-    __shared__ __align__(16) float B[AH * TX];
+    __shared__ __align__(16) float B[AH * BW];
     // centre values (G_{i-1} at the thread's output voxels) of the last R+1
     // input planes: private to each thread, kept in LDS because the slot
     // index is not a compile-time constant
     __shared__ float C[DOG ? (R + 1) * NY * NT : 1];
-    __shared__ __align__(16) float B2[PB ? BH * TX : 1];
+    __shared__ __align__(16) float B2[PB ? BH * BW : 1];
 
     const int tid = threadIdx.x;
     const int logical = xcd_remap(blockIdx.x, fl.n_blocks);
@@ -156,11 +164,13 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
             loff[k] = AH * AW + (idx - AE);
         }
     }
-    float pre[KL];
-    auto load_plane = [&](int zi) {
+    // two planes in flight: staging buffer b holds the plane of every step
+    // with the parity b
+    float pre[2][KL];
+    auto load_plane = [&](float(&dstv)[KL], int zi) {
         const auto rs = plane_rsrc(src + (size_t)clampi(zi, 0, nz - 1) * nxy, plane_bytes);
 #pragma unroll
-        for (int k = 0; k < KL; ++k) pre[k] = buf_load(rs, goff[k]);
+        for (int k = 0; k < KL; ++k) dstv[k] = buf_load(rs, goff[k]);
     };
 
     float w[M];
@@ -191,130 +201,160 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
     const unsigned so = (tx & 1) == 0 && (gx >> 1) < jb.mx && (gy0 >> 1) < jb.my
                             ? 4u * (unsigned)((gy0 >> 1) * jb.mx + (gx >> 1))
                             : kDropOffset;
-    float ring[NY][M];
+    float ring[NY][LR];
 #pragma unroll
     for (int j = 0; j < NY; ++j)
 #pragma unroll
-        for (int t = 0; t < M; ++t) ring[j][t] = 0.f;
+        for (int t = 0; t < LR; ++t) ring[j][t] = 0.f;
     float subacc = 0.f;
     int cslot = 0;                                  // C slot of the current step (it mod R+1)
 
     // Input plane z0 - R + it is staged at step it; output plane z0 + it - 2R
     // completes at step it. The plane loop is unrolled by the ring length so
     // that every ring slot is a fixed register.
+    //
+    // Every step issues the same memory operations: the loads of the next
+    // plane (the last input plane again at the final step) and one store per
+    // output stream, whose per-lane offset is kDropOffset while the step has
+    // nothing to write there. Loads and stores share one completion counter;
+    // with a fixed count after each plane's loads, the wait before staging
+    // that plane covers its loads only, not the stores issued after them.
     const int nplanes = (z1 - z0) + 2 * R;
-    load_plane(z0 - R);
-    for (int base = 0; base < nplanes; base += M) {
-        static_for<0, M>([&](auto pc) {
+    const int zin_last = z1 - 1 + R;               // last input plane of the slab
+    const bool has_sub = subp != nullptr;
+    float *const subbase = has_sub ? subp : dst;
+    const unsigned sub_bytes = has_sub ? 4u * (unsigned)sub_plane : 0u;   // 0: every store dropped
+    load_plane(pre[0], z0 - R);
+    load_plane(pre[1], z0 - R + 1);
+    // Steps past the slab's last (dead steps, only in the final round of the
+    // unrolled loop) skip the arithmetic but keep the memory operations and
+    // barriers, so the loop body has no early exit and the same operation
+    // count on every path.
+    for (int base = 0; base < nplanes; base += LR) {
+        static_for<0, LR>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
+            constexpr int pb = p & 1;
             const int it = base + p;
-            if (it >= nplanes) return;
+            const bool live = it < nplanes;
 #pragma unroll
-            for (int k = 0; k < KL; ++k) A[loff[k]] = pre[k];
+            for (int k = 0; k < KL; ++k) A[loff[k]] = pre[pb][k];
             __syncthreads();
-            if (it + 1 < nplanes) load_plane(z0 - R + it + 1);
+            load_plane(pre[pb], min(z0 - R + it + 2, zin_last));
             const int oz = z0 + it - 2 * R;
+            const bool zact = live && it >= 2 * R;  // output plane oz exists
             float cv0 = 0.f, cv1 = 0.f;
-            if constexpr (DOG) {
-                // D_{i-1} needs G_{i-1} at the output voxel: keep this plane's centre
-                // values, and take those of the plane staged R steps ago (slot cslot+1)
-                const int rslot = cslot == R ? 0 : cslot + 1;
-                C[(cslot * NY + 0) * NT + tid] = A[(R + tyb) * AW + R + tx];
-                C[(cslot * NY + 1) * NT + tid] = A[(R + tyb + 1) * AW + R + tx];
-                if (it >= 2 * R) {
-                    cv0 = C[(rslot * NY + 0) * NT + tid];
-                    cv1 = C[(rslot * NY + 1) * NT + tid];
+            if (live) {
+                if constexpr (DOG) {
+                    // D_{i-1} needs G_{i-1} at the output voxel: keep this plane's centre
+                    // values, and take those of the plane staged R steps ago (slot cslot+1)
+                    const int rslot = cslot == R ? 0 : cslot + 1;
+                    C[(cslot * NY + 0) * NT + tid] = A[(R + tyb) * AW + R + tx];
+                    C[(cslot * NY + 1) * NT + tid] = A[(R + tyb + 1) * AW + R + tx];
+                    if (zact) {
+                        cv0 = C[(rslot * NY + 0) * NT + tid];
+                        cv1 = C[(rslot * NY + 1) * NT + tid];
+                    }
+                    cslot = rslot;
                 }
-                cslot = rslot;
-            }
 
-            // x pass: 4 consecutive outputs per item from one LDS strip
-            for (int item = tid; item < AH * XQ; item += NT) {
-                const int r = item / XQ, xb = (item - r * XQ) * 4;
-                float in[XIN];
-                const float4 *s4 = reinterpret_cast<const float4 *>(&A[r * AW + xb]);
+                // x pass: 4 consecutive outputs per item from one LDS strip. A
+                // wavefront covers 8 rows per round, its 16-lane groups the
+                // rows {0, 2}, {1, 3}, {4, 6}, {5, 7} (8 items of a row each)
+                static_assert(XQ == 8, "8 items per row");
+                const int lane = tid & 63, lg = lane >> 4;
+                const int rlane = 4 * (lg >> 1) + (lg & 1) + 2 * ((lane >> 3) & 1);
+                const int xb = 4 * (lane & 7);
+                for (int r = 8 * (tid >> 6) + rlane; r < AH; r += 8 * (NT / 64)) {
+                    float in[XIN];
+                    const float4 *s4 = reinterpret_cast<const float4 *>(&A[r * AW + xb]);
 #pragma unroll
-                for (int q = 0; q < XIN / 4; ++q) {
-                    const float4 v = s4[q];
-                    in[4 * q + 0] = v.x;
-                    in[4 * q + 1] = v.y;
-                    in[4 * q + 2] = v.z;
-                    in[4 * q + 3] = v.w;
-                }
-                float o[4];
+                    for (int q = 0; q < XIN / 4; ++q) {
+                        const float4 v = s4[q];
+                        in[4 * q + 0] = v.x;
+                        in[4 * q + 1] = v.y;
+                        in[4 * q + 2] = v.z;
+                        in[4 * q + 3] = v.w;
+                    }
+                    float o[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) o[q] = sym_stencil<R>(w, [&](int t) { return in[q + t]; });
-                *reinterpret_cast<float4 *>(&B[r * TX + xb]) = make_float4(o[0], o[1], o[2], o[3]);
-                if constexpr (PB) {
-                    // rows y0 - RB .. y0 + TY + RB of the pre-blur, x from the same registers
-                    if (r >= R - RB && r < R + TY + RB) {
-                        float ob[4];
+                    for (int q = 0; q < 4; ++q) o[q] = sym_stencil<R>(w, [&](int t) { return in[q + t]; });
+                    *reinterpret_cast<float4 *>(&B[r * BW + xb]) = make_float4(o[0], o[1], o[2], o[3]);
+                    if constexpr (PB) {
+                        // rows y0 - RB .. y0 + TY + RB of the pre-blur, x from the same registers
+                        if (r >= R - RB && r < R + TY + RB) {
+                            float ob[4];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            ob[q] = sym_stencil<RB>(wb, [&](int t) { return in[q + R - RB + t]; });
-                        *reinterpret_cast<float4 *>(&B2[(r - (R - RB)) * TX + xb]) =
-                            make_float4(ob[0], ob[1], ob[2], ob[3]);
+                            for (int q = 0; q < 4; ++q)
+                                ob[q] = sym_stencil<RB>(wb, [&](int t) { return in[q + R - RB + t]; });
+                            *reinterpret_cast<float4 *>(&B2[(r - (R - RB)) * BW + xb]) =
+                                make_float4(ob[0], ob[1], ob[2], ob[3]);
+                        }
                     }
                 }
             }
             __syncthreads();
 
-            // y pass: NY consecutive outputs of column tx, into ring slot p
-            {
+            float pbv[NY], zo[NY];
+#pragma unroll
+            for (int j = 0; j < NY; ++j) pbv[j] = zo[j] = 0.f;
+            if (live) {
+                // y pass: NY consecutive outputs of column tx, into ring slot p
                 float col[NY + 2 * R];
 #pragma unroll
-                for (int q = 0; q < NY + 2 * R; ++q) col[q] = B[(tyb + q) * TX + tx];
+                for (int q = 0; q < NY + 2 * R; ++q) col[q] = B[(tyb + q) * BW + tx];
 #pragma unroll
                 for (int j = 0; j < NY; ++j) ring[j][p] = sym_stencil<R>(w, [&](int t) { return col[j + t]; });
-            }
 
-            if constexpr (PB) {
-                // pre-blur: y pass into the shift ring (oldest plane first), then z
-                float colb[NY + 2 * RB];
+                if constexpr (PB) {
+                    // pre-blur: y pass into the shift ring (oldest plane first), then z
+                    float colb[NY + 2 * RB];
 #pragma unroll
-                for (int q = 0; q < NY + 2 * RB; ++q) colb[q] = B2[(tyb + q) * TX + tx];
+                    for (int q = 0; q < NY + 2 * RB; ++q) colb[q] = B2[(tyb + q) * BW + tx];
 #pragma unroll
-                for (int j = 0; j < NY; ++j) {
+                    for (int j = 0; j < NY; ++j) {
 #pragma unroll
-                    for (int t = 0; t + 1 < MB; ++t) ringb[j][t] = ringb[j][t + 1];
-                    ringb[j][MB - 1] = sym_stencil<RB>(wb, [&](int t) { return colb[j + t]; });
-                }
-                // the ring now holds input planes zin - 2RB .. zin (zin = z0 - R + it);
-                // its centre plane is an output plane of this slab from step R + RB on
-                const int qz = z0 - R + it - RB;
-                if (it >= R + RB && qz < z1) {
-                    const auto rs = plane_rsrc(pbp + (size_t)qz * nxy, plane_bytes);
-#pragma unroll
-                    for (int j = 0; j < NY; ++j)
-                        buf_store(rs, j == 0 ? o0 : o1, sym_stencil<RB>(wb, [&](int t) { return ringb[j][t]; }));
-                }
-            }
-
-            if (it >= 2 * R) {
-                // z pass: slot (p + 1 + t) % M holds input plane (it - 2R + t)
-                float zo[NY];
-#pragma unroll
-                for (int j = 0; j < NY; ++j)
-                    zo[j] = sym_stencil<R>(w, [&](int t) { return ring[j][(p + 1 + t) % M]; });
-                const auto rd = plane_rsrc(dst + (size_t)oz * nxy, plane_bytes);
-                buf_store(rd, o0, zo[0]);
-                buf_store(rd, o1, zo[1]);
-                if constexpr (DOG) {
-                    const auto re = plane_rsrc(dogp + (size_t)oz * nxy, plane_bytes);
-                    buf_store(re, o0, cv0 - zo[0]);
-                    buf_store(re, o1, cv1 - zo[1]);
-                }
-                if (subp != nullptr) {
-                    const float s2 = zo[0] + zo[1];
-                    const float s4 = s2 + __shfl_xor(s2, 1);
-                    if ((oz & 1) == 0) {
-                        subacc = s4;
-                    } else if ((oz >> 1) < jb.mz) {
-                        const auto rsub = plane_rsrc(subp + (size_t)(oz >> 1) * sub_plane, 4u * (unsigned)sub_plane);
-                        buf_store(rsub, so, (subacc + s4) * 0.125f);
+                        for (int t = 0; t + 1 < MB; ++t) ringb[j][t] = ringb[j][t + 1];
+                        ringb[j][MB - 1] = sym_stencil<RB>(wb, [&](int t) { return colb[j + t]; });
+                        pbv[j] = sym_stencil<RB>(wb, [&](int t) { return ringb[j][t]; });
                     }
                 }
+                // z pass: slot (p + 2 + t) % LR holds input plane (it - 2R + t)
+                if (zact) {
+#pragma unroll
+                    for (int j = 0; j < NY; ++j)
+                        zo[j] = sym_stencil<R>(w, [&](int t) { return ring[j][(p + 2 + t) % LR]; });
+                }
             }
+            if constexpr (PB) {
+                // the pre-blur ring holds input planes zin - 2RB .. zin (zin = z0 - R + it);
+                // its centre plane is an output plane of this slab from step R + RB on
+                const int qz = z0 - R + it - RB;
+                const bool pact = live && it >= R + RB && qz < z1;
+                const auto rs = plane_rsrc(pbp + (size_t)clampi(qz, 0, nz - 1) * nxy, plane_bytes);
+                buf_store(rs, pact ? o0 : kDropOffset, pbv[0]);
+                buf_store(rs, pact ? o1 : kDropOffset, pbv[1]);
+            }
+            const int ozc = clampi(oz, 0, nz - 1);
+            const unsigned a0 = zact ? o0 : kDropOffset, a1 = zact ? o1 : kDropOffset;
+            const auto rd = plane_rsrc(dst + (size_t)ozc * nxy, plane_bytes);
+            buf_store(rd, a0, zo[0]);
+            buf_store(rd, a1, zo[1]);
+            if constexpr (DOG) {
+                const auto re = plane_rsrc(dogp + (size_t)ozc * nxy, plane_bytes);
+                buf_store(re, a0, cv0 - zo[0]);
+                buf_store(re, a1, cv1 - zo[1]);
+            }
+            // 2x2x2 mean: the even plane's partial sum waits in subacc, the odd
+            // plane completes it
+            float s4 = 0.f;
+            if (has_sub) {
+                const float s2 = zo[0] + zo[1];
+                s4 = s2 + __shfl_xor(s2, 1);
+            }
+            const bool sact = zact && (oz & 1) != 0 && (oz >> 1) < jb.mz;
+            const auto rsub = plane_rsrc(subbase + (size_t)(ozc >> 1) * sub_plane, sub_bytes);
+            buf_store(rsub, sact ? so : kDropOffset, (subacc + s4) * 0.125f);
+            if (zact && (oz & 1) == 0) subacc = s4;
         });
     }
 }
