@@ -263,8 +263,18 @@ def measure_plain(name, steps, warmup, kw, stream, stage_reps=10, vol=None):
                        stage_reps, stream)
     st_br = time_calls(lambda: plan.describe(buf.ws, buf.kp, buf.count, brief=buf.brief, rrief=buf.rrief,
                                              stream=stream), stage_reps, stream)
-    log("[bench] %s stages ms: pyramid %.4f detect %.4f siftrank %.4f brief+rrief %.4f"
-        % (name, st_pyr, st_det, st_sr, st_br))
+    # dominant orientations and oriented SIFT-Rank (beside the step: the
+    # step's SIFT-Rank is the upright one)
+    nk = S.MAX_ORIENTATIONS
+    o_nf = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    o_fr = torch.zeros(cap, nk, 9, dtype=torch.float32, device="cuda")
+    o_sr = torch.zeros(cap, nk, 64, dtype=torch.uint8, device="cuda")
+    st_or = time_calls(lambda: plan.orient(buf.ws, buf.kp, buf.count, o_nf, o_fr, o_sr, 0.8, stream),
+                       max(2, stage_reps // 2), stream)
+    frames_hist = np.bincount(o_nf[:min(count, cap)].cpu().numpy(), minlength=nk + 1).tolist()
+    del o_nf, o_fr, o_sr
+    log("[bench] %s stages ms: pyramid %.4f detect %.4f siftrank %.4f brief+rrief %.4f orient %.4f "
+        "(frames per keypoint %s)" % (name, st_pyr, st_det, st_sr, st_br, st_or, frames_hist))
     res = {
         "volumes_per_s": round(1000.0 / ms_step, 2),
         "ms_per_step": round(ms_step, 4),
@@ -273,6 +283,8 @@ def measure_plain(name, steps, warmup, kw, stream, stage_reps=10, vol=None):
         "pyramid_launches": nl,
         "stages_ms": {"pyramid": round(st_pyr, 4), "detect": round(st_det, 4), "siftrank": round(st_sr, 4),
                       "brief_rrief": round(st_br, 4)},
+        "orientation": {"ms": round(st_or, 4), "frames_per_keypoint_histogram": frames_hist,
+                        "note": "sift3d_orient (frames and oriented SIFT-Rank), not part of the timed step"},
         "roofline": roofline,
     }
     return res, (ctx, plan, buf, dvol, vol)
@@ -659,6 +671,7 @@ def main():
                    "parallelism": "single GPU"},
         "voxels_per_s": head["voxels_per_s"],
         "stages_ms": head["stages_ms"],
+        "orientation": head["orientation"],
         "roofline": head["roofline"],
         "extra_workloads": extras or None,
         "batch": batch,

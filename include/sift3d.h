@@ -304,6 +304,37 @@ int sift3d_describe(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes,
                     const sift3d_keypoint *d_kp, const int *d_count, int kp_capacity,
                     uint8_t *d_siftrank, uint64_t *d_brief, uint8_t *d_rrief, void *stream);
 
+/*
+ * Dominant orientations and SIFT-Rank after reorientation (Related Work,
+ * 3D SIFT-Rank: dominant peaks of a discrete spherical histogram of
+ * gradient directions give one or more 3x3 rotations per keypoint, and the
+ * descriptor is computed in each rotated frame). For keypoint k of volume v
+ * (row v * kp_capacity + k, k < min(d_count[v], kp_capacity)), on G_s of
+ * its octave, over the SIFT-Rank window d in [-R, R]^3:
+ *   - every sample's gradient g (central differences at clamp(v + d)) with
+ *     |g| > 0 goes to the nearest of the 26 directions n/|n|,
+ *     n in {-1,0,1}^3 \ {0}; a bin sums |g| and g;
+ *   - peaks: bins whose sum is >= peak_ratio times the largest and above
+ *     every bin within 60 degrees (equal sums: the lower bin number, with
+ *     bins numbered in (z, y, x) order of n, wins), in decreasing order;
+ *     each gives a primary axis e1 = the bin's mean gradient, normalised;
+ *   - per primary axis, the same histogram of g - (g.e1) e1; each of its
+ *     peaks gives e2 (its mean, orthogonal part, normalised), e3 = e1 x e2;
+ *   - frames are listed primary by primary, at most SIFT3D_MAX_ORIENTATIONS;
+ *   - per frame, SIFT-Rank with each sample's offset and gradient in frame
+ *     coordinates (R^T d, R^T g) and the upright binning rules.
+ * Outputs: d_nframes [cap] int (0..SIFT3D_MAX_ORIENTATIONS); d_frames
+ * [cap][SIFT3D_MAX_ORIENTATIONS][9] float32, R[3 i + j] = component i of
+ * axis j (unused frames zero); d_siftrank [cap][SIFT3D_MAX_ORIENTATIONS][64]
+ * uint8 ranks (unused frames zero). Sums are fixed-point integers, so the
+ * results are bit-reproducible. 0 < peak_ratio <= 1 (0.8 is the usual
+ * value), else SIFT3D_E_ARG. The pyramid must have been built in d_ws.
+ */
+#define SIFT3D_MAX_ORIENTATIONS 4
+int sift3d_orient(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes,
+                  const sift3d_keypoint *d_kp, const int *d_count, int kp_capacity, double peak_ratio,
+                  int *d_nframes, float *d_frames, uint8_t *d_siftrank, void *stream);
+
 /* build_pyramid + detect + describe on one stream. */
 int sift3d_extract(const sift3d_plan *plan, const float *d_vol, void *d_ws, size_t ws_bytes,
                    sift3d_keypoint *d_kp, int kp_capacity, int *d_count, uint8_t *d_siftrank,

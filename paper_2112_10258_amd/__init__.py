@@ -7,6 +7,7 @@ declared in include/sift3d.h.
 from .sift3d import (  # noqa: F401
     DETECT_STATIC_SCRATCH,
     KEYPOINT_BYTES,
+    MAX_ORIENTATIONS,
     KEYPOINT_DTYPE,
     MATCH_BRIEF,
     MATCH_RANKS,

@@ -1305,6 +1305,38 @@ int sift3d_describe(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes, 
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }
 
+int sift3d_orient(const sift3d_plan *plan, const void *d_ws, size_t ws_bytes, const sift3d_keypoint *d_kp,
+                  const int *d_count, int kp_capacity, double peak_ratio, int *d_nframes, float *d_frames,
+                  uint8_t *d_siftrank, void *stream)
+{
+    int rc = check_ws(plan, d_ws, ws_bytes);
+    if (rc != SIFT3D_OK) return rc;
+    if (d_count == nullptr || kp_capacity < 0 || (kp_capacity > 0 && d_kp == nullptr)) return SIFT3D_E_ARG;
+    if (!(peak_ratio > 0.0 && peak_ratio <= 1.0)) return SIFT3D_E_ARG;
+    if (kp_capacity > 0 && (d_nframes == nullptr || d_frames == nullptr || d_siftrank == nullptr)) return SIFT3D_E_ARG;
+    const sift3d_params &p = plan->ctx->p;
+    OrientLaunch a{};
+    a.units = plan->d_units;
+    a.vols = plan->d_vols;
+    a.n_vol = plan->n_vol;
+    a.S = plan->S;
+    for (int s = 0; s <= plan->S; ++s) a.sift_R[s] = (int)std::ceil(p.siftrank_factor * scale_sigma(p, s));
+    a.ws = const_cast<char *>(static_cast<const char *>(d_ws));
+    a.kp = d_kp;
+    a.counts = d_count;
+    a.cap = kp_capacity;
+    a.tau = peak_ratio;
+    a.nframes = d_nframes;
+    a.frames = d_frames;
+    a.siftrank = d_siftrank;
+    a.n_units = (int)plan->units.size();
+    if (a.n_units <= kInlineUnits)
+        for (int u = 0; u < a.n_units; ++u) a.inl[u] = plan->units[u];
+    const hipError_t e = launch_orient(a, (long long)kp_capacity * plan->n_vol, plan->ctx->n_cu,
+                                       static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
+}
+
 int sift3d_extract(const sift3d_plan *plan, const float *d_vol, void *d_ws, size_t ws_bytes, sift3d_keypoint *d_kp,
                    int kp_capacity, int *d_count, uint8_t *d_siftrank, uint64_t *d_brief, uint8_t *d_rrief,
                    void *stream)

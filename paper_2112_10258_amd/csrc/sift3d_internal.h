@@ -247,6 +247,25 @@ struct DescLaunch {
     DUnit inl[kInlineUnits];      // copy of units when n_units <= kInlineUnits
 };
 
+// Dominant orientations and oriented SIFT-Rank (orient.hip).
+constexpr int kMaxOrient = SIFT3D_MAX_ORIENTATIONS;   // frames kept per keypoint
+
+struct OrientLaunch {
+    const DUnit *units;
+    const DVol *vols;
+    int n_vol, S, n_units;
+    int sift_R[kMaxScales + 1];
+    char *ws;
+    const sift3d_keypoint *kp;    // [n_vol][cap]
+    const int *counts;            // [n_vol]
+    int cap;
+    double tau;                   // peak threshold relative to the histogram maximum
+    int *nframes;                 // [n_vol][cap]
+    float *frames;                // [n_vol][cap][kMaxOrient][9]
+    uint8_t *siftrank;            // [n_vol][cap][kMaxOrient][64]
+    DUnit inl[kInlineUnits];      // copy of units when n_units <= kInlineUnits
+};
+
 // ---------------------------------------------------------------- host plan
 
 struct OctaveGeom {
@@ -360,6 +379,7 @@ hipError_t launch_blur_z(const ZLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_blur_compact(const CompactLaunch &a, int max_r, hipStream_t st);
 hipError_t launch_detect(const DetLaunch &a, hipStream_t st);
 hipError_t launch_describe(const DescLaunch &a, long long kp_slots, int n_cu, hipStream_t st);
+hipError_t launch_orient(const OrientLaunch &a, long long kp_slots, int n_cu, hipStream_t st);
 
 // Workspace levels of an octave, in units of one padded level.
 inline int lev_G(int i) { return i; }

@@ -25,6 +25,7 @@ assert KEYPOINT_DTYPE.itemsize == KEYPOINT_BYTES
 
 OK, E_ARG, E_TOO_SMALL, E_WORKSPACE, E_HIP, E_UNSUPPORTED, E_SCRATCH = 0, -1, -2, -3, -5, -6, -7
 DETECT_STATIC_SCRATCH = 64 << 20     # SIFT3D_DETECT_STATIC_SCRATCH
+MAX_ORIENTATIONS = 4                 # SIFT3D_MAX_ORIENTATIONS
 PENDING = 1
 
 
@@ -136,6 +137,7 @@ def _load():
         "sift3d_detect_static": (i, [_vp, _vp, sz, _vp, i, _vp, _vp]),
         "sift3d_plan_detect_scratch": (i, [_vp, P(sz)]),
         "sift3d_describe": (i, [_vp, _vp, sz, _vp, _vp, i, _vp, _vp, _vp, _vp]),
+        "sift3d_orient": (i, [_vp, _vp, sz, _vp, _vp, i, ctypes.c_double, _vp, _vp, _vp, _vp]),
         "sift3d_extract": (i, [_vp, _vp, _vp, sz, _vp, i, _vp, _vp, _vp, _vp, _vp]),
         "sift3d_pyramid_pass_count": (i, [_vp, P(i)]),
         "sift3d_pyramid_pass_info": (i, [_vp, i, P(i), P(sz)]),
@@ -432,6 +434,14 @@ class Plan:
                                        _vp(count.data_ptr()), self.capacity, _vp(_ptr(siftrank)),
                                        _vp(_ptr(brief)), _vp(_ptr(rrief)), _vp(_stream(stream))),
                "sift3d_describe")
+
+    def orient(self, ws, kp, count, nframes, frames, siftrank, peak_ratio=0.8, stream=None):
+        """sift3d_orient: nframes [cap*n_volumes] int32, frames [.., 4, 9] float32,
+        siftrank [.., 4, 64] uint8 (torch device tensors)."""
+        _check(_load().sift3d_orient(self.handle, _vp(ws.data_ptr()), ws.numel(), _vp(_ptr(kp)),
+                                     _vp(count.data_ptr()), self.capacity, float(peak_ratio),
+                                     _vp(_ptr(nframes)), _vp(_ptr(frames)), _vp(_ptr(siftrank)),
+                                     _vp(_stream(stream))), "sift3d_orient")
 
     def extract(self, vol, ws, kp, count, siftrank=None, brief=None, rrief=None, stream=None):
         _check(_load().sift3d_extract(self.handle, _vp(vol.data_ptr()), _vp(ws.data_ptr()), ws.numel(),
