@@ -202,10 +202,12 @@ def launch_roofline(steps_info, launch_ms, workload):
     }
 
 
-def measure_plain(name, steps, warmup, kw, stream, stage_reps=10, vol=None):
+def measure_plain(name, steps, warmup, kw, stream, stage_reps=10, vol=None, tune=False):
     """K timed whole extractions of one volume resident in HBM (instrumented
-    steps), then a separate stage breakdown. Returns (result dict, context for
-    later use)."""
+    steps), then a separate stage breakdown. With tune, the plan is first
+    autotuned on this device (sift3d_plan_tune: tile height and slabs of its
+    fused launches; results unchanged bit for bit). Returns (result dict,
+    context for later use)."""
     import torch
 
     import paper_2112_10258_amd as S
@@ -218,6 +220,11 @@ def measure_plain(name, steps, warmup, kw, stream, stage_reps=10, vol=None):
     plan = S.Plan(ctx, (nx, ny, nz), cap)
     buf = S.Buffers(plan)
     dvol = torch.from_numpy(vol).cuda()
+    tuning = None
+    if tune:
+        t0 = time.perf_counter()
+        tuning = plan.tune(dvol, buf.ws, reps=3, stream=stream)
+        log(f"[bench] {name}: plan tuned in {time.perf_counter() - t0:.2f} s ({len(tuning)} fused launches)")
     steps_info = plan.pyramid_steps()
     nl = len(steps_info)
 
@@ -286,7 +293,13 @@ def measure_plain(name, steps, warmup, kw, stream, stage_reps=10, vol=None):
         "orientation": {"ms": round(st_or, 4), "frames_per_keypoint_histogram": frames_hist,
                         "note": "sift3d_orient (frames and oriented SIFT-Rank), not part of the timed step"},
         "roofline": roofline,
+        "plan": "autotuned (sift3d_plan_tune)" if tune else "default rule",
     }
+    if tuning is not None:
+        res["tuning"] = [{"step": r["step"], "default_ty_slabs": [r["default"]["ty"], r["default"]["slabs"]],
+                          "tuned_ty_slabs": [r["tuned"]["ty"], r["tuned"]["slabs"]],
+                          "default_us": round(r["default"]["ms"] * 1e3, 2), "tuned_us": round(r["tuned"]["ms"] * 1e3, 2)}
+                         for r in tuning]
     return res, (ctx, plan, buf, dvol, vol)
 
 
@@ -546,6 +559,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the config-2, box-filter and matching extras")
+    ap.add_argument("--no-tune", action="store_true", help="headline on the default plan (no sift3d_plan_tune)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB on the device a few times (reference dispatch for counter runs)")
     ap.add_argument("--pmc-steps", type=int, default=0,
@@ -590,11 +604,21 @@ def main():
     log(f"[bench] workload {args.workload}: {desc}")
     if args.pmc_steps:
         _, (ctx, plan, buf, dvol, _) = measure_plain(args.workload, args.pmc_steps, args.warmup, kw, stream,
+                                                     tune=not args.no_tune,
                                                      stage_reps=1)
         log(f"[bench] {args.pmc_steps} plain steps for the counters")
         return
-    head, (ctx, plan, buf, dvol, vol) = measure_plain(args.workload, args.steps, args.warmup, kw, stream)
+    untuned, keep = measure_plain(args.workload, args.steps, args.warmup, kw, stream)
+    vol = keep[4]
+    del keep
+    torch.cuda.empty_cache()
+    head, (ctx, plan, buf, dvol, vol) = measure_plain(args.workload, args.steps, args.warmup, kw, stream, vol=vol,
+                                                      tune=not args.no_tune)
     log(f"[bench] roofline: { {k: v for k, v in head['roofline'].items() if k != 'launches'} }")
+    untuned_summary = {"ms_per_step": untuned["ms_per_step"], "volumes_per_s": untuned["volumes_per_s"],
+                       "stages_ms": untuned["stages_ms"],
+                       "roofline_frac": untuned["roofline"]["frac"], "avg_launch_us": untuned["roofline"]["avg_launch_us"],
+                       "launches_us": [lv["us"] for lv in untuned["roofline"]["launches"]]}
 
     box = None
     if not args.no_extra and args.workload == "config4":
@@ -616,7 +640,11 @@ def main():
 
     extras = {}
     if not args.no_extra and args.workload != "config2":
-        c2, keep = measure_plain("config2", 50, 5, dict(WORKLOADS["config2"][1], **extra), stream)
+        c2d, keep = measure_plain("config2", 50, 5, dict(WORKLOADS["config2"][1], **extra), stream)
+        del keep
+        c2, keep = measure_plain("config2", 50, 5, dict(WORKLOADS["config2"][1], **extra), stream,
+                                 tune=not args.no_tune)
+        c2["untuned_plan"] = {"ms_per_step": c2d["ms_per_step"], "avg_launch_us": c2d["roofline"]["avg_launch_us"]}
         c2["roofline"].pop("launches", None)
         c2["note"] = "levels of 14.6 MB sit in the 256 MB last-level cache: algorithmic GB/s, not HBM"
         extras["config2"] = c2
@@ -672,6 +700,9 @@ def main():
         "voxels_per_s": head["voxels_per_s"],
         "stages_ms": head["stages_ms"],
         "orientation": head["orientation"],
+        "plan": head["plan"],
+        "tuning": head.get("tuning"),
+        "untuned_plan": untuned_summary,
         "roofline": head["roofline"],
         "extra_workloads": extras or None,
         "batch": batch,

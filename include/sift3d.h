@@ -240,6 +240,28 @@ int sift3d_pyramid_step(const sift3d_plan *plan, int step, const float *d_vol, v
                         void *stream);
 
 /*
+ * Autotune the plan's fused streaming launches on this device: for every
+ * fused launch of the schedule, time `reps` launches (after one untimed) of
+ * each candidate tile height (16 or 32 rows) and number of z-slabs per job
+ * (1, and 1/2 .. 4 times the rule that fills every resident workgroup slot
+ * once), and keep the fastest; the plan's schedule and device tables are
+ * rebuilt with the choices. The candidates compute every voxel's stencils
+ * in the same order, so a tuned plan gives bit-identical results. Runs the
+ * whole pyramid of d_vol into d_ws first (every launch's input must exist)
+ * and synchronises `stream` between candidates: a plan-time call, not to be
+ * made while other work uses the plan. On error the plan is restored to the
+ * default rule. reps in 1..1000.
+ */
+int sift3d_plan_tune(sift3d_plan *plan, const float *d_vol, void *d_ws, size_t ws_bytes, int reps, void *stream);
+
+/* Results of the last sift3d_plan_tune: one record per fused launch;
+ * info = {schedule step, default tile height, default slabs, tuned tile
+ * height, tuned slabs, candidates timed}, ms = {default, tuned} average
+ * launch time in milliseconds. */
+int sift3d_plan_tuning_count(const sift3d_plan *plan, int *n);
+int sift3d_plan_tuning(const sift3d_plan *plan, int idx, int info[6], float ms[2]);
+
+/*
  * 4D extremum detection (Section 3.2.2, 4D Peak Detection): for every
  * octave, scale s = 1..S and interior voxel v (1 <= x <= nx-2, same for y,
  * z) keep v if |D_s(v)| > dog_threshold and the sum over its 80 neighbours

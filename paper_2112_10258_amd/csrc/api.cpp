@@ -100,11 +100,20 @@ int check_params(const sift3d_params *p)
 // blocks but pay 2R halo planes each, and on a 145x174x145 octave 12 planes
 // beat both 8 (every resident slot filled, 2.25x the planes at R = 5) and
 // 2R (16 at R = 8: G_4 35 -> 31.5 us).
-int slab_planes(int nz, int slabs)
+//
+// The fused pass runs its plane loop in rounds of 2R + 2 steps (the length
+// of its register ring), and a slab of L planes takes L + 2R steps, so
+// steps past the end of a slab in its last round still cost their loads
+// and barriers. When a slab has more than one round, L is raised (by less
+// than one round) until L + 2R fills whole rounds; the last slab of a job
+// keeps the remainder.
+int slab_planes(int nz, int slabs, int r)
 {
     int L = (nz + slabs - 1) / slabs;
     L = std::max(L, kMinSlabPlanes);
     L = (L + 1) & ~1;
+    const int round = 2 * r + 2;
+    if (L + 2 * r > round) L = ((L + 2 * r + round - 1) / round) * round - 2 * r;   // even: round and 2r are
     return std::min(L, (nz + 1) & ~1);
 }
 
@@ -346,7 +355,7 @@ DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs, int ty, bool wi
         f.nz = g.nz;
         f.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
         f.tiles_y = (g.ny + ty - 1) / ty;
-        f.L = slab_planes(g.nz, slabs);
+        f.L = slab_planes(g.nz, slabs, pl->brief_rb);
         f.slabs = (g.nz + f.L - 1) / f.L;
         f.taps = pl->brief_tapset;
         f.pb = -1;
@@ -377,7 +386,7 @@ DFJob fused_job(const sift3d_plan *pl, const Task &k, int slabs, int ty, bool wi
     f.nz = g.nz;
     f.tiles_x = (g.nx + kBlurTX - 1) / kBlurTX;
     f.tiles_y = (g.ny + ty - 1) / ty;
-    f.L = slab_planes(g.nz, slabs);
+    f.L = slab_planes(g.nz, slabs, L.r);
     f.slabs = (g.nz + f.L - 1) / f.L;
     f.taps = L.tapset;
     if (with_pb) {
@@ -538,13 +547,16 @@ void build_schedule(sift3d_plan *pl)
                 (task_r(t) == r0 && task_dog(t) == dog0 && (with_pb[t] != 0) == pb0 ? grp : rest).push_back(t);
             long long voxels = 0;
             for (int t : grp) voxels += (long long)task_geom(t).n;
-            const int ty = voxels >= kBlurTallVoxels ? kBlurTYTall : kBlurTYSmall;
+            // tile height and slabs: the default rule, or the tuned pair of this step
+            const size_t si = pl->sched.size();
+            const bool tuned = si < pl->fused_tune.size() && pl->fused_tune[si].first > 0;
+            const int ty = tuned ? pl->fused_tune[si].first : (voxels >= kBlurTallVoxels ? kBlurTYTall : kBlurTYSmall);
             long long tiles = 0;
             for (int t : grp) {
                 const OctaveGeom &g = task_geom(t);
                 tiles += (long long)((g.nx + kBlurTX - 1) / kBlurTX) * ((g.ny + ty - 1) / ty);
             }
-            const int slabs = fused_slabs(pl, tiles, r0, dog0, pb0, ty);
+            const int slabs = tuned ? pl->fused_tune[si].second : fused_slabs(pl, tiles, r0, dog0, pb0, ty);
             Step st{0, grp, (int)pl->fjobs.size(), (int)grp.size(), 0, r0, dog0, ty, pb0};
             for (int t : grp) {
                 DFJob f = fused_job(pl, pl->tasks[t], slabs, ty, pb0);
@@ -625,9 +637,13 @@ void build_schedule(sift3d_plan *pl)
     }
 }
 
-// Upload the plan's device tables (one allocation).
+// Upload the plan's device tables (one allocation; a previous one is freed).
 int upload_tables(sift3d_plan *pl)
 {
+    if (pl->d_tables != nullptr) {
+        (void)hipFree(pl->d_tables);
+        pl->d_tables = nullptr;
+    }
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t b_units = al(pl->units.size() * sizeof(DUnit));
     const size_t b_vols = al(pl->dvols.size() * sizeof(DVol));
@@ -1212,6 +1228,132 @@ int sift3d_detect(const sift3d_plan *plan, void *d_ws, size_t ws_bytes, sift3d_k
     if (d_count == nullptr || kp_capacity < 0 || (kp_capacity > 0 && d_kp == nullptr)) return SIFT3D_E_ARG;
     char *ws = static_cast<char *>(d_ws);
     return run_detect(plan, ws, ws + plan->det_scratch_off, d_kp, kp_capacity, d_count, static_cast<hipStream_t>(stream));
+}
+
+int sift3d_plan_tune(sift3d_plan *plan, const float *d_vol, void *d_ws, size_t ws_bytes, int reps, void *stream)
+{
+    int rc = check_ws(plan, d_ws, ws_bytes);
+    if (rc != SIFT3D_OK) return rc;
+    if (d_vol == nullptr || reps < 1 || reps > 1000) return SIFT3D_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // start from the default rule
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e);
+    plan->tuning.clear();
+    plan->fused_tune.clear();
+    build_schedule(plan);
+    if ((rc = upload_tables(plan)) != SIFT3D_OK) return rc;
+    // every level the launches read
+    for (const Step &stp : plan->sched)
+        if ((rc = run_step(plan, stp, d_vol, d_ws, st)) != SIFT3D_OK) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e);
+    }
+    // average ms of `reps` launches of step i, after one untimed launch
+    auto time_step = [&](int i, float &ms) -> int {
+        int r = run_step(plan, plan->sched[i], d_vol, d_ws, st);
+        hipError_t ee = hipEventRecord(e0, st);
+        for (int k = 0; r == SIFT3D_OK && ee == hipSuccess && k < reps; ++k) r = run_step(plan, plan->sched[i], d_vol, d_ws, st);
+        if (ee == hipSuccess) ee = hipEventRecord(e1, st);
+        if (ee == hipSuccess) ee = hipEventSynchronize(e1);
+        if (ee == hipSuccess) ee = hipEventElapsedTime(&ms, e0, e1);
+        if (r != SIFT3D_OK) return r;
+        if (ee != hipSuccess) return hip_fail(ee);
+        ms /= (float)reps;
+        return SIFT3D_OK;
+    };
+    // re-plan with the current overrides (the stream is idle: every timing synchronised)
+    auto replan = [&]() -> int {
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e);
+        build_schedule(plan);
+        return upload_tables(plan);
+    };
+    plan->fused_tune.assign(plan->sched.size(), {0, 0});
+    const size_t n = plan->sched.size();
+    for (size_t i = 0; i < n && rc == SIFT3D_OK; ++i) {
+        const Step def = plan->sched[i];
+        if (def.type != 0) continue;
+        const int def_slabs = plan->fjobs[def.first].slabs;
+        sift3d_plan::TuneRecord tr{(int)i, def.ty, def_slabs, def.ty, def_slabs, 0, 0.f, 0.f};
+        if ((rc = time_step((int)i, tr.def_ms)) != SIFT3D_OK) break;
+        tr.ms = tr.def_ms;
+        int best_req = 0;                       // requested slabs of the best candidate (0: default rule)
+        std::vector<std::pair<int, int>> tried{{def.ty, def_slabs}};
+        // candidates: both tile heights, slabs around the default fill rule
+        // (tile heights and slab splits change no result: every voxel's
+        // stencils run in the same order)
+        for (int ty : {kBlurTYSmall, kBlurTYTall}) {
+            long long tiles = 0;
+            for (int t : def.tasks) {
+                const Task &k = plan->tasks[t];
+                const OctaveGeom &g = plan->vols[k.vol].oct[k.kind == 0 ? plan->blur[k.pass].octave : k.octave];
+                tiles += (long long)((g.nx + kBlurTX - 1) / kBlurTX) * ((g.ny + ty - 1) / ty);
+            }
+            const int s0 = fused_slabs(plan, tiles, def.max_r, def.dog, def.pb, ty);
+            std::vector<int> cands;
+            for (int sl : {1, (s0 + 1) / 2, s0, (3 * s0 + 1) / 2, 2 * s0, 3 * s0, 4 * s0})
+                if (sl >= 1 && std::find(cands.begin(), cands.end(), sl) == cands.end()) cands.push_back(sl);
+            for (int sl : cands) {
+                plan->fused_tune[i] = {ty, sl};
+                if ((rc = replan()) != SIFT3D_OK) break;
+                // the slab length rules can merge requests: time each layout once
+                const std::pair<int, int> got{ty, plan->fjobs[plan->sched[i].first].slabs};
+                if (std::find(tried.begin(), tried.end(), got) != tried.end()) continue;
+                tried.push_back(got);
+                float ms = 0.f;
+                if ((rc = time_step((int)i, ms)) != SIFT3D_OK) break;
+                ++tr.candidates;
+                if (ms < tr.ms) {
+                    tr.ms = ms;
+                    tr.ty = got.first;
+                    tr.slabs = got.second;
+                    best_req = sl;
+                }
+            }
+            if (rc != SIFT3D_OK) break;
+        }
+        plan->fused_tune[i] = best_req > 0 ? std::make_pair(tr.ty, best_req) : std::make_pair(0, 0);
+        plan->tuning.push_back(tr);
+    }
+    if (rc == SIFT3D_OK) rc = replan();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SIFT3D_OK) {
+        // back to the default rule
+        plan->fused_tune.clear();
+        plan->tuning.clear();
+        (void)hipStreamSynchronize(st);
+        build_schedule(plan);
+        (void)upload_tables(plan);
+    }
+    return rc;
+}
+
+int sift3d_plan_tuning_count(const sift3d_plan *plan, int *n)
+{
+    if (plan == nullptr || n == nullptr) return SIFT3D_E_ARG;
+    *n = (int)plan->tuning.size();
+    return SIFT3D_OK;
+}
+
+int sift3d_plan_tuning(const sift3d_plan *plan, int idx, int info[6], float ms[2])
+{
+    if (plan == nullptr || idx < 0 || idx >= (int)plan->tuning.size() || info == nullptr || ms == nullptr)
+        return SIFT3D_E_ARG;
+    const auto &t = plan->tuning[idx];
+    info[0] = t.step;
+    info[1] = t.def_ty;
+    info[2] = t.def_slabs;
+    info[3] = t.ty;
+    info[4] = t.slabs;
+    info[5] = t.candidates;
+    ms[0] = t.def_ms;
+    ms[1] = t.ms;
+    return SIFT3D_OK;
 }
 
 int sift3d_plan_detect_scratch(const sift3d_plan *plan, size_t *bytes)

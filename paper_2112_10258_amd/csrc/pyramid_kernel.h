@@ -230,9 +230,14 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
     // unrolled loop) skip the arithmetic but keep the memory operations and
     // barriers, so the loop body has no early exit and the same operation
     // count on every path.
-    for (int base = 0; base < nplanes; base += LR) {
-        static_for<0, LR>([&](auto pc) {
+    // The first round is peeled: there the step number is a constant, and
+    // the steps before any output exists (the first 2R for G and D, R + RB
+    // for the pre-blur) issue no stores. Every later step issues all of them.
+    auto step = [&](auto pc, int base, auto first_round) {
             constexpr int p = decltype(pc)::value;
+            constexpr bool FIRST = decltype(first_round)::value;
+            constexpr bool ZSTORE = !FIRST || p >= 2 * R;       // G, D and sub-sample stores issued
+            constexpr bool PSTORE = !FIRST || p >= R + RB;      // pre-blur stores issued
             constexpr int pb = p & 1;
             const int it = base + p;
             const bool live = it < nplanes;
@@ -325,7 +330,7 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
                         zo[j] = sym_stencil<R>(w, [&](int t) { return ring[j][(p + 2 + t) % LR]; });
                 }
             }
-            if constexpr (PB) {
+            if constexpr (PB && PSTORE) {
                 // the pre-blur ring holds input planes zin - 2RB .. zin (zin = z0 - R + it);
                 // its centre plane is an output plane of this slab from step R + RB on
                 const int qz = z0 - R + it - RB;
@@ -334,6 +339,7 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
                 buf_store(rs, pact ? o0 : kDropOffset, pbv[0]);
                 buf_store(rs, pact ? o1 : kDropOffset, pbv[1]);
             }
+            if constexpr (!ZSTORE) return;
             const int ozc = clampi(oz, 0, nz - 1);
             const unsigned a0 = zact ? o0 : kDropOffset, a1 = zact ? o1 : kDropOffset;
             const auto rd = plane_rsrc(dst + (size_t)ozc * nxy, plane_bytes);
@@ -355,8 +361,10 @@ __global__ void __launch_bounds__(blur_threads(TY)) blur_level_kernel(const Fuse
             const auto rsub = plane_rsrc(subbase + (size_t)(ozc >> 1) * sub_plane, sub_bytes);
             buf_store(rsub, sact ? so : kDropOffset, (subacc + s4) * 0.125f);
             if (zact && (oz & 1) == 0) subacc = s4;
-        });
-    }
+    };
+    static_for<0, LR>([&](auto pc) { step(pc, 0, std::true_type{}); });
+    for (int base = LR; base < nplanes; base += LR)
+        static_for<0, LR>([&](auto pc) { step(pc, base, std::false_type{}); });
 }
 
 

@@ -361,6 +361,13 @@ struct sift3d_plan {
     std::vector<s3d::DCJob> cjobs;
     // device tables (one allocation, owned by the plan)
     void *d_tables;
+    // autotuned fused launches: schedule step -> (tile height, slabs per job)
+    std::vector<std::pair<int, int>> fused_tune;       // (0, 0): default rule
+    struct TuneRecord {
+        int step, def_ty, def_slabs, ty, slabs, candidates;
+        float def_ms, ms;
+    };
+    std::vector<TuneRecord> tuning;
     s3d::DUnit *d_units;
     s3d::DVol *d_vols;
     s3d::DXYJob *d_xy;

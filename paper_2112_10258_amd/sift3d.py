@@ -135,6 +135,9 @@ def _load():
         "sift3d_build_pyramid": (i, [_vp, _vp, _vp, sz, _vp]),
         "sift3d_detect": (i, [_vp, _vp, sz, _vp, i, _vp, _vp]),
         "sift3d_detect_static": (i, [_vp, _vp, sz, _vp, i, _vp, _vp]),
+        "sift3d_plan_tune": (i, [_vp, _vp, _vp, sz, i, _vp]),
+        "sift3d_plan_tuning_count": (i, [_vp, P(i)]),
+        "sift3d_plan_tuning": (i, [_vp, i, P(i), P(ctypes.c_float)]),
         "sift3d_plan_detect_scratch": (i, [_vp, P(sz)]),
         "sift3d_describe": (i, [_vp, _vp, sz, _vp, _vp, i, _vp, _vp, _vp, _vp]),
         "sift3d_orient": (i, [_vp, _vp, sz, _vp, _vp, i, ctypes.c_double, _vp, _vp, _vp, _vp]),
@@ -417,6 +420,26 @@ class Plan:
     def detect(self, ws, kp, count, stream=None):
         _check(_load().sift3d_detect(self.handle, _vp(ws.data_ptr()), ws.numel(), _vp(_ptr(kp)), self.capacity,
                                      _vp(count.data_ptr()), _vp(_stream(stream))), "sift3d_detect")
+
+    def tune(self, vol, ws, reps=3, stream=None):
+        """sift3d_plan_tune: time tile height and slab candidates of every fused
+        launch and keep the fastest (plan-time, synchronises). Returns the records."""
+        _check(_load().sift3d_plan_tune(self.handle, _vp(_ptr(vol)), _vp(ws.data_ptr()), ws.numel(), int(reps),
+                                        _vp(_stream(stream))), "sift3d_plan_tune")
+        return self.tuning()
+
+    def tuning(self):
+        lib = _load()
+        n = ctypes.c_int()
+        _check(lib.sift3d_plan_tuning_count(self.handle, ctypes.byref(n)), "sift3d_plan_tuning_count")
+        out = []
+        for i in range(n.value):
+            info = (ctypes.c_int * 6)()
+            ms = (ctypes.c_float * 2)()
+            _check(lib.sift3d_plan_tuning(self.handle, i, info, ms), "sift3d_plan_tuning")
+            out.append({"step": info[0], "default": {"ty": info[1], "slabs": info[2], "ms": round(ms[0], 5)},
+                        "tuned": {"ty": info[3], "slabs": info[4], "ms": round(ms[1], 5)}, "candidates": info[5]})
+        return out
 
     def detect_static(self, ws, kp, count, stream=None):
         """sift3d_detect with the library's static scratch (allocates nothing)."""
