@@ -93,14 +93,20 @@ def summarize_pmc(fetch_dir, write_dir, workload, out_path):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of two rocprofv3 --pmc runs
     of this script (--copy-calibration --pmc-steps N) -> bytes per octave-0
     level launch G_1..G_5, scaled by what the same counters read for a 1 GiB
-    device copy. The octave-0 launch of radius R is the blur_level_kernel<R,
-    true, ...> dispatch with the largest grid (default parameters: radii 4, 5,
-    6, 8, 10; on 512x512x384 every octave-0 level runs on the fused pass)."""
+    device copy. The octave-0 launches of radius R are the blur_level_kernel<R,
+    true, ...> dispatches (after the last calibration copy) whose count is
+    within half of the largest (default parameters: radii 4, 5, 6, 8, 10; on
+    512x512x384 every octave-0 level runs on the fused pass)."""
     import csv
     import glob
     import re
 
+    def is_copy(k, v):
+        return ("copy" in k.lower() or "elementwise" in k.lower()) and v * 1024 > COPY_BYTES / 2
+
     def rows(d, counter):
+        """(kernel, grid, KiB) of the dispatches after the last calibration
+        copy (which runs after the plan is tuned), and the copies' KiB."""
         fs = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
         if not fs:
             raise SystemExit(f"no counter_collection.csv under {d}")
@@ -110,18 +116,19 @@ def summarize_pmc(fetch_dir, write_dir, workload, out_path):
                 if r.get("Counter_Name") == counter:
                     name = (r["Kernel_Name"].replace("void ", "").replace("s3d::(anonymous namespace)::", "")
                             .replace("s3d::fused::", ""))
-                    out.append((name, int(r["Grid_Size"]), float(r["Counter_Value"])))
-        return out
-
-    fr, wr = rows(fetch_dir, "FETCH_SIZE"), rows(write_dir, "WRITE_SIZE")
-
-    def copy_kib(rs):
-        c = [v for k, g, v in rs if ("copy" in k.lower() or "elementwise" in k.lower()) and v * 1024 > COPY_BYTES / 2]
-        if not c:
+                    out.append((int(r["Dispatch_Id"]), name, int(r["Grid_Size"]), float(r["Counter_Value"])))
+        out.sort()
+        copies = [i for i, (_, k, _, v) in enumerate(out) if is_copy(k, v)]
+        if not copies:
             raise SystemExit("copy calibration dispatch not found")
+        return [(k, g, v) for _, k, g, v in out[copies[-1] + 1:]], [out[i][3] for i in copies]
+
+    (fr, fc), (wr, wc) = rows(fetch_dir, "FETCH_SIZE"), rows(write_dir, "WRITE_SIZE")
+
+    def copy_kib(c):
         return float(np.median(c))
 
-    cf, cw = copy_kib(fr), copy_kib(wr)
+    cf, cw = copy_kib(fc), copy_kib(wc)
     f_factor, w_factor = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
     calib = {"bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
              "fetch_factor": round(f_factor, 4), "write_factor": round(w_factor, 4)}
@@ -138,11 +145,13 @@ def summarize_pmc(fetch_dir, write_dir, workload, out_path):
     fused_re = re.compile(r"^blur_level_kernel<(\d+), true")
 
     def octave0(rs, R):
-        ds = [(g, v) for k, g, v in rs if (m := fused_re.match(k)) and int(m.group(1)) == R]
+        # octave 0 moves 8x the bytes of octave 1 (whose launch can have as
+        # many blocks): keep the dispatches within half of the largest count
+        ds = [v for k, g, v in rs if (m := fused_re.match(k)) and int(m.group(1)) == R]
         if not ds:
             return []
-        gmax = max(g for g, _ in ds)
-        return [v for g, v in ds if g == gmax]
+        vmax = max(ds)
+        return [v for v in ds if v >= 0.5 * vmax]
 
     levels = []
     for i, R in enumerate((4, 5, 6, 8, 10), start=1):
@@ -202,7 +211,7 @@ def launch_roofline(steps_info, launch_ms, workload):
     }
 
 
-def measure_plain(name, steps, warmup, kw, stream, stage_reps=10, vol=None, tune=False):
+def measure_plain(name, steps, warmup, kw, stream, stage_reps=10, vol=None, tune=False, after_tune=None):
     """K timed whole extractions of one volume resident in HBM (instrumented
     steps), then a separate stage breakdown. With tune, the plan is first
     autotuned on this device (sift3d_plan_tune: tile height and slabs of its
@@ -225,6 +234,8 @@ def measure_plain(name, steps, warmup, kw, stream, stage_reps=10, vol=None, tune
         t0 = time.perf_counter()
         tuning = plan.tune(dvol, buf.ws, reps=3, stream=stream)
         log(f"[bench] {name}: plan tuned in {time.perf_counter() - t0:.2f} s ({len(tuning)} fused launches)")
+    if after_tune is not None:
+        after_tune()
     steps_info = plan.pyramid_steps()
     nl = len(steps_info)
 
@@ -588,7 +599,8 @@ def main():
 
     import paper_2112_10258_amd as S
 
-    if args.copy_calibration:
+    def copy_calibration():
+        """1 GiB device copies: the reference dispatch for the counter runs."""
         a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(3):
@@ -603,9 +615,11 @@ def main():
     stream = torch.cuda.current_stream()
     log(f"[bench] workload {args.workload}: {desc}")
     if args.pmc_steps:
+        # the copies run after the plan is tuned, so the counter summary
+        # reads only the dispatches of the plan as it is timed
         _, (ctx, plan, buf, dvol, _) = measure_plain(args.workload, args.pmc_steps, args.warmup, kw, stream,
-                                                     tune=not args.no_tune,
-                                                     stage_reps=1)
+                                                     tune=not args.no_tune, stage_reps=1,
+                                                     after_tune=copy_calibration if args.copy_calibration else None)
         log(f"[bench] {args.pmc_steps} plain steps for the counters")
         return
     untuned, keep = measure_plain(args.workload, args.steps, args.warmup, kw, stream)
