@@ -28,6 +28,17 @@ Recipes (all draws from numpy Generator(PCG64(seed))):
 * ``pair_draws``: the standard-normal draws that the BRIEF/RRIEF point-pair
   selection consumes, shape (n, 2, 3) float64. How they are turned into
   point offsets is part of the method and is done by each side.
+* ``similarity_copy``: a volume resampled under a known similarity
+  transform T(x) = s R x + t (input voxel coordinates, x = (x, y, z)),
+  B(y) = A(T^-1(y)) by scipy's cubic-spline affine_transform (outside A:
+  0), optionally with fresh N(0, noise^2) noise. R comes from scipy's
+  Rotation.from_rotvec(axis * angle); t keeps A's centre at B's centre.
+  The stand-in for the paper's pairs of brain volumes: the true
+  correspondences are known.
+* ``hough_scene``: oriented keypoint geometry rows (x, y, z, sigma, R[9])
+  for two point sets, the first n_true of A mapped into B by a planted
+  similarity with small position, scale and frame noise, the rest random;
+  frames from scipy's Rotation.random.
 """
 from __future__ import annotations
 
@@ -43,6 +54,8 @@ __all__ = [
     "config3",
     "config4",
     "config5_requests",
+    "similarity_copy",
+    "hough_scene",
     "PAIR_SEED",
 ]
 
@@ -193,3 +206,71 @@ def config5_requests(n: int = 2000, rate: float = 200.0, seed: int = 5000):
     t = np.cumsum(gaps) - gaps[0]
     idx = rng.choice(len(CONFIG5_SIZES), size=n, p=CONFIG5_PROBS)
     return [(float(t[i]), CONFIG5_SIZES[int(idx[i])], seed + i) for i in range(n)]
+
+
+# --- pairs with known correspondences -------------------------------------
+
+def _rotation(axis, angle):
+    from scipy.spatial.transform import Rotation
+    a = np.asarray(axis, dtype=np.float64)
+    return Rotation.from_rotvec(a / np.linalg.norm(a) * float(angle)).as_matrix()
+
+
+def similarity_copy(vol: np.ndarray, scale: float = 1.0, axis=(0.3, -0.5, 0.8), angle_deg: float = 20.0,
+                    noise: float = 0.0, seed: int = 7):
+    """(vol_b, s, R, t): vol resampled under T(x) = s R x + t (recipe in the
+    module doc). Shape unchanged; t = c - s R c with c the volume centre."""
+    nz, ny, nx = vol.shape
+    R = _rotation(axis, np.deg2rad(angle_deg))
+    s = float(scale)
+    c = np.array([(nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0])
+    t = c - s * (R @ c)
+    # output index o (z, y, x) reads input T^-1: x_a = R^T (x_b - t) / s
+    P = np.array([[0, 0, 1], [0, 1, 0], [1, 0, 0]], dtype=np.float64)
+    M = P @ (R.T / s) @ P
+    off = P @ (-(R.T @ t) / s)
+    out = ndi.affine_transform(vol.astype(np.float64), M, offset=off, order=3, mode="constant", cval=0.0)
+    if noise > 0.0:
+        out = out + _rng(seed).normal(0.0, noise, out.shape)
+    return np.ascontiguousarray(out.astype(np.float32)), s, R, t
+
+
+def hough_scene(n_true: int, n_false: int, seed: int, scale: float = 1.3, axis=(1.0, 2.0, -0.5),
+                angle_deg: float = 35.0, shift=(12.0, -7.0, 5.0), extent=(145.0, 174.0, 145.0),
+                pos_noise: float = 0.3, frame_noise_deg: float = 3.0):
+    """Synthetic matched geometry for the Hough vote.
+
+    Returns (geo_a [n][13] float32, geo_b [n][13] float32, match [n] int32,
+    truth dict(s, R, t)). Row i of A matches row match[i] of B (a random
+    permutation). A's positions are uniform in the extent, sigma is
+    1.6 * 2^U[0, 3], frames are random rotations. For i < n_true the B row
+    is (s R x + t + N(0, pos_noise^2) per axis, s sigma, R_noise R R_a) with
+    R_noise a rotation of N(0, frame_noise_deg^2) degrees about a random
+    axis; the other B rows are independent random keypoints.
+    """
+    from scipy.spatial.transform import Rotation
+    rng = _rng(seed)
+    n = int(n_true) + int(n_false)
+    R = _rotation(axis, np.deg2rad(angle_deg))
+    s = float(scale)
+    ext = np.asarray(extent, dtype=np.float64)
+    xa = rng.random((n, 3)) * ext
+    sa = 1.6 * 2.0 ** rng.uniform(0.0, 3.0, n)
+    Ra = Rotation.random(n, random_state=rng).as_matrix()
+    c = (ext - 1.0) / 2.0
+    t = c - s * (R @ c) + np.asarray(shift, dtype=np.float64)
+    xb = rng.random((n, 3)) * ext
+    sb = 1.6 * 2.0 ** rng.uniform(0.0, 3.0, n)
+    Rb = Rotation.random(n, random_state=rng).as_matrix()
+    for i in range(int(n_true)):
+        ax = rng.standard_normal(3)
+        Rn = _rotation(ax, np.deg2rad(frame_noise_deg * rng.standard_normal()))
+        xb[i] = s * (R @ xa[i]) + t + rng.normal(0.0, pos_noise, 3)
+        sb[i] = s * sa[i]
+        Rb[i] = Rn @ R @ Ra[i]
+    perm = rng.permutation(n)          # B row of pair i is perm[i]
+    geo_a = np.zeros((n, 13), dtype=np.float32)
+    geo_b = np.zeros((n, 13), dtype=np.float32)
+    geo_a[:, :3], geo_a[:, 3], geo_a[:, 4:] = xa, sa, Ra.reshape(n, 9)
+    geo_b[perm, :3], geo_b[perm, 3], geo_b[perm, 4:] = xb, sb, Rb.reshape(n, 9)
+    return geo_a, geo_b, perm.astype(np.int32), {"s": s, "R": R, "t": t}

@@ -575,3 +575,8 @@ def extract(vol: np.ndarray, p: Params, draws: np.ndarray):
     kps = detect([oc.D for oc in octs], p)
     desc = describe([oc.G for oc in octs], kps, draws, p)
     return octs, kps, desc
+
+
+# ------------------------------------------- matching: normalisation, Hough
+from .hough import (HoughParams, geometry, hough, hough_default_params, hypothesis, pack_key,  # noqa: E402
+                    rotation_vector, similarity_fit, unit_normalize, unpack_key)
