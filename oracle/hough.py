@@ -170,8 +170,9 @@ def hypothesis(ga: np.ndarray, gb: np.ndarray, hp: HoughParams):
       neighbouring bin on the nearer side, b + 1 if q - b >= 0.5 else b - 1;
       lo = min of the two. The match votes for the 2^7 bins lo + {0, 1}^7.
 
-    Inputs are geometry rows (float32, taken exactly). Returns (lo [7] int,
-    s, R, margin): margin is the smallest distance, in bin units, of any q
+    Inputs are geometry rows (float32, taken exactly; both sigmas > 0).
+    Returns (lo [7] int, or None if a coordinate is not finite, s, R,
+    margin): margin is the smallest distance, in bin units, of any q
     to a multiple of 1/2 (where floor or the side would change), or of the
     rotation-vector branch decision."""
     ga = np.asarray(ga, dtype=np.float64)
@@ -185,6 +186,8 @@ def hypothesis(ga: np.ndarray, gb: np.ndarray, hp: HoughParams):
     v = np.concatenate([[math.log2(s)], w, p])
     width = np.array([hp.scale_bin] + [hp.angle_bin] * 3 + [hp.trans_bin] * 3)
     lo = np.zeros(N_DIMS, dtype=np.int64)
+    if not np.all(np.isfinite(v)):
+        return None, s, R, mg
     for d in range(N_DIMS):
         q = v[d] / width[d]
         b = math.floor(q)
@@ -218,10 +221,13 @@ def hough(geo_a: np.ndarray, geo_b: np.ndarray, match: np.ndarray, hp: HoughPara
     inliers (Section 3.3; reading R26).
 
     geo_a [n_a][13], geo_b [n_b][13]: geometry rows; match [n_a]: index of
-    A row i's match in B, or -1 (rows outside [0, n_b) do not vote).
+    A row i's match in B, or -1. A match is valid when its index is in
+    [0, n_b) and both rows have sigma > 0; only valid matches vote and can
+    be inliers.
 
       1. every valid match votes once for each of its 2^7 bins (hypothesis);
-         a match with a coordinate outside -256 .. 254 does not vote;
+         a match with a bin coordinate outside -256 .. 254 (or a vote
+         coordinate that is not finite) does not vote;
       2. the winning bin has the most votes; among equal counts, the
          smallest packed key (pack_key);
       3. the fit set is the matches voting for the winning bin;
@@ -241,7 +247,10 @@ def hough(geo_a: np.ndarray, geo_b: np.ndarray, match: np.ndarray, hp: HoughPara
     gb = np.asarray(geo_b, dtype=np.float32)
     match = np.asarray(match, dtype=np.int64)
     n_a, n_b = len(ga), len(gb)
+    # a match counts when its index is in range and both scales are positive
     valid = (match >= 0) & (match < n_b)
+    for i in np.nonzero(valid)[0]:
+        valid[i] = bool(ga[i, 3] > 0.0) and bool(gb[match[i], 3] > 0.0)
     lo = np.full((n_a, N_DIMS), -1, dtype=np.int64)
     voted = np.zeros(n_a, dtype=bool)
     margin = np.full(n_a, np.inf)
@@ -251,7 +260,7 @@ def hough(geo_a: np.ndarray, geo_b: np.ndarray, match: np.ndarray, hp: HoughPara
             continue
         l, _, _, mg = hypothesis(ga[i], gb[match[i]], hp)
         margin[i] = mg
-        if np.any(l < -FIELD_BIAS) or np.any(l + 1 > (1 << FIELD_BITS) - 1 - FIELD_BIAS):
+        if l is None or np.any(l < -FIELD_BIAS) or np.any(l + 1 > (1 << FIELD_BITS) - 1 - FIELD_BIAS):
             continue
         lo[i], voted[i] = l, True
         for corner in range(1 << N_DIMS):

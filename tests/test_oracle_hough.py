@@ -288,3 +288,14 @@ def test_similarity_copy_moves_a_blob_where_the_transform_says():
     m = w > 0.5 * w.max()
     got = np.array([(x * w)[m].sum(), (y * w)[m].sum(), (z * w)[m].sum()]) / w[m].sum()
     assert np.linalg.norm(got - (s * R @ c + t)) < 0.2
+
+
+def test_hough_ignores_rows_without_a_positive_scale():
+    ga, gb, m, _ = P.hough_scene(30, 0, seed=19)
+    hp = O.hough_default_params((145, 174, 145))
+    ref = O.hough(ga, gb, m, hp)
+    ga2 = np.concatenate([ga, ga[:3]])
+    ga2[30:, 3] = [0.0, -1.0, np.nan]
+    r = O.hough(ga2, gb, np.concatenate([m, m[:3]]), hp)
+    assert not r["voted"][30:].any() and not r["inlier"][30:].any()
+    assert (r["bin"], r["votes"], r["n_inliers"]) == (ref["bin"], ref["votes"], ref["n_inliers"])
