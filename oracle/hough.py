@@ -193,6 +193,11 @@ def hypothesis(ga: np.ndarray, gb: np.ndarray, hp: HoughParams):
         b = math.floor(q)
         nb = b + 1 if q - b >= 0.5 else b - 1
         lo[d] = min(b, nb)
+        # a scale ratio that is a power of two (keypoints of the same level,
+        # or levels whole octaves apart) has an exact log2: its decision is
+        # exact in any implementation, so it sets no margin
+        if d == 0 and math.frexp(s)[0] == 0.5:
+            continue
         mg = min(mg, abs(q - round(2.0 * q) / 2.0))
     return lo, s, R, mg
 
