@@ -30,9 +30,14 @@ __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t rs, unsigned bo
 {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)boff, 0, 0));
 }
+// Stores carry the non-temporal cache policy (aux bit 1): a level written
+// here is read back only by a later launch, after far more than the L2 has
+// streamed through on the volumes where it matters (about 3% off the
+// 512x512x384 pyramid, no change at 145x174x145 or 256^3).
+constexpr int kStoreNonTemporal = 2;
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t rs, unsigned boff, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, (int)boff, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, (int)boff, 0, kStoreNonTemporal);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
