@@ -483,6 +483,112 @@ int sift3d_match(int kind, const void *d_a, int n_a, const void *d_b, int n_b, i
                  int32_t *d_d1, int32_t *d_d2, void *stream);
 
 /*
+ * Unit-length normalisation of descriptors (Section 3.1, step e: descriptors
+ * are scaled to unit length and stored, so that the nearest neighbour under
+ * the Euclidean distance is also the largest scalar product). Row i of d_in
+ * becomes row i of d_out, float32:
+ *   kind SIFT3D_MATCH_BRIEF: rows of row_elems (1..4) uint64 words; entry
+ *     b (b < 64 row_elems, bit b % 64 of word b / 64, least significant
+ *     first) is +1/sqrt(64 row_elems) if the bit is set, else its negative.
+ *     Squared distances of the results are 4 Hamming / (64 row_elems);
+ *   kind SIFT3D_MATCH_RANKS: rows of row_elems (64..256, multiple of 64)
+ *     uint8 ranks r; entry r_j / |r|, computed in double and rounded once;
+ *     an all-zero row stays zero.
+ * d_in [n][row] (4-byte aligned) and d_out [n][64 row_elems or row_elems]
+ * are device memory owned by the caller. Stream-ordered, allocates nothing.
+ * SIFT3D_E_ARG for a bad kind, size or pointer.
+ */
+int sift3d_normalize(int kind, const void *d_in, int n, int row_elems, float *d_out, void *stream);
+
+/*
+ * Matching units of one volume's keypoints: the rows the Hough vote
+ * (sift3d_hough) and the matcher read, listed in keypoint order. K =
+ * min(*d_count, kp_capacity) keypoints of d_kp are read.
+ *   d_nframes != NULL (oriented descriptors, sift3d_orient's outputs): a
+ *     unit per frame f < d_nframes[k] of keypoint k, in (k, f) order; its
+ *     frame is d_frames[k][f] and its descriptor row k * 4 + f of d_desc;
+ *   d_nframes == NULL (upright descriptors): a unit per keypoint, frame the
+ *     identity, descriptor row k of d_desc (d_frames unused).
+ * Unit u gets: d_unit[u] = k * SIFT3D_MAX_ORIENTATIONS + f (f = 0 upright);
+ * d_geo[u][13] float32 = (xf, yf, zf, sigma, R[9]) with R[3 i + j] =
+ * component i of axis j; d_desc_out[u] = a copy of the descriptor row
+ * (desc_row_bytes bytes, a multiple of 4 up to 1024). d_desc and d_desc_out
+ * may both be NULL to skip the copy. *d_n_units = the number of units (at
+ * most kp_capacity * SIFT3D_MAX_ORIENTATIONS, or kp_capacity upright; the
+ * outputs must hold that many rows). Device memory owned by the caller;
+ * stream-ordered, allocates nothing. SIFT3D_E_ARG for a bad size or pointer.
+ */
+int sift3d_units(const sift3d_keypoint *d_kp, const int *d_count, int kp_capacity, const int *d_nframes,
+                 const float *d_frames, const void *d_desc, int desc_row_bytes, int32_t *d_unit, float *d_geo,
+                 void *d_desc_out, int *d_n_units, void *stream);
+
+/*
+ * Global 7-DoF similarity between two volumes by a Hough vote over matched
+ * oriented keypoints, and its inliers (Section 3.3: matches count when they
+ * are inliers to a global rotation + translation + isotropic scale found by
+ * a Hough transform; the vote layout below is this library's reading).
+ *   - A match i (A row i, B row d_match[i]) is valid when 0 <= d_match[i] <
+ *     n_b and both rows have sigma > 0. It implies s = sigma_b / sigma_a,
+ *     R = R_b R_a^T and p = x_b + s R (c - x_a), the image of A's reference
+ *     point c. Its vote vector (log2 s, rotation vector of R, p) is divided
+ *     by the bin widths (scale_bin, angle_bin x3, trans_bin x3); per
+ *     coordinate q the bin floor(q) and its neighbour on the nearer side
+ *     (+1 if q - floor(q) >= 1/2, else -1) are taken, and the match votes
+ *     once for each of the 2^7 bins so formed. A bin key packs coordinate d
+ *     (0 scale, 1..3 rotation, 4..6 p) as (c_d + 256) in bits 9d..9d+8; a
+ *     match whose bins leave -256..255 (or whose vote is not finite) does
+ *     not vote. The rotation vector is theta a with cos theta =
+ *     clamp((tr R - 1)/2, -1, 1): from the antisymmetric part of R when cos
+ *     theta >= -0.99, else from its symmetric part (the column of the
+ *     largest diagonal of (R + R^T)/2 - cos theta I, signed to agree with
+ *     the antisymmetric part).
+ *   - The winning bin has the most votes; ties go to the smallest key.
+ *   - Fit set: the matches voting for it. Each of `iterations` rounds, if
+ *     the fit set has >= 3 matches, fits the least-squares similarity
+ *     x_b ~ s R x_a + t of their positions (Horn's quaternion form) and
+ *     marks as inliers the valid matches with |s R x_a + t - x_b| <=
+ *     inlier_sigmas * sigma_b and |log2(s sigma_a / sigma_b)| <=
+ *     inlier_log2s; they are the next round's fit set. Fewer than 3 stops
+ *     the rounds (in the first: no transform, status 0).
+ * d_geo_a [n_a][13], d_geo_b [n_b][13]: rows as sift3d_units writes them;
+ * d_match [n_a] int32 (e.g. sift3d_match's d_idx). Arithmetic in double.
+ * Outputs: *d_out (device memory) and d_inlier [n_a] uint8 (1 = inlier).
+ * d_ws: workspace of sift3d_hough_workspace(n_a) bytes. Vote counts are
+ * order-independent integers and every sum has a fixed order, so results
+ * are reproducible. 0 <= n_a <= 2^21, n_b >= 0, widths > 0, inlier limits
+ * >= 0, 1 <= iterations <= 16, else SIFT3D_E_ARG; SIFT3D_E_WORKSPACE for a
+ * short workspace. Stream-ordered, allocates nothing.
+ */
+typedef struct sift3d_hough_params {
+    double scale_bin;      /* [1.0] log2(scale) bin width                        */
+    double angle_bin;      /* [pi/6] rotation-vector component bin width, rad    */
+    double trans_bin;      /* [max(nx,ny,nz)/4] bin width of p, input voxels      */
+    double centre[3];      /* [((nx-1)/2, (ny-1)/2, (nz-1)/2)] reference point c  */
+    double inlier_sigmas;  /* [2.0] position tolerance in units of sigma_b       */
+    double inlier_log2s;   /* [0.5] scale-ratio tolerance, log2 units             */
+    int iterations;        /* [2] fit / inlier rounds                            */
+} sift3d_hough_params;
+
+typedef struct sift3d_similarity {
+    int32_t status;        /* 1 = transform found, 0 = none                      */
+    int32_t votes;         /* votes of the winning bin (0: no valid vote)        */
+    int64_t bin;           /* packed key of the winning bin, -1 if none          */
+    int32_t n_fit;         /* matches in the last fit                            */
+    int32_t n_inliers;
+    double scale;          /* x_b = scale * rot * x_a + trans                    */
+    double rot[9];         /* row-major                                          */
+    double trans[3];
+} sift3d_similarity;
+
+/* Defaults above for a volume A of dims (nx, ny, nz). Host only. */
+int sift3d_hough_default_params(int nx, int ny, int nz, sift3d_hough_params *hp);
+/* Workspace bytes sift3d_hough needs for n_a matches. Host only. */
+int sift3d_hough_workspace(int n_a, size_t *bytes);
+int sift3d_hough(const float *d_geo_a, int n_a, const float *d_geo_b, int n_b, const int32_t *d_match,
+                 const sift3d_hough_params *hp, void *d_ws, size_t ws_bytes, sift3d_similarity *d_out,
+                 uint8_t *d_inlier, void *stream);
+
+/*
  * Uniform-filter approximation of a Gaussian blur (Related Work: the
  * Gaussian scale space can also be generated with separable uniform 1D
  * filters). Along x, then y, then z, `passes` uniform passes of width

@@ -13,6 +13,7 @@ from .sift3d import (  # noqa: F401
     MATCH_RANKS,
     Buffers,
     Context,
+    HoughParams,
     Params,
     Plan,
     Server,
@@ -23,6 +24,12 @@ from .sift3d import (  # noqa: F401
     pair_offsets,
     exported_symbols,
     fetch_results,
+    hough,
+    hough_default_params,
+    hough_workspace_bytes,
     match,
+    normalize,
     run_extract,
+    similarity_dict,
+    units,
 )

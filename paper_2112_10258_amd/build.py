@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsift3d.so")
-SOURCES = ["pyramid.hip", "pyramid_tall.hip", "separable.hip", "compact.hip", "match.hip", "box.hip", "detect.hip", "describe.hip", "orient.hip", "api.cpp", "server.cpp"]
+SOURCES = ["pyramid.hip", "pyramid_tall.hip", "separable.hip", "compact.hip", "match.hip", "box.hip", "detect.hip", "describe.hip", "orient.hip", "hough.hip", "api.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

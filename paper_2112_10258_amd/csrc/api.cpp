@@ -1511,6 +1511,151 @@ int sift3d_match(int kind, const void *d_a, int n_a, const void *d_b, int n_b, i
     return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
 }
 
+int sift3d_normalize(int kind, const void *d_in, int n, int row_elems, float *d_out, void *stream)
+{
+    if (n < 0) return SIFT3D_E_ARG;
+    size_t align;
+    if (kind == SIFT3D_MATCH_BRIEF) {
+        if (row_elems < 1 || row_elems > kMaxPairs / 64) return SIFT3D_E_ARG;
+        align = 8;
+    } else if (kind == SIFT3D_MATCH_RANKS) {
+        if (row_elems < 64 || row_elems > kMaxPairs || row_elems % 64 != 0) return SIFT3D_E_ARG;
+        align = 4;
+    } else {
+        return SIFT3D_E_ARG;
+    }
+    if (n == 0) return SIFT3D_OK;
+    if (d_in == nullptr || d_out == nullptr) return SIFT3D_E_ARG;
+    if (reinterpret_cast<uintptr_t>(d_in) % align != 0 || reinterpret_cast<uintptr_t>(d_out) % 4 != 0)
+        return SIFT3D_E_ARG;
+    const hipError_t e = launch_normalize(kind, d_in, n, row_elems, d_out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
+}
+
+int sift3d_units(const sift3d_keypoint *d_kp, const int *d_count, int kp_capacity, const int *d_nframes,
+                 const float *d_frames, const void *d_desc, int desc_row_bytes, int32_t *d_unit, float *d_geo,
+                 void *d_desc_out, int *d_n_units, void *stream)
+{
+    if (d_kp == nullptr || d_count == nullptr || d_unit == nullptr || d_geo == nullptr || d_n_units == nullptr)
+        return SIFT3D_E_ARG;
+    if (kp_capacity < 0 || kp_capacity > (1 << 26)) return SIFT3D_E_ARG;
+    if (d_nframes != nullptr && d_frames == nullptr) return SIFT3D_E_ARG;
+    if ((d_desc == nullptr) != (d_desc_out == nullptr)) return SIFT3D_E_ARG;
+    if (d_desc != nullptr) {
+        if (desc_row_bytes < 4 || desc_row_bytes > 1024 || desc_row_bytes % 4 != 0) return SIFT3D_E_ARG;
+        if (reinterpret_cast<uintptr_t>(d_desc) % 4 != 0 || reinterpret_cast<uintptr_t>(d_desc_out) % 4 != 0)
+            return SIFT3D_E_ARG;
+    }
+    UnitsArgs a{};
+    a.kp = d_kp;
+    a.count = d_count;
+    a.cap = kp_capacity;
+    a.nframes = d_nframes;
+    a.frames = d_frames;
+    a.desc = static_cast<const uint8_t *>(d_desc);
+    a.row_bytes = desc_row_bytes;
+    a.unit = d_unit;
+    a.geo = d_geo;
+    a.desc_out = static_cast<uint8_t *>(d_desc_out);
+    a.n_units = d_n_units;
+    const hipError_t e = launch_units(a, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
+}
+
+int sift3d_hough_default_params(int nx, int ny, int nz, sift3d_hough_params *hp)
+{
+    if (hp == nullptr || nx < 1 || ny < 1 || nz < 1) return SIFT3D_E_ARG;
+    hp->scale_bin = 1.0;
+    hp->angle_bin = M_PI / 6.0;
+    hp->trans_bin = 0.25 * std::max(nx, std::max(ny, nz));
+    hp->centre[0] = (nx - 1) / 2.0;
+    hp->centre[1] = (ny - 1) / 2.0;
+    hp->centre[2] = (nz - 1) / 2.0;
+    hp->inlier_sigmas = 2.0;
+    hp->inlier_log2s = 0.5;
+    hp->iterations = 2;
+    return SIFT3D_OK;
+}
+
+namespace {
+constexpr int kHoughMaxMatches = 1 << 21;
+
+// Workspace of the Hough vote: table keys, table counts, per-match low
+// corners, the two winner scalars; each part 256-byte aligned.
+struct HoughLayout {
+    size_t keys, counts, lo, best, total;
+    int log2_slots;
+};
+
+HoughLayout hough_layout(int n_a)
+{
+    HoughLayout L{};
+    L.log2_slots = hough_log2_slots(n_a);
+    const size_t slots = (size_t)1 << L.log2_slots;
+    L.keys = 0;
+    L.counts = align256(L.keys + slots * sizeof(unsigned long long));
+    L.lo = align256(L.counts + slots * sizeof(unsigned));
+    L.best = align256(L.lo + (size_t)std::max(n_a, 1) * sizeof(unsigned long long));
+    L.total = align256(L.best + 16);
+    return L;
+}
+
+bool finite_positive(double v) { return std::isfinite(v) && v > 0.0; }
+}  // namespace
+
+int sift3d_hough_workspace(int n_a, size_t *bytes)
+{
+    if (bytes == nullptr || n_a < 0 || n_a > kHoughMaxMatches) return SIFT3D_E_ARG;
+    *bytes = hough_layout(n_a).total;
+    return SIFT3D_OK;
+}
+
+int sift3d_hough(const float *d_geo_a, int n_a, const float *d_geo_b, int n_b, const int32_t *d_match,
+                 const sift3d_hough_params *hp, void *d_ws, size_t ws_bytes, sift3d_similarity *d_out,
+                 uint8_t *d_inlier, void *stream)
+{
+    if (hp == nullptr || d_out == nullptr || d_ws == nullptr) return SIFT3D_E_ARG;
+    if (n_a < 0 || n_a > kHoughMaxMatches || n_b < 0) return SIFT3D_E_ARG;
+    if (n_a > 0 && (d_geo_a == nullptr || d_match == nullptr || d_inlier == nullptr)) return SIFT3D_E_ARG;
+    if (n_b > 0 && d_geo_b == nullptr) return SIFT3D_E_ARG;
+    if (!finite_positive(hp->scale_bin) || !finite_positive(hp->angle_bin) || !finite_positive(hp->trans_bin))
+        return SIFT3D_E_ARG;
+    if (!(hp->inlier_sigmas >= 0.0) || !(hp->inlier_log2s >= 0.0) || !std::isfinite(hp->inlier_sigmas) ||
+        !std::isfinite(hp->inlier_log2s))
+        return SIFT3D_E_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(hp->centre[k])) return SIFT3D_E_ARG;
+    if (hp->iterations < 1 || hp->iterations > 16) return SIFT3D_E_ARG;
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0 || reinterpret_cast<uintptr_t>(d_out) % 8 != 0)
+        return SIFT3D_E_ARG;
+    const HoughLayout L = hough_layout(n_a);
+    if (ws_bytes < L.total) return SIFT3D_E_WORKSPACE;
+    char *ws = static_cast<char *>(d_ws);
+    HoughArgs a{};
+    a.geo_a = d_geo_a;
+    a.geo_b = d_geo_b;
+    a.match = d_match;
+    a.n_a = n_a;
+    a.n_b = n_b;
+    a.width[0] = hp->scale_bin;
+    for (int k = 1; k < 4; ++k) a.width[k] = hp->angle_bin;
+    for (int k = 4; k < 7; ++k) a.width[k] = hp->trans_bin;
+    for (int k = 0; k < 3; ++k) a.centre[k] = hp->centre[k];
+    a.inl_sig = hp->inlier_sigmas;
+    a.inl_log2s = hp->inlier_log2s;
+    a.iterations = hp->iterations;
+    a.keys = reinterpret_cast<unsigned long long *>(ws + L.keys);
+    a.counts = reinterpret_cast<unsigned *>(ws + L.counts);
+    a.log2_slots = L.log2_slots;
+    a.lo = reinterpret_cast<unsigned long long *>(ws + L.lo);
+    a.best_count = reinterpret_cast<unsigned *>(ws + L.best);
+    a.best_key = reinterpret_cast<unsigned long long *>(ws + L.best + 8);
+    a.out = d_out;
+    a.inlier = d_inlier;
+    const hipError_t e = launch_hough(a, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SIFT3D_OK : hip_fail(e);
+}
+
 int sift3d_box_blur(const float *d_in, float *d_out, float *d_tmp, int nx, int ny, int nz, int half_width,
                     int passes, void *stream)
 {

@@ -268,6 +268,40 @@ struct OrientLaunch {
 
 // ---------------------------------------------------------------- host plan
 
+// Matching units of one volume (sift3d_units).
+struct UnitsArgs {
+    const sift3d_keypoint *kp;
+    const int *count;
+    int cap;
+    const int *nframes;     // NULL: upright, one unit per keypoint
+    const float *frames;    // [cap][kMaxOrient][9]
+    const uint8_t *desc;    // rows of row_bytes (NULL: no copy)
+    int row_bytes;
+    int32_t *unit;
+    float *geo;             // [units][13]
+    uint8_t *desc_out;
+    int *n_units;
+};
+
+// The 7-DoF similarity Hough vote (sift3d_hough).
+struct HoughArgs {
+    const float *geo_a, *geo_b;        // [n][13]: x, y, z, sigma, R[9]
+    const int32_t *match;
+    int n_a, n_b;
+    double width[7];                   // bin widths: log2 s, rotation vector x3, centre image x3
+    double centre[3];
+    double inl_sig, inl_log2s;
+    int iterations;
+    unsigned long long *keys;          // hash table [2^log2_slots]
+    unsigned *counts;
+    int log2_slots;
+    unsigned long long *lo;            // [n_a] low corner of each match's bins (all ones: no vote)
+    unsigned *best_count;
+    unsigned long long *best_key;
+    sift3d_similarity *out;
+    uint8_t *inlier;                   // [n_a]
+};
+
 struct OctaveGeom {
     int nx, ny, nz;
     size_t n;             // voxels
@@ -387,6 +421,10 @@ hipError_t launch_blur_compact(const CompactLaunch &a, int max_r, hipStream_t st
 hipError_t launch_detect(const DetLaunch &a, hipStream_t st);
 hipError_t launch_describe(const DescLaunch &a, long long kp_slots, int n_cu, hipStream_t st);
 hipError_t launch_orient(const OrientLaunch &a, long long kp_slots, int n_cu, hipStream_t st);
+hipError_t launch_normalize(int kind, const void *in, int n, int row_elems, float *out, hipStream_t st);
+hipError_t launch_units(const UnitsArgs &a, hipStream_t st);
+int hough_log2_slots(int n_a);   // hash-table size: 2^l >= 2 * 2^7 * n_a, l >= 8
+hipError_t launch_hough(const HoughArgs &a, hipStream_t st);
 
 // Workspace levels of an octave, in units of one padded level.
 inline int lev_G(int i) { return i; }

@@ -91,6 +91,35 @@ class ServerCounters(ctypes.Structure):
     ]
 
 
+class HoughParams(ctypes.Structure):
+    _fields_ = [
+        ("scale_bin", ctypes.c_double),
+        ("angle_bin", ctypes.c_double),
+        ("trans_bin", ctypes.c_double),
+        ("centre", ctypes.c_double * 3),
+        ("inlier_sigmas", ctypes.c_double),
+        ("inlier_log2s", ctypes.c_double),
+        ("iterations", ctypes.c_int),
+    ]
+
+
+class Similarity(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("votes", ctypes.c_int32),
+        ("bin", ctypes.c_int64),
+        ("n_fit", ctypes.c_int32),
+        ("n_inliers", ctypes.c_int32),
+        ("scale", ctypes.c_double),
+        ("rot", ctypes.c_double * 9),
+        ("trans", ctypes.c_double * 3),
+    ]
+
+
+SIMILARITY_BYTES = 128
+assert ctypes.sizeof(Similarity) == SIMILARITY_BYTES
+
+
 class Sift3dError(RuntimeError):
     def __init__(self, code: int, what: str):
         lib = _load()
@@ -159,6 +188,11 @@ def _load():
         "sift3d_server_clock": (ctypes.c_double, []),
         "sift3d_server_destroy": (i, [_vp]),
         "sift3d_match": (i, [i, _vp, i, _vp, i, i, _vp, _vp, _vp, _vp]),
+        "sift3d_normalize": (i, [i, _vp, i, i, _vp, _vp]),
+        "sift3d_units": (i, [_vp, _vp, i, _vp, _vp, _vp, i, _vp, _vp, _vp, _vp, _vp]),
+        "sift3d_hough_default_params": (i, [i, i, i, P(HoughParams)]),
+        "sift3d_hough_workspace": (i, [i, P(sz)]),
+        "sift3d_hough": (i, [_vp, i, _vp, i, _vp, P(HoughParams), _vp, sz, _vp, _vp, _vp]),
         "sift3d_box_blur": (i, [_vp, _vp, _vp, i, i, i, i, i, _vp]),
         "sift3d_box_half_width": (i, [ctypes.c_double, i, P(i)]),
         "sift3d_error_string": (ctypes.c_char_p, [i]),
@@ -218,6 +252,93 @@ def match(a, b, kind: int, stream=None):
                                 int(a.shape[1]), _vp(idx.data_ptr()), _vp(d1.data_ptr()), _vp(d2.data_ptr()),
                                 _vp(_stream(stream))), "sift3d_match")
     return idx, d1, d2
+
+
+def normalize(desc, kind: int, stream=None):
+    """Unit-length descriptors (sift3d_normalize): [n][words] int64 BRIEF
+    rows (kind MATCH_BRIEF) give [n][64 words] float32 of +-1/sqrt(64 words);
+    [n][m] uint8 rank rows (kind MATCH_RANKS) give [n][m] float32 r/|r|."""
+    import torch
+    assert desc.is_cuda and desc.dim() == 2
+    desc = desc.contiguous()
+    n, w = desc.shape
+    cols = 64 * w if kind == MATCH_BRIEF else w
+    out = torch.empty((n, cols), dtype=torch.float32, device=desc.device)
+    _check(_load().sift3d_normalize(int(kind), _vp(desc.data_ptr() if n else None), n, int(w),
+                                    _vp(out.data_ptr() if n else None), _vp(_stream(stream))), "sift3d_normalize")
+    return out
+
+
+def units(kp, count, capacity: int, nframes=None, frames=None, desc=None, stream=None):
+    """Matching units of one volume (sift3d_units). kp: keypoint rows
+    (uint8 [cap][40] device tensor or any device tensor of that size),
+    count: int32 device tensor whose first element is the keypoint count.
+    nframes/frames: sift3d_orient outputs for oriented units (None: upright,
+    one unit per keypoint with the identity frame). desc: device tensor of
+    descriptor rows ([cap*4][row] oriented, [cap][row] upright) to copy, or
+    None. Returns (unit int32 [n], geo float32 [n][13], desc_out or None),
+    cut to the unit count (read back to the host)."""
+    import torch
+    dev = count.device
+    rows = capacity * (MAX_ORIENTATIONS if nframes is not None else 1)
+    unit = torch.empty(max(rows, 1), dtype=torch.int32, device=dev)
+    geo = torch.empty((max(rows, 1), 13), dtype=torch.float32, device=dev)
+    n = torch.empty(1, dtype=torch.int32, device=dev)
+    dout, rb = None, 0
+    if desc is not None:
+        if not desc.is_contiguous() or rows == 0 or desc.numel() % rows:
+            raise ValueError("units: desc must be contiguous with one row per keypoint (per frame if oriented)")
+        per_row = desc.numel() // rows
+        rb = per_row * desc.element_size()
+        dout = torch.empty((max(rows, 1), per_row), dtype=desc.dtype, device=dev)
+    _check(_load().sift3d_units(_vp(kp.data_ptr()), _vp(count.data_ptr()), int(capacity),
+                                _vp(_ptr(nframes)), _vp(_ptr(frames)), _vp(_ptr(desc)), int(rb),
+                                _vp(unit.data_ptr()), _vp(geo.data_ptr()), _vp(_ptr(dout)), _vp(n.data_ptr()),
+                                _vp(_stream(stream))), "sift3d_units")
+    k = int(n.item())
+    return unit[:k], geo[:k], (dout[:k] if dout is not None else None)
+
+
+def hough_default_params(shape_xyz) -> HoughParams:
+    hp = HoughParams()
+    nx, ny, nz = (int(v) for v in shape_xyz)
+    _check(_load().sift3d_hough_default_params(nx, ny, nz, ctypes.byref(hp)), "sift3d_hough_default_params")
+    return hp
+
+
+def hough_workspace_bytes(n_a: int) -> int:
+    b = ctypes.c_size_t()
+    _check(_load().sift3d_hough_workspace(int(n_a), ctypes.byref(b)), "sift3d_hough_workspace")
+    return b.value
+
+
+def hough(geo_a, geo_b, match_idx, hp: HoughParams, ws=None, stream=None, sync=True):
+    """7-DoF similarity Hough vote and inliers (sift3d_hough). geo_a [n_a][13],
+    geo_b [n_b][13] float32 and match_idx [n_a] int32 device tensors.
+    Returns (result, inlier): result is a dict read from the device (when
+    sync) or the raw uint8 [128] device tensor; inlier is uint8 [n_a]."""
+    import torch
+    dev = match_idx.device
+    n_a, n_b = int(geo_a.shape[0]), int(geo_b.shape[0])
+    if ws is None:
+        ws = torch.empty(hough_workspace_bytes(n_a), dtype=torch.uint8, device=dev)
+    out = torch.zeros(SIMILARITY_BYTES, dtype=torch.uint8, device=dev)
+    inl = torch.empty(max(n_a, 1), dtype=torch.uint8, device=dev)
+    _check(_load().sift3d_hough(_vp(geo_a.data_ptr() if n_a else None), n_a,
+                                _vp(geo_b.data_ptr() if n_b else None), n_b,
+                                _vp(match_idx.data_ptr() if n_a else None), ctypes.byref(hp),
+                                _vp(ws.data_ptr()), ws.numel(), _vp(out.data_ptr()), _vp(inl.data_ptr()),
+                                _vp(_stream(stream))), "sift3d_hough")
+    if not sync:
+        return out, inl[:n_a]
+    return similarity_dict(out), inl[:n_a]
+
+
+def similarity_dict(raw) -> dict:
+    """The sift3d_similarity in a uint8 [128] tensor as a dict of numpy values."""
+    r = Similarity.from_buffer_copy(bytes(raw.cpu().numpy().tobytes()))
+    return {"status": r.status, "votes": r.votes, "bin": r.bin, "n_fit": r.n_fit, "n_inliers": r.n_inliers,
+            "scale": r.scale, "R": np.array(r.rot[:]).reshape(3, 3), "t": np.array(r.trans[:])}
 
 
 def box_half_width(sigma: float, passes: int) -> int:

@@ -1,6 +1,7 @@
 """CPU checks of the C ABI: the library loads, exports every declared entry
 point, and its host-only functions behave (no compute calls)."""
 import ctypes
+import math
 import os
 import re
 
@@ -85,7 +86,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("no C compiler")
     mirrors = {"sift3d_params": S.Params, "sift3d_server_config": S.ServerConfig,
-               "sift3d_result": S.Result, "sift3d_server_counters": S.ServerCounters}
+               "sift3d_result": S.Result, "sift3d_server_counters": S.ServerCounters,
+               "sift3d_hough_params": S.HoughParams, "sift3d_similarity": S.Similarity}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sift3d.h"', "int main(void) {"]
     for cname, py in mirrors.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -158,3 +160,54 @@ def test_box_blur_binding_rejects_host_tensors():
     import paper_2112_10258_amd as S
     with pytest.raises(ValueError):
         S.box_blur(torch.zeros(4, 5, 6), 1, 3)
+
+
+def test_matching_entry_points_validate_on_host():
+    """sift3d_normalize, sift3d_units and sift3d_hough check their
+    arguments before any launch; the Hough defaults and workspace sizes are
+    host computations."""
+    import ctypes
+
+    import paper_2112_10258_amd.sift3d as S
+    lib = S._load()
+    null = None
+    # normalize: n = 0 is a no-op; bad kind, row length or null pointers fail
+    assert lib.sift3d_normalize(1, null, 0, 64, null, null) == 0
+    assert lib.sift3d_normalize(2, null, 1, 64, null, null) == -1
+    assert lib.sift3d_normalize(0, null, 1, 5, null, null) == -1
+    assert lib.sift3d_normalize(1, null, 1, 100, null, null) == -1
+    assert lib.sift3d_normalize(1, null, 1, 64, null, null) == -1
+    assert lib.sift3d_normalize(1, null, -1, 64, null, null) == -1
+    # units: null outputs, negative capacity, frames missing, half a copy
+    fake = ctypes.c_void_p(4096)
+    assert lib.sift3d_units(null, fake, 4, null, null, null, 0, fake, fake, null, fake, null) == -1
+    assert lib.sift3d_units(fake, fake, -1, null, null, null, 0, fake, fake, null, fake, null) == -1
+    assert lib.sift3d_units(fake, fake, 4, fake, null, null, 0, fake, fake, null, fake, null) == -1
+    assert lib.sift3d_units(fake, fake, 4, null, null, fake, 64, fake, fake, null, fake, null) == -1
+    assert lib.sift3d_units(fake, fake, 4, null, null, fake, 6, fake, fake, fake, fake, null) == -1
+    # Hough defaults and workspace
+    hp = S.HoughParams()
+    assert lib.sift3d_hough_default_params(145, 174, 145, ctypes.byref(hp)) == 0
+    assert hp.trans_bin == 43.5 and tuple(hp.centre) == (72.0, 86.5, 72.0) and hp.iterations == 2
+    assert abs(hp.angle_bin - math.pi / 6) < 1e-15 and hp.scale_bin == 1.0
+    assert hp.inlier_sigmas == 2.0 and hp.inlier_log2s == 0.5
+    assert lib.sift3d_hough_default_params(0, 1, 1, ctypes.byref(hp)) == -1
+    b = ctypes.c_size_t()
+    assert lib.sift3d_hough_workspace(1000, ctypes.byref(b)) == 0
+    assert b.value >= 2 * 128 * 1000 * 12 + 8 * 1000
+    assert lib.sift3d_hough_workspace(-1, ctypes.byref(b)) == -1
+    assert lib.sift3d_hough_workspace((1 << 21) + 1, ctypes.byref(b)) == -1
+    ws = ctypes.c_void_p(1 << 20)
+    good = S.HoughParams()
+    lib.sift3d_hough_default_params(64, 64, 64, ctypes.byref(good))
+    for field, bad in (("scale_bin", 0.0), ("angle_bin", -1.0), ("trans_bin", float("nan")),
+                       ("inlier_sigmas", -0.5), ("inlier_log2s", float("inf")), ("iterations", 0),
+                       ("iterations", 17)):
+        hp = S.HoughParams.from_buffer_copy(good)
+        setattr(hp, field, bad)
+        assert lib.sift3d_hough(fake, 4, fake, 4, fake, ctypes.byref(hp), ws, 1 << 30, fake, fake, null) == -1, field
+    # short workspace
+    assert lib.sift3d_hough(fake, 4, fake, 4, fake, ctypes.byref(good), ws, 16, fake, fake, null) == -3
+    # null pointers with work to do
+    assert lib.sift3d_hough(null, 4, fake, 4, fake, ctypes.byref(good), ws, 1 << 30, fake, fake, null) == -1
+    assert lib.sift3d_hough(fake, 4, fake, 4, fake, ctypes.byref(good), null, 1 << 30, fake, fake, null) == -1
