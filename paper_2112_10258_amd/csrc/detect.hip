@@ -271,25 +271,28 @@ __global__ void __launch_bounds__(kScanThreads) detect_scan_kernel(const DetLaun
 // blocks of D_s at z-1 and z+1, and the 8-voxel ring of D_s at z.
 //
 // One wavefront loads 64 consecutive x (lanes 0 and 63 are halo, lanes
-// 1..62 produce) of one y row and streams z through a slab: per plane and
-// level it loads rows y-1, y, y+1 (coalesced), takes x neighbours from the
-// adjacent lanes with DPP whole-wave shifts, and keeps 3x3 max/min of the
-// last three planes in registers. The next plane is loaded before the
-// current one is reduced. No LDS, no barriers. Ballots of the flags are
-// the 64-bit words of the per-row keypoint bit masks (bit l of word t is
-// x = 62 t + l).
+// 1..62 produce) of WY consecutive y rows and streams z through a slab: per
+// plane and level it loads the WY + 2 rows y0-1 .. y0+WY (coalesced), takes
+// x neighbours from the adjacent lanes with DPP whole-wave shifts, reduces
+// each loaded row over x once, and combines three such rows per output row;
+// the 3x3 max/min of the last three planes stay in registers. The next
+// plane is loaded before the current one is reduced. No LDS, no barriers.
+// Ballots of the flags are the 64-bit words of the per-row keypoint bit
+// masks (bit l of word t is x = 62 t + l).
 
-// Rows y-1, y, y+1 of plane pz of every level, as buffer loads: each plane
-// is a buffer resource built in scalar registers (base, size), the per-lane
-// part is a 32-bit byte offset inside the plane (a plane is at most 2^30
-// floats), so a load costs no per-lane address arithmetic (plain global
-// loads made the compiler add a 64-bit per-lane address for every row).
-// Offsets stay inside the plane (clamped rows, clamped x).
+// Rows y0-1 .. y0+WY of plane pz of every level, as buffer loads: each
+// plane is a buffer resource built in scalar registers (base, size), the
+// per-lane part is a 32-bit byte offset inside the plane (a plane is at
+// most 2^30 floats), so a load costs no per-lane address arithmetic (plain
+// global loads made the compiler add a 64-bit per-lane address for every
+// row). Offsets stay inside the plane (clamped rows, clamped x).
 constexpr int kRawBufferWord3 = 0x00020000;   // dword 3 of a raw (untyped) buffer resource on gfx9
+constexpr unsigned kDropOffset = 0x80000000u;  // past any resource here: the store is dropped
+typedef unsigned u32x2 __attribute__((__vector_size__(8)));
 
-template <int NL>
+template <int NL, int NR>
 __device__ __forceinline__ void load_plane_rows(const float *D, long long lstride, long long nxy, int pz,
-                                                const unsigned (&boff)[3], float (&v)[NL][3])
+                                                const unsigned (&boff)[NR], float (&v)[NL][NR])
 {
     const int bytes = (int)(unsigned)min(nxy * 4, 0xffffffffLL);   // bound of the offsets (unsigned)
 #pragma unroll
@@ -298,7 +301,8 @@ __device__ __forceinline__ void load_plane_rows(const float *D, long long lstrid
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(pl), (short)0, bytes, kRawBufferWord3);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) v[l][r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)boff[r], 0, 0));
+        for (int r = 0; r < NR; ++r)
+            v[l][r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)boff[r], 0, 0));
     }
 }
 
@@ -322,6 +326,8 @@ template <int S, bool INL>
 __global__ void __launch_bounds__(256) detect_tile_kernel(const DetLaunch a)
 {
     constexpr int NL = S + 2;
+    constexpr int WY = kDTWY;          // output rows per wavefront
+    constexpr int NR = WY + 2;         // loaded rows per plane and level
     const int u = last_le(a.n_units, [&](int i) { return (long long)unit_at<INL>(a, i).tile_block0; }, blockIdx.x);
     const DUnit &un = unit_at<INL>(a, u);
     const float *D = unit_D(a, un);
@@ -330,83 +336,115 @@ __global__ void __launch_bounds__(256) detect_tile_kernel(const DetLaunch a)
     const int txi = local % un.tiles_x;
     const int rest = local / un.tiles_x;
     const int tyi = rest % un.tiles_y, tzi = rest / un.tiles_y;
-    const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
-    const int nx = un.nx, ny = un.ny, nz = un.nz;
+    // the wavefront index is uniform: keep it (and every row address) scalar
+    const int lane = threadIdx.x & 63, wy = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nx = un.nx, ny = un.ny, nz = un.nz, words = un.words;
     const int xl = txi * kDTXOut + lane;             // this lane's column
-    const int y = 1 + tyi * kDTY + wy, z0 = 1 + tzi * kDTZ;
-    if (y > ny - 2) return;                          // whole wavefront: no row here
+    const int y0 = 1 + tyi * kDTY + wy * WY;         // first output row of this wavefront
+    if (y0 > ny - 2) return;                         // whole wavefront: no row here
+    const int z0 = 1 + tzi * kDTZ;
     const int z1 = min(z0 + kDTZ, nz - 1);           // outputs z0 .. z1-1 (interior)
     const int x = min(xl, nx - 1);
     const bool in_x = lane >= 1 && lane <= kDTXOut && xl <= nx - 2;
+    const float thr = a.thr;
 
-    // Rings over the planes, indexed by plane number: M/m[l][k % 3] = 3x3
-    // max/min of level l at plane k, cen/rx/rn[s][k % 2] = centre value and
-    // 8-ring max/min of D_s at plane k, v[k % 2] = the rows of plane k (the
-    // plane loop is unrolled by 6, so every slot is a fixed register).
-    float M[NL][3], m[NL][3];
-    float cen[S + 1][2], rx[S + 1][2], rn[S + 1][2];
+    // Rings over the planes, indexed by plane number: M/m[l][k % 3][r] = 3x3
+    // max/min of level l around output row r at plane k, cen/rx/rn[s][k %
+    // 2][r] = centre value and 8-ring max/min of D_s at plane k, v[k % 2] =
+    // the rows of plane k (the plane loop is unrolled by 6, so every slot is
+    // a fixed register).
+    float M[NL][3][WY], m[NL][3][WY];
+    float cen[S + 1][2][WY], rx[S + 1][2][WY], rn[S + 1][2][WY];
 #pragma unroll
     for (int l = 0; l < NL; ++l)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) M[l][q] = m[l][q] = 0.f;
+        for (int q = 0; q < 3; ++q)
 #pragma unroll
-    for (int l = 0; l <= S; ++l) cen[l][0] = cen[l][1] = rx[l][0] = rx[l][1] = rn[l][0] = rn[l][1] = 0.f;
+            for (int r = 0; r < WY; ++r) M[l][q][r] = m[l][q][r] = 0.f;
+#pragma unroll
+    for (int l = 0; l <= S; ++l)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < WY; ++r) cen[l][q][r] = rx[l][q][r] = rn[l][q][r] = 0.f;
 
     const long long nxy = (long long)nx * ny;
-    unsigned roff[3];   // byte offsets of rows y-1, y, y+1 at column x
+    unsigned roff[NR];   // byte offsets of rows y0-1 .. y0+WY at column x
 #pragma unroll
-    for (int r = 0; r < 3; ++r) roff[r] = 4u * (unsigned)(min(max(y - 1 + r, 0), ny - 1) * nx + x);
-    float v[2][NL][3];
-    load_plane_rows<NL>(D, un.lstride, nxy, z0 - 1, roff, v[0]);
-    const int nplanes = (z1 - z0) + 2;
+    for (int r = 0; r < NR; ++r) roff[r] = 4u * (unsigned)(min(max(y0 - 1 + r, 0), ny - 1) * nx + x);
+    // Mask words go out through a buffer resource: every plane step issues
+    // the same loads and stores (a step past the slab re-reads its last
+    // plane, and a store with nothing to write goes to an offset past the
+    // resource, which the hardware drops), so the waits before each plane's
+    // use count exactly the loads issued after it.
+    const unsigned mask_bytes = (unsigned)min((long long)S * (nz - 2) * (ny - 2) * words * 8, 0x7fffffffLL);
+    const __amdgpu_buffer_rsrc_t mrs = __builtin_amdgcn_make_buffer_rsrc(masks, (short)0, (int)mask_bytes,
+                                                                         kRawBufferWord3);
+    // plane k (z = z0 - 1 + k) sits in buffer k % 3: loads run two planes ahead
+    float v[3][NL][NR];
+    const int nplanes = (z1 - z0) + 2;   // >= 3
+    load_plane_rows<NL, NR>(D, un.lstride, nxy, z0 - 1, roff, v[0]);
+    load_plane_rows<NL, NR>(D, un.lstride, nxy, z0, roff, v[1]);
     for (int base = 0; base < nplanes; base += 6) {
         static_for<0, 6>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
-            constexpr int b = p % 2, nb = (p + 1) % 2;          // plane buffers of k, k+1
+            constexpr int b = p % 3, nb = (p + 2) % 3;          // plane buffers of k, k+2
             constexpr int q0 = (p + 1) % 3, q1 = (p + 2) % 3, q2 = p % 3;   // M slots of k-2, k-1, k
             constexpr int c0 = (p + 1) % 2, c1 = p % 2;          // cen/rx/rn slots of k-1, k
             const int k = base + p;
-            if (k >= nplanes) return;
-            if (k + 1 < nplanes) load_plane_rows<NL>(D, un.lstride, nxy, z0 + k, roff, v[nb]);
+            load_plane_rows<NL, NR>(D, un.lstride, nxy, z0 - 1 + min(k + 2, nplanes - 1), roff, v[nb]);
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
-                float hx[3], hn[3], left1 = 0.f, right1 = 0.f;
+                // each loaded row reduced over x once
+                float hx[NR], hn[NR], lf[NR], rt[NR];
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const float left = from_left(v[b][l][r]);
-                    const float right = from_right(v[b][l][r]);
-                    hx[r] = fmaxf(fmaxf(left, right), v[b][l][r]);
-                    hn[r] = fminf(fminf(left, right), v[b][l][r]);
-                    if (r == 1) {
-                        left1 = left;
-                        right1 = right;
+                for (int r = 0; r < NR; ++r) {
+                    lf[r] = from_left(v[b][l][r]);
+                    rt[r] = from_right(v[b][l][r]);
+                    hx[r] = fmaxf(fmaxf(lf[r], rt[r]), v[b][l][r]);
+                    hn[r] = fminf(fminf(lf[r], rt[r]), v[b][l][r]);
+                }
+#pragma unroll
+                for (int r = 0; r < WY; ++r) {
+                    M[l][q2][r] = fmaxf(fmaxf(hx[r], hx[r + 1]), hx[r + 2]);
+                    m[l][q2][r] = fminf(fminf(hn[r], hn[r + 1]), hn[r + 2]);
+                    if (l >= 1 && l <= S) {
+                        cen[l][c1][r] = v[b][l][r + 1];
+                        rx[l][c1][r] = fmaxf(fmaxf(hx[r], hx[r + 2]), fmaxf(lf[r + 1], rt[r + 1]));
+                        rn[l][c1][r] = fminf(fminf(hn[r], hn[r + 2]), fminf(lf[r + 1], rt[r + 1]));
                     }
                 }
-                M[l][q2] = fmaxf(fmaxf(hx[0], hx[1]), hx[2]);
-                m[l][q2] = fminf(fminf(hn[0], hn[1]), hn[2]);
-                if (l >= 1 && l <= S) {
-                    cen[l][c1] = v[b][l][1];
-                    rx[l][c1] = fmaxf(fmaxf(hx[0], hx[2]), fmaxf(left1, right1));
-                    rn[l][c1] = fminf(fminf(hn[0], hn[2]), fminf(left1, right1));
-                }
             }
-            if (k >= 2) {
-                const int z = z0 + k - 2;
-                const long long row_z = (long long)(z - 1) * (ny - 2) + (y - 1);
+            {
+                const int z = z0 + k - 2;                // output plane of this step
+                const bool zlive = k >= 2 && k < nplanes;
 #pragma unroll
-                for (int s = 1; s <= S; ++s) {
-                    const float vv = cen[s][c0];
-                    float mx = fmaxf(fmaxf(M[s - 1][q0], M[s - 1][q1]), M[s - 1][q2]);
-                    mx = fmaxf(mx, fmaxf(fmaxf(M[s + 1][q0], M[s + 1][q1]), M[s + 1][q2]));
-                    mx = fmaxf(mx, fmaxf(fmaxf(M[s][q0], M[s][q2]), rx[s][c0]));
-                    float mn = fminf(fminf(m[s - 1][q0], m[s - 1][q1]), m[s - 1][q2]);
-                    mn = fminf(mn, fminf(fminf(m[s + 1][q0], m[s + 1][q1]), m[s + 1][q2]));
-                    mn = fminf(mn, fminf(fminf(m[s][q0], m[s][q2]), rn[s][c0]));
-                    const bool flag = in_x && fabsf(vv) > a.thr && (vv > mx || vv < mn);
-                    const unsigned long long bits = __ballot(flag);
-                    if (lane == 0) {
+                for (int r = 0; r < WY; ++r) {
+                    const int y = y0 + r;
+                    const bool live = zlive && y <= ny - 2;   // the same for the whole wavefront
+                    const long long row_z = (long long)(z - 1) * (ny - 2) + (y - 1);
+                    // 3x3x3 max / min of every level around (x, y, z), once per level
+                    float ZX[NL], ZN[NL];
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        ZX[l] = fmaxf(fmaxf(M[l][q0][r], M[l][q1][r]), M[l][q2][r]);
+                        ZN[l] = fminf(fminf(m[l][q0][r], m[l][q1][r]), m[l][q2][r]);
+                    }
+#pragma unroll
+                    for (int s = 1; s <= S; ++s) {
+                        const float vv = cen[s][c0][r];
+                        const float mx = fmaxf(fmaxf(ZX[s - 1], ZX[s + 1]),
+                                               fmaxf(fmaxf(M[s][q0][r], M[s][q2][r]), rx[s][c0][r]));
+                        const float mn = fminf(fminf(ZN[s - 1], ZN[s + 1]),
+                                               fminf(fminf(m[s][q0][r], m[s][q2][r]), rn[s][c0][r]));
+                        // evaluated in full (no short-circuit branches)
+                        const bool flag = in_x & (fabsf(vv) > thr) & ((vv > mx) | (vv < mn));
+                        const unsigned long long bits = __ballot(flag);
                         const long long row = (long long)(s - 1) * (nz - 2) * (ny - 2) + row_z;
-                        masks[row * un.words + txi] = bits;
+                        const unsigned woff = (unsigned)((row * words + txi) * 8);
+                        const unsigned off = live && lane == 0 ? woff : kDropOffset;
+                        const u32x2 w = {(unsigned)bits, (unsigned)(bits >> 32)};
+                        __builtin_amdgcn_raw_buffer_store_b64(w, mrs, (int)off, 0, 0);
                     }
                 }
             }

@@ -72,9 +72,10 @@ constexpr int kDetRowsPerWave = 4;
 constexpr int kDetRowsPerBlock = (kDetThreads / 64) * kDetRowsPerWave;
 constexpr int kScanThreads = 1024;
 // Strict-extremum path (votes == 80): one wavefront per (62 output x plus
-// a halo lane on each side, one y row, kDTZ planes); 4 wavefronts (4
-// consecutive y rows) per block. Mask word t of a row covers x = 62 t + bit.
-constexpr int kDTXOut = 62, kDTY = 4, kDTZ = 16;
+// a halo lane on each side, kDTWY consecutive y rows, kDTZ planes); 4
+// wavefronts (kDTY = 4 kDTWY consecutive rows) per block. Mask word t of a
+// row covers x = 62 t + bit.
+constexpr int kDTXOut = 62, kDTWY = 2, kDTY = 4 * kDTWY, kDTZ = 16;
 constexpr int kRowBlock = 256;              // rows per count / emit block; volumes start on a block
 
 // ---------------------------------------------------------------- device tables
