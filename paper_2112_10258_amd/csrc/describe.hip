@@ -9,6 +9,7 @@
 // Floating-point sums are accumulated in double precision in a fixed order
 // (no atomics), so results are bit-reproducible run to run.
 #include <algorithm>
+#include <type_traits>
 
 #include "sift3d_internal.h"
 
@@ -76,26 +77,93 @@ __device__ __forceinline__ void sift_column(const float *T, int nx, int ny, int 
     }
 }
 
-// Stage G_s over clamp(keypoint - R - 1 .. keypoint + R + 1) per axis into
-// T, then accumulate this thread's (dx, dy) column (threads < (2R+1)^2).
-// Called by the whole workgroup (it contains a barrier).
-template <int R>
-__device__ __forceinline__ void sift_window(const float *G, float *T, int nx, int ny, int nz, int kx, int ky, int kz,
-                                            int tid, double (&acc)[16])
-{
-    constexpr int W = 2 * R + 1, TW = 2 * R + 3;
-    const int cx = kx - R - 1, cy = ky - R - 1, cz = kz - R - 1;
-    const size_t nxy = (size_t)nx * ny;
-    for (int idx = tid; idx < TW * TW * TW; idx += kDescThreads) {
-        const int i = idx % TW, jk = idx / TW;
-        const int j = jk % TW, k = jk / TW;
-        const int gx = clampi(cx + i, 0, nx - 1), gy = clampi(cy + j, 0, ny - 1), gz = clampi(cz + k, 0, nz - 1);
-        T[idx] = G[(size_t)gz * nxy + (size_t)gy * nx + gx];
+// The cube of G_s a window reads, clamp(keypoint - R - 1 .. keypoint + R +
+// 1) per axis, passes through registers: element idx = tid + 256 j of the
+// (2R+3)^3 cube (x fastest) is slot j of thread tid. cube_fetch issues the
+// loads of the next keypoint's cube while the current one is still being
+// ranked; cube_stage writes the slots to LDS.
+constexpr int kCubeSlots = (kSiftTile * kSiftTile * kSiftTile + kDescThreads - 1) / kDescThreads;
+constexpr int kRawBufferWord3 = 0x00020000;   // dword 3 of a raw (untyped) buffer resource on gfx9
+
+// Slot j of thread tid is element idx = tid + 256 j: its (x, y, z) in the
+// cube advance from slot to slot by 256 written in base TW (one carry per
+// digit at most), so one code path serves every radius.
+struct CubeWalk {
+    int TW, N, s0, s1, s2;   // side, elements, digits of 256 in base TW
+    int i, j, k;             // position of this thread's current slot
+    __device__ __forceinline__ CubeWalk(int R, int tid)
+    {
+        TW = 2 * R + 3;
+        N = TW * TW * TW;
+        s2 = kDescThreads / (TW * TW);
+        const int r2 = kDescThreads - s2 * TW * TW;
+        s1 = r2 / TW;
+        s0 = r2 - s1 * TW;
+        // the slot positions are recomputed per call rather than kept live
+        // across the keypoint loop
+        int t = tid;
+        asm volatile("" : "+v"(t));
+        i = t % TW;
+        const int jk = t / TW;
+        j = jk % TW;
+        k = jk / TW;
     }
-    __syncthreads();
-    if (tid < W * W) {
-        const int dy = tid / W - R, dx = tid - (tid / W) * W - R;
-        sift_column<R>(T, nx, ny, nz, kx, ky, kz, dx, dy, acc);
+    __device__ __forceinline__ void next()
+    {
+        i += s0;
+        const int ci = i >= TW;
+        i -= ci ? TW : 0;
+        j += s1 + ci;
+        const int cj = j >= TW;
+        j -= cj ? TW : 0;
+        k += s2 + cj;
+    }
+};
+
+__device__ __forceinline__ void cube_fetch(const float *G, int nx, int ny, int nz, int kx, int ky, int kz, int R,
+                                           int tid, float (&pre)[kCubeSlots])
+{
+    CubeWalk w(R, tid);
+    const int cx = kx - R - 1, cy = ky - R - 1, cz = kz - R - 1;
+    // a buffer resource over the level: each load needs only a 32-bit
+    // offset (the level holds at most 2^30 floats)
+    const unsigned bytes = (unsigned)min((long long)nx * ny * nz * 4, 0xffffffffLL);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(G), (short)0, (int)bytes, kRawBufferWord3);
+#pragma unroll
+    for (int s = 0; s < kCubeSlots; ++s) {
+        if (tid + kDescThreads * s < w.N) {
+            const int gx = clampi(cx + w.i, 0, nx - 1), gy = clampi(cy + w.j, 0, ny - 1);
+            const int gz = clampi(cz + w.k, 0, nz - 1);
+            const unsigned off = 4u * (((unsigned)gz * (unsigned)ny + (unsigned)gy) * (unsigned)nx + (unsigned)gx);
+            pre[s] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+        }
+        w.next();
+    }
+}
+
+__device__ __forceinline__ void cube_stage(float *T, int R, int tid, const float (&pre)[kCubeSlots])
+{
+    const int TW = 2 * R + 3, N = TW * TW * TW;
+#pragma unroll
+    for (int s = 0; s < kCubeSlots; ++s) {
+        const int idx = tid + kDescThreads * s;
+        if (idx < N) T[idx] = pre[s];
+    }
+}
+
+// f(std::integral_constant<int, R>) for the window half-width R (1..7).
+template <typename F>
+__device__ __forceinline__ void with_radius(int R, F &&f)
+{
+    switch (R) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    default: f(std::integral_constant<int, 7>{}); break;
     }
 }
 
@@ -137,35 +205,70 @@ __device__ __forceinline__ void siftrank_body(const DescLaunch &a, int blk, int 
     __shared__ double rows[2 * kMaxSiftR + 1][3][16];   // per (row, x class) sums
     __shared__ double cls[9][16];
     __shared__ double hist[64];
+    __shared__ int rank_part[kDescThreads / 64][64];
+    static_assert(kDescThreads == 256, "four wavefronts share the ranking");
     const int tid = threadIdx.x;
+    // the window of a keypoint: level, octave dims and radius, or not a
+    // keypoint of this plan
+    struct Win {
+        const float *G;
+        int nx, ny, nz, R;
+        bool ok;
+    };
+    auto window_of = [&](const DVol &vol, const sift3d_keypoint &kp) -> Win {
+        Win w{};
+        w.ok = !(kp.octave < 0 || kp.octave >= vol.n_units || kp.scale < 1 || kp.scale > a.S);
+        if (!w.ok) return w;
+        const DUnit &oc = (INL ? a.inl[vol.unit0 + kp.octave] : a.units[vol.unit0 + kp.octave]);
+        w.nx = oc.nx;
+        w.ny = oc.ny;
+        w.nz = oc.nz;
+        w.G = reinterpret_cast<const float *>(a.ws + oc.g0) + oc.lstride * kp.scale;
+        w.R = a.sift_R[kp.scale];
+        return w;
+    };
+    auto fetch = [&](const Win &w, const sift3d_keypoint &kp, float (&pre)[kCubeSlots]) {
+        if (w.ok) cube_fetch(w.G, w.nx, w.ny, w.nz, kp.x, kp.y, kp.z, w.R, tid, pre);
+    };
+    float pre[kCubeSlots];
     long long base = 0;
     for (int v = 0; v < a.n_vol; ++v) {
     const int count = min(a.counts[v], a.cap);
     const DVol vol = a.vols[v];
-    for (int kk = first_of_block(blk, base, nblk); kk < count; kk += nblk) {
+    int kk = first_of_block(blk, base, nblk);
+    sift3d_keypoint kp{};
+    Win win{};
+    if (kk < count) {
+        kp = a.kp[(size_t)v * a.cap + kk];
+        win = window_of(vol, kp);
+        fetch(win, kp, pre);
+    }
+    for (; kk < count; kk += nblk) {
         const size_t k = (size_t)v * a.cap + kk;
-        const sift3d_keypoint kp = a.kp[k];
-        if (kp.octave < 0 || kp.octave >= vol.n_units || kp.scale < 1 || kp.scale > a.S) {
-            // not a keypoint of this plan
+        if (!win.ok) {
+            // not a keypoint of this plan (uniform: the whole workgroup)
             if (tid < 64) a.siftrank[k * 64 + tid] = 0;
+            if (kk + nblk < count) {
+                kp = a.kp[k + nblk];
+                win = window_of(vol, kp);
+                fetch(win, kp, pre);
+            }
             continue;
         }
-        const DUnit &oc = (INL ? a.inl[vol.unit0 + kp.octave] : a.units[vol.unit0 + kp.octave]);
-        const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
-        const float *G = reinterpret_cast<const float *>(a.ws + oc.g0) + oc.lstride * kp.scale;
-        const int R = a.sift_R[kp.scale];
+        const sift3d_keypoint cur = kp;
+        const Win cw = win;
+        const int R = cw.R;
         const int W = 2 * R + 1;
+        cube_stage(T, R, tid, pre);
+        __syncthreads();   // the cube is staged
         double acc[16];
 #pragma unroll
         for (int b = 0; b < 16; ++b) acc[b] = 0.0;
-        switch (R) {
-        case 1: sift_window<1>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-        case 2: sift_window<2>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-        case 3: sift_window<3>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-        case 4: sift_window<4>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-        case 5: sift_window<5>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-        case 6: sift_window<6>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
-        default: sift_window<7>(G, T, nx, ny, nz, kp.x, kp.y, kp.z, tid, acc); break;
+        if (tid < W * W) {
+            const int dy = tid / W - R, dx = tid - (tid / W) * W - R;
+            with_radius(R, [&](auto r) {
+                sift_column<decltype(r)::value>(T, cw.nx, cw.ny, cw.nz, cur.x, cur.y, cur.z, dx, dy, acc);
+            });
         }
         __syncthreads();   // the column sums overwrite the staged cube
         if (tid < W * W) {
@@ -206,16 +309,29 @@ __device__ __forceinline__ void siftrank_body(const DescLaunch &a, int blk, int 
             hist[tid] = h;
         }
         __syncthreads();
-        if (tid < 64) {
-            const double h = hist[tid];
-            int r = 0;
-#pragma unroll 8
-            for (int e = 0; e < 64; ++e) {
-                const double o = hist[e];
-                r += (int)(o < h) | ((int)(o == h) & (int)(e < tid));
-            }
-            a.siftrank[k * 64 + tid] = (uint8_t)r;
+        // the next keypoint's cube is fetched while this one is ranked
+        if (kk + nblk < count) {
+            kp = a.kp[k + nblk];
+            win = window_of(vol, kp);
+            fetch(win, kp, pre);
         }
+        {
+            // rank of bin e = tid % 64 among the 64 (ties by index): the four
+            // wavefronts count over a quarter of the bins each
+            const int e = tid & 63, q = tid >> 6;
+            const double h = hist[e];
+            int r = 0;
+#pragma unroll
+            for (int o = 16 * q; o < 16 * q + 16; ++o) {
+                const double x = hist[o];
+                r += (int)(x < h) | ((int)(x == h) & (int)(o < e));
+            }
+            rank_part[q][e] = r;
+        }
+        __syncthreads();
+        if (tid < 64)
+            a.siftrank[k * 64 + tid] =
+                (uint8_t)(rank_part[0][tid] + rank_part[1][tid] + rank_part[2][tid] + rank_part[3][tid]);
         __syncthreads();
     }
     base += count;
