@@ -73,3 +73,20 @@ def test_match_extracted_descriptors():
         _same(A, A[perm], kind, f)
         _same(A, Bh, kind, f + " vs other volume")
     print(f"[match] extracted descriptors: {g['count']} vs {h['count']} keypoints ok", flush=True)
+
+
+@pytest.mark.parametrize("m", [64, 256])
+def test_match_rank_rows_with_many_ties_and_extreme_bytes(m):
+    """Rows drawn from a small pool (many exact ties inside one tile, across
+    the two halves of a lane pair and across wavefronts and tiles) and bytes
+    at both ends of 0..255, with more A rows than one workgroup's block."""
+    import paper_2112_10258_amd as S
+    rng = np.random.default_rng(300 + m)
+    pool = rng.integers(0, 256, size=(40, m), dtype=np.uint8)
+    pool[0] = 0
+    pool[1] = 255
+    n_a, n_b = 1000, 2600
+    A = pool[rng.integers(0, 40, n_a)]
+    B = pool[rng.integers(0, 40, n_b)]
+    _same(A, B, S.MATCH_RANKS, ("pool", m))
+    print(f"[match] ranks {m}: pool rows with ties ok", flush=True)
