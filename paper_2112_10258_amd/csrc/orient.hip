@@ -119,6 +119,34 @@ struct OrientShared {
     double S;
 };
 
+// Register run of one column: the sums of consecutive samples that fall in
+// the same direction bin, added to the LDS histogram when the bin changes.
+struct BinRun {
+    int bin = -1;
+    unsigned long long w = 0, x = 0, y = 0, z = 0;
+    __device__ __forceinline__ void flush(OrientShared &s)
+    {
+        if (bin < 0) return;
+        atomicAdd(&s.acc[0][bin], w);
+        atomicAdd(&s.acc[1][bin], x);
+        atomicAdd(&s.acc[2][bin], y);
+        atomicAdd(&s.acc[3][bin], z);
+    }
+    __device__ __forceinline__ void add(OrientShared &s, int b, unsigned long long tw, unsigned long long tx,
+                                        unsigned long long ty, unsigned long long tz)
+    {
+        if (b != bin) {
+            flush(s);
+            bin = b;
+            w = x = y = z = 0;
+        }
+        w += tw;
+        x += tx;
+        y += ty;
+        z += tz;
+    }
+};
+
 // Peaks of the histogram in s.acc[0] into s.peaks (called by wavefront 0).
 __device__ void find_peaks(OrientShared &s, double tau, int lane)
 {
@@ -218,19 +246,19 @@ __device__ void orient_one(OrientShared &s, const OrientLaunch &a, const float *
     const bool col = tid < W * W;
     const int dy = tid / W - R, dx = tid - (tid / W) * W - R;
 
-    // pass 1: spherical histogram of the gradients
+    // pass 1: spherical histogram of the gradients. Consecutive samples of a
+    // column that fall in the same bin are summed in registers and added to
+    // LDS once (integer sums: the result does not depend on the grouping).
     if (col) {
+        BinRun run;
         for (int dz = -R; dz <= R; ++dz) {
             double gx, gy, gz;
             grad<R>(s, nx, ny, nz, kx, ky, kz, dx, dy, dz, gx, gy, gz);
             const double m = sqrt(gx * gx + gy * gy + gz * gz);
             if (!(m > 0.0)) continue;
-            const int b = nearest_dir(gx, gy, gz);
-            atomicAdd(&s.acc[0][b], fix(m, S));
-            atomicAdd(&s.acc[1][b], fix(gx, S));
-            atomicAdd(&s.acc[2][b], fix(gy, S));
-            atomicAdd(&s.acc[3][b], fix(gz, S));
+            run.add(s, nearest_dir(gx, gy, gz), fix(m, S), fix(gx, S), fix(gy, S), fix(gz, S));
         }
+        run.flush(s);
     }
     __syncthreads();
     if (wave == 0) {
@@ -256,6 +284,7 @@ __device__ void orient_one(OrientShared &s, const OrientLaunch &a, const float *
         __syncthreads();
         const double e1x = s.e1[ip][0], e1y = s.e1[ip][1], e1z = s.e1[ip][2];
         if (col) {
+            BinRun run;
             for (int dz = -R; dz <= R; ++dz) {
                 double gx, gy, gz;
                 grad<R>(s, nx, ny, nz, kx, ky, kz, dx, dy, dz, gx, gy, gz);
@@ -263,12 +292,9 @@ __device__ void orient_one(OrientShared &s, const OrientLaunch &a, const float *
                 const double px = gx - t * e1x, py = gy - t * e1y, pz = gz - t * e1z;
                 const double m2 = sqrt(px * px + py * py + pz * pz);
                 if (!(m2 > 0.0)) continue;
-                const int b = nearest_dir(px, py, pz);
-                atomicAdd(&s.acc[0][b], fix(m2, S));
-                atomicAdd(&s.acc[1][b], fix(px, S));
-                atomicAdd(&s.acc[2][b], fix(py, S));
-                atomicAdd(&s.acc[3][b], fix(pz, S));
+                run.add(s, nearest_dir(px, py, pz), fix(m2, S), fix(px, S), fix(py, S), fix(pz, S));
             }
+            run.flush(s);
         }
         __syncthreads();
         if (wave == 0) find_peaks(s, a.tau, lane);
@@ -296,12 +322,24 @@ __device__ void orient_one(OrientShared &s, const OrientLaunch &a, const float *
 
     // pass 3: SIFT-Rank of every frame
     if (col && nf > 0) {
+        // per frame, a run of samples feeding one single bin is summed in
+        // registers (integer sums); samples on a frame plane (several bins)
+        // go to LDS at once
+        int rbin[kMaxOrient];
+        unsigned long long racc[kMaxOrient];
+#pragma unroll
+        for (int f = 0; f < kMaxOrient; ++f) {
+            rbin[f] = -1;
+            racc[f] = 0ull;
+        }
         for (int dz = -R; dz <= R; ++dz) {
             double gx, gy, gz;
             grad<R>(s, nx, ny, nz, kx, ky, kz, dx, dy, dz, gx, gy, gz);
             const double m = sqrt(gx * gx + gy * gy + gz * gz);
             if (!(m > 0.0)) continue;
-            for (int f = 0; f < nf; ++f) {
+#pragma unroll
+            for (int f = 0; f < kMaxOrient; ++f) {
+                if (f >= nf) break;
                 const double *F = s.frame[f];
                 int bo = 0, lo[3], hi[3];
                 double w0[3];
@@ -315,12 +353,26 @@ __device__ void orient_one(OrientShared &s, const OrientLaunch &a, const float *
                     hi[j] = dp < 0.0 ? 0 : 1;
                     w0[j] = dp == 0.0 ? 0.5 : 1.0;
                 }
-                for (int bz = lo[2]; bz <= hi[2]; ++bz)
-                    for (int by = lo[1]; by <= hi[1]; ++by)
-                        for (int bx = lo[0]; bx <= hi[0]; ++bx)
-                            atomicAdd(&s.hist[f][8 * (bx + 2 * by + 4 * bz) + bo], fix(m * w0[0] * w0[1] * w0[2], S));
+                const unsigned long long term = fix(m * w0[0] * w0[1] * w0[2], S);
+                if (lo[0] == hi[0] && lo[1] == hi[1] && lo[2] == hi[2]) {
+                    const int bin = 8 * (lo[0] + 2 * lo[1] + 4 * lo[2]) + bo;
+                    if (bin != rbin[f]) {
+                        if (rbin[f] >= 0) atomicAdd(&s.hist[f][rbin[f]], racc[f]);
+                        rbin[f] = bin;
+                        racc[f] = 0ull;
+                    }
+                    racc[f] += term;
+                } else {
+                    for (int bz = lo[2]; bz <= hi[2]; ++bz)
+                        for (int by = lo[1]; by <= hi[1]; ++by)
+                            for (int bx = lo[0]; bx <= hi[0]; ++bx)
+                                atomicAdd(&s.hist[f][8 * (bx + 2 * by + 4 * bz) + bo], term);
+                }
             }
         }
+#pragma unroll
+        for (int f = 0; f < kMaxOrient; ++f)
+            if (f < nf && rbin[f] >= 0) atomicAdd(&s.hist[f][rbin[f]], racc[f]);
     }
     __syncthreads();
     // ranks (ties by index) and outputs
