@@ -41,6 +41,7 @@ enum {
     SIFT3D_E_HIP = -5,        /* a HIP runtime call failed                  */
     SIFT3D_E_UNSUPPORTED = -6, /* parameter outside what the kernels support */
     SIFT3D_E_SCRATCH = -7,    /* plan needs more than the static scratch    */
+    SIFT3D_E_TIMEOUT = -8,    /* server request not admitted in time        */
     SIFT3D_PENDING = 1         /* sift3d_server_result: not finished yet   */
 };
 
@@ -390,6 +391,10 @@ typedef struct sift3d_server_config {
     int max_inflight;   /* groups on the device at once, 1..256             */
     int kp_capacity;    /* keypoint and descriptor rows per request, >= 1    */
     int max_batch;      /* requests per group, 1..64 (1 = no grouping)        */
+    double admit_timeout_s; /* 0 = a request waits for admission without limit;
+                               > 0: a request not admitted within this many
+                               seconds of its submission ends with status
+                               SIFT3D_E_TIMEOUT (it must still be released)  */
 } sift3d_server_config;
 
 /* Result of one request; device pointers stay valid until its release. */

@@ -6,6 +6,13 @@ declared in include/sift3d.h.
 """
 from .sift3d import (  # noqa: F401
     DETECT_STATIC_SCRATCH,
+    E_ARG,
+    E_HIP,
+    E_SCRATCH,
+    E_TIMEOUT,
+    E_TOO_SMALL,
+    E_UNSUPPORTED,
+    E_WORKSPACE,
     KEYPOINT_BYTES,
     MAX_ORIENTATIONS,
     KEYPOINT_DTYPE,

@@ -1689,6 +1689,7 @@ const char *sift3d_error_string(int code)
     case SIFT3D_E_HIP: return "HIP runtime error";
     case SIFT3D_E_UNSUPPORTED: return "parameter outside the supported range";
     case SIFT3D_E_SCRATCH: return "detection scratch larger than the static maximum";
+    case SIFT3D_E_TIMEOUT: return "request not admitted within the server's admission timeout";
     case SIFT3D_PENDING: return "request not finished";
     default: return "unknown error";
     }

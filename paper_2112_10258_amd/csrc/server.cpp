@@ -33,6 +33,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdint>
 #include <map>
@@ -340,6 +341,14 @@ void scheduler(sift3d_server *sv)
         // under the lock: released slots back to the pool, then admissions
         for (Slot *s : sv->to_release) sv->policy->add_idle(s, now_s());
         sv->to_release.clear();
+        bool expired_any = false;
+        {
+            // requests past their admission deadline end before admissions
+            std::vector<int64_t> expired;
+            sv->policy->expire(now_s(), expired);
+            for (int64_t id : expired) fail_request(sv, sv->reqs.at(id), SIFT3D_E_TIMEOUT, 0);
+            expired_any = !expired.empty();
+        }
         std::vector<Start> starts;
         while ((int)(sv->running.size() + starts.size()) < sv->cfg.max_inflight) {
             Start st;
@@ -380,7 +389,7 @@ void scheduler(sift3d_server *sv)
 
         lk.lock();
         // publish
-        bool notify = false;
+        bool notify = expired_any;
         for (Start &st : starts) {
             if (st.rc != SIFT3D_OK) {
                 for (Request *r : st.reqs) fail_request(sv, r, st.rc, st.hip_error);
@@ -435,8 +444,16 @@ void scheduler(sift3d_server *sv)
         if (stopping && sv->running.empty()) break;
         if (sv->work_gen != gen || !starts.empty() || !finished.empty()) continue;   // new work arrived meanwhile
         if (sv->running.empty()) {
-            // idle until a submission, a release or stop: nothing pending can start before one
-            sv->cv_work.wait(lk, [&] { return sv->work_gen != gen; });
+            // idle until a submission, a release or stop (nothing pending can
+            // start before one), or until the next admission deadline
+            const double dl = sv->policy->next_deadline();
+            if (dl > 0.0) {
+                const double wait_s = std::max(0.0, dl - now_s());
+                sv->cv_work.wait_for(lk, std::chrono::duration<double>(wait_s),
+                                     [&] { return sv->work_gen != gen; });
+            } else {
+                sv->cv_work.wait(lk, [&] { return sv->work_gen != gen; });
+            }
         } else {
             // poll the device; new submissions and releases wake us early
             sv->cv_work.wait_for(lk, std::chrono::microseconds(20));
@@ -454,7 +471,8 @@ int sift3d_server_create(sift3d_ctx *ctx, const sift3d_server_config *cfg, sift3
     *out = nullptr;
     if (ctx == nullptr || cfg == nullptr) return SIFT3D_E_ARG;
     if (cfg->n_streams < 1 || cfg->n_streams > 8 || cfg->max_inflight < 1 || cfg->max_inflight > 256 ||
-        cfg->kp_capacity < 1 || cfg->hbm_budget == 0 || cfg->max_batch < 1 || cfg->max_batch > 64)
+        cfg->kp_capacity < 1 || cfg->hbm_budget == 0 || cfg->max_batch < 1 || cfg->max_batch > 64 ||
+        !(cfg->admit_timeout_s >= 0.0) || !std::isfinite(cfg->admit_timeout_s))
         return SIFT3D_E_ARG;
     sift3d_params p;
     sift3d_ctx_params(ctx, &p);
@@ -529,7 +547,8 @@ int sift3d_server_submit(sift3d_server *sv, const float *d_vol, int nx, int ny, 
         r->rc = SIFT3D_OK;
         r->t_submit = now_s();
         sv->reqs[r->id] = r;
-        sv->policy->pending.push_back(s3d::serve::Waiting{r->id, r->shape, fp});
+        const double deadline = sv->cfg.admit_timeout_s > 0.0 ? r->t_submit + sv->cfg.admit_timeout_s : 0.0;
+        sv->policy->pending.push_back(s3d::serve::Waiting{r->id, r->shape, fp, deadline});
         ++sv->work_gen;
         ++sv->stats.submitted;
         *ticket = r->id;

@@ -42,6 +42,7 @@ struct Waiting {
     int64_t id;
     Shape shape;
     size_t footprint;                 // bytes of a lone slot of its shape
+    double deadline = 0.0;            // admission deadline (clock seconds); 0 = none
 };
 
 // What the executor must do to start one admitted group.
@@ -69,6 +70,29 @@ public:
     size_t allocated() const { return allocated_; }   // all slots, idle or held, and reservations
     size_t idle_bytes() const { return idle_bytes_; }
     const std::map<Kind, std::vector<Slot *>> &idle() const { return idle_; }
+
+    // Requests whose admission deadline has passed leave the queue; their
+    // ids are appended to `out` in arrival order.
+    void expire(double now, std::vector<int64_t> &out)
+    {
+        for (size_t i = 0; i < pending.size();) {
+            if (pending[i].deadline > 0.0 && pending[i].deadline <= now) {
+                out.push_back(pending[i].id);
+                pending.erase(pending.begin() + (long)i);
+            } else {
+                ++i;
+            }
+        }
+    }
+
+    // Earliest admission deadline of the queue, or 0 if none.
+    double next_deadline() const
+    {
+        double t = 0.0;
+        for (const Waiting &w : pending)
+            if (w.deadline > 0.0 && (t == 0.0 || w.deadline < t)) t = w.deadline;
+        return t;
+    }
 
     // A slot whose group has been released (or never ran) becomes idle.
     void add_idle(Slot *s, double now)

@@ -23,7 +23,7 @@ KEYPOINT_DTYPE = np.dtype([
 KEYPOINT_BYTES = 40
 assert KEYPOINT_DTYPE.itemsize == KEYPOINT_BYTES
 
-OK, E_ARG, E_TOO_SMALL, E_WORKSPACE, E_HIP, E_UNSUPPORTED, E_SCRATCH = 0, -1, -2, -3, -5, -6, -7
+OK, E_ARG, E_TOO_SMALL, E_WORKSPACE, E_HIP, E_UNSUPPORTED, E_SCRATCH, E_TIMEOUT = 0, -1, -2, -3, -5, -6, -7, -8
 DETECT_STATIC_SCRATCH = 64 << 20     # SIFT3D_DETECT_STATIC_SCRATCH
 MAX_ORIENTATIONS = 4                 # SIFT3D_MAX_ORIENTATIONS
 PENDING = 1
@@ -54,6 +54,7 @@ class ServerConfig(ctypes.Structure):
         ("max_inflight", ctypes.c_int),
         ("kp_capacity", ctypes.c_int),
         ("max_batch", ctypes.c_int),
+        ("admit_timeout_s", ctypes.c_double),
     ]
 
 
@@ -647,11 +648,12 @@ class Server:
     volumes as they arrive, poll or wait for results, release their slots."""
 
     def __init__(self, ctx: Context, hbm_budget: int, n_streams: int = 4, max_inflight: int = 8,
-                 kp_capacity: int = 1 << 14, max_batch: int = 8):
+                 kp_capacity: int = 1 << 14, max_batch: int = 8, admit_timeout_s: float = 0.0):
         lib = _load()
         self.ctx = ctx
         self.capacity = int(kp_capacity)
-        cfg = ServerConfig(int(hbm_budget), int(n_streams), int(max_inflight), int(kp_capacity), int(max_batch))
+        cfg = ServerConfig(int(hbm_budget), int(n_streams), int(max_inflight), int(kp_capacity), int(max_batch),
+                           float(admit_timeout_s))
         h = ctypes.c_void_p()
         _check(lib.sift3d_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "sift3d_server_create")
         self.handle = h

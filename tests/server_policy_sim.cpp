@@ -54,7 +54,7 @@ double fake_duration(const Kind &k)
 struct Req {
     Shape shape;
     double arrival;
-    int state = 0;          // 0 waiting to arrive, 1 pending, 2 running, 3 done
+    int state = 0;          // 0 waiting to arrive, 1 pending, 2 running, 3 done, 4 timed out
     FakeSlot *slot = nullptr;
 };
 
@@ -68,10 +68,11 @@ struct Running {
 
 int main(int argc, char **argv)
 {
-    if (argc != 7) {
-        std::fprintf(stderr, "usage: %s SEED BUDGET_MB MAX_BATCH MAX_INFLIGHT N_REQ SATURATED\n", argv[0]);
+    if (argc != 7 && argc != 8) {
+        std::fprintf(stderr, "usage: %s SEED BUDGET_MB MAX_BATCH MAX_INFLIGHT N_REQ SATURATED [TIMEOUT_S]\n", argv[0]);
         return 2;
     }
+    const double timeout = argc == 8 ? std::atof(argv[7]) : 0.0;
     const unsigned seed = (unsigned)std::atoi(argv[1]);
     const size_t budget = (size_t)(std::atof(argv[2]) * (1 << 20));
     const int max_batch = std::atoi(argv[3]), max_inflight = std::atoi(argv[4]), n_req = std::atoi(argv[5]);
@@ -102,7 +103,8 @@ int main(int argc, char **argv)
     std::set<FakeSlot *> live;
     size_t live_bytes = 0, peak = 0;
     long next_slot = 0, groups = 0, evictions = 0, allocations = 0, max_group = 0, max_running = 0;
-    bool ok_budget = true, ok_shape = true, ok_pow2 = true, ok_head = true, deadlock = false;
+    bool ok_budget = true, ok_shape = true, ok_pow2 = true, ok_head = true, deadlock = false, ok_deadline = true;
+    long expired = 0;
     size_t next_arrival = 0, consumer = 0, done = 0;
     double now = 0.0;
     std::vector<FakeSlot *> released;
@@ -112,17 +114,30 @@ int main(int argc, char **argv)
         while (next_arrival < reqs.size() && reqs[next_arrival].arrival <= now) {
             Req &r = reqs[next_arrival];
             r.state = 1;
-            pol.pending.push_back(s3d::serve::Waiting{(int64_t)next_arrival, r.shape, fake_bytes(Kind{r.shape, 1})});
+            pol.pending.push_back(s3d::serve::Waiting{(int64_t)next_arrival, r.shape, fake_bytes(Kind{r.shape, 1}),
+                                                      timeout > 0.0 ? r.arrival + timeout : 0.0});
             ++next_arrival;
         }
         // the client: results in submission order, released once read
-        while (consumer < reqs.size() && reqs[consumer].state == 3) {
+        while (consumer < reqs.size() && (reqs[consumer].state == 3 || reqs[consumer].state == 4)) {
             FakeSlot *s = reqs[consumer].slot;
-            if (--s->holders == 0) released.push_back(s);
+            if (s != nullptr && --s->holders == 0) released.push_back(s);
             ++consumer;
         }
         for (FakeSlot *s : released) pol.add_idle(s, now);
         released.clear();
+        // requests past their admission deadline end first
+        {
+            std::vector<int64_t> exp;
+            pol.expire(now, exp);
+            for (int64_t id : exp) {
+                if (now - reqs[id].arrival < timeout) ok_deadline = false;
+                reqs[id].state = 4;
+                reqs[id].slot = nullptr;
+                ++expired;
+                ++done;
+            }
+        }
         // admissions
         while ((int)running.size() < max_inflight) {
             const int64_t head = pol.pending.empty() ? -1 : pol.pending.front().id;
@@ -153,6 +168,7 @@ int main(int argc, char **argv)
             s->holders = (int)n;
             Running g{s, {}, now + fake_duration(a.kind)};
             for (int64_t id : a.reqs) {
+                if (timeout > 0.0 && now > reqs[id].arrival + timeout) ok_deadline = false;
                 reqs[id].state = 2;
                 reqs[id].slot = s;
                 g.reqs.push_back(id);
@@ -164,7 +180,9 @@ int main(int argc, char **argv)
         double t_next = 1e300;
         for (const Running &g : running) t_next = std::min(t_next, g.t_end);
         if (next_arrival < reqs.size()) t_next = std::min(t_next, reqs[next_arrival].arrival);
-        const bool client_can_move = consumer < reqs.size() && reqs[consumer].state == 3;
+        if (pol.next_deadline() > 0.0) t_next = std::min(t_next, pol.next_deadline());
+        const bool client_can_move =
+            consumer < reqs.size() && (reqs[consumer].state == 3 || reqs[consumer].state == 4);
         if (t_next == 1e300 && !client_can_move && released.empty()) {
             deadlock = true;
             break;
@@ -187,9 +205,9 @@ int main(int argc, char **argv)
     std::printf("{\"requests\": %zu, \"rejected\": %d, \"completed\": %zu, \"deadlock\": %s, \"budget\": %zu, "
                 "\"peak_bytes\": %zu, \"groups\": %ld, \"max_group\": %ld, \"allocations\": %ld, "
                 "\"evictions\": %ld, \"max_running\": %ld, \"ok_budget\": %s, \"ok_shape\": %s, \"ok_pow2\": %s, "
-                "\"ok_head\": %s, \"sim_seconds\": %.6f}\n",
+                "\"ok_head\": %s, \"expired\": %ld, \"ok_deadline\": %s, \"sim_seconds\": %.6f}\n",
                 reqs.size(), rejected, done, deadlock ? "true" : "false", budget, peak, groups, max_group, allocations,
                 evictions, max_running, ok_budget ? "true" : "false", ok_shape ? "true" : "false",
-                ok_pow2 ? "true" : "false", ok_head ? "true" : "false", now);
+                ok_pow2 ? "true" : "false", ok_head ? "true" : "false", expired, ok_deadline ? "true" : "false", now);
     return 0;
 }

@@ -158,3 +158,41 @@ def test_server_groups_waiting_requests_of_one_shape():
         assert st["groups"] < len(order), "no requests were grouped"
     finally:
         srv.close()
+
+
+def test_admission_timeout_ends_requests_that_wait_too_long():
+    """With one group on the device at a time and a 1 ms admission timeout,
+    a burst of requests cannot all be admitted in time: the late ones end
+    with SIFT3D_E_TIMEOUT (and can be released), the others equal the
+    plain path. Without a timeout the same burst completes."""
+    import torch
+    import paper_2112_10258_amd as S
+    ctx = _ctx()
+    vol = _vols()[0]
+    ref = _plain(ctx, vol)
+    dv = torch.from_numpy(vol).cuda()
+    torch.cuda.synchronize()
+    for timeout in (1e-3, 0.0):
+        srv = S.Server(ctx, hbm_budget=8 << 30, n_streams=1, max_inflight=1, max_batch=1, kp_capacity=CAP,
+                       admit_timeout_s=timeout)
+        try:
+            tickets = [srv.submit(dv) for _ in range(40)]
+            res = [srv.result(t) for t in tickets]
+            ok = [t for t, r in zip(tickets, res) if r.status == 0]
+            late = [r for r in res if r.status == S.E_TIMEOUT]
+            assert len(ok) + len(late) == len(tickets)
+            for t in ok:
+                _same(srv.fetch(t), ref, f"timeout {timeout}")
+            for r in late:
+                assert r.t_done - r.t_submit >= timeout * 0.999
+            for t in tickets:
+                srv.release(t)
+            st = srv.stats()
+            print(f"[serve] admission timeout {timeout}: {len(ok)} admitted, {len(late)} timed out", flush=True)
+            if timeout > 0:
+                assert len(ok) >= 1 and len(late) >= 1
+                assert st["failed"] == len(late)
+            else:
+                assert not late and st["failed"] == 0
+        finally:
+            srv.close()

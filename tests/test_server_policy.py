@@ -25,15 +25,16 @@ def sim(tmp_path_factory):
     return exe
 
 
-def run(sim, seed, budget_mb, max_batch, max_inflight, n_req, saturated):
+def run(sim, seed, budget_mb, max_batch, max_inflight, n_req, saturated, timeout=0.0):
     out = subprocess.check_output([sim, str(seed), str(budget_mb), str(max_batch), str(max_inflight), str(n_req),
-                                   "1" if saturated else "0"], timeout=60)
+                                   "1" if saturated else "0", repr(float(timeout))], timeout=60)
     return json.loads(out)
 
 
 def check(r, max_batch, max_inflight):
     assert not r["deadlock"], r
     assert r["completed"] == r["requests"], r
+    assert r["ok_deadline"], r
     assert r["ok_budget"] and r["peak_bytes"] <= r["budget"], r
     assert r["ok_shape"] and r["ok_pow2"] and r["ok_head"], r
     assert r["max_group"] <= max_batch and r["max_running"] <= max_inflight, r
@@ -68,3 +69,19 @@ def test_random_configurations(sim):
         mi = int(rng.choice([1, 2, 4, 8]))
         r = run(sim, 100 + seed, budget, mb, mi, 150, bool(rng.integers(2)))
         check(r, mb, mi)
+
+
+def test_admission_timeout_ends_only_requests_past_their_deadline(sim):
+    # a saturated burst through one group at a time: with a timeout the
+    # late requests expire (never after being admitted, never before their
+    # deadline) and everything else completes; without one nothing expires
+    r = run(sim, 7, 200000, 1, 1, 400, True, timeout=0.01)
+    check(r, 1, 1)
+    assert r["expired"] > 0 and r["expired"] < r["requests"]
+    r0 = run(sim, 7, 200000, 1, 1, 400, True, timeout=0.0)
+    check(r0, 1, 1)
+    assert r0["expired"] == 0
+    # tight budgets and paced arrivals with a timeout still never deadlock
+    for seed, mb, sat in ((8, 1500, True), (9, 2000, False), (10, 4096, True)):
+        r = run(sim, seed, mb, 8, 4, 300, sat, timeout=0.05)
+        check(r, 8, 4)
