@@ -365,14 +365,50 @@ __device__ __forceinline__ void brief_body(const DescLaunch &a, int blk, int nbl
     const int gw = __builtin_amdgcn_readfirstlane(blk * (kDescThreads / 64) + (threadIdx.x >> 6));
     const int nwaves = nblk * (kDescThreads / 64);
     const int n = a.brief_n, nw = n / 64;
+    // The two samples of every pair of a keypoint (8 loads per lane) are
+    // issued one keypoint ahead: the next keypoint's loads are in flight
+    // while the current one is compared and sorted.
+    auto gather = [&](const DVol &vol, const sift3d_keypoint &kp, float (&s1)[kBriefRegs],
+                      float (&s2)[kBriefRegs]) -> bool {
+        if (kp.octave < 0 || kp.octave >= vol.n_units || kp.scale < 1 || kp.scale > a.S) return false;
+        const DUnit &oc = (INL ? a.inl[vol.unit0 + kp.octave] : a.units[vol.unit0 + kp.octave]);
+        const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
+        const float *B = reinterpret_cast<const float *>(a.ws + oc.b1) + oc.lstride * (kp.scale - 1);
+#pragma unroll
+        for (int j = 0; j < kBriefRegs; ++j) {
+            const int i = 64 * j + lane;
+            s1[j] = s2[j] = 0.f;
+            if (i < n) {
+                const int32_t *o = a.pairs + ((size_t)(kp.scale - 1) * n + i) * 6;
+                const int x1 = clampi(kp.x + o[0], 0, nx - 1), y1 = clampi(kp.y + o[1], 0, ny - 1);
+                const int z1 = clampi(kp.z + o[2], 0, nz - 1);
+                const int x2 = clampi(kp.x + o[3], 0, nx - 1), y2 = clampi(kp.y + o[4], 0, ny - 1);
+                const int z2 = clampi(kp.z + o[5], 0, nz - 1);
+                s1[j] = B[((size_t)z1 * ny + y1) * nx + x1];
+                s2[j] = B[((size_t)z2 * ny + y2) * nx + x2];
+            }
+        }
+        return true;
+    };
+    float n1[kBriefRegs], n2[kBriefRegs];
     long long base = 0;
     for (int v = 0; v < a.n_vol; ++v) {
     const int count = min(a.counts[v], a.cap);
     const DVol vol = a.vols[v];
-    for (int kk = first_of_block(gw, base, nwaves); kk < count; kk += nwaves) {
+    int kk = first_of_block(gw, base, nwaves);
+    bool nok = false;
+    if (kk < count) nok = gather(vol, a.kp[(size_t)v * a.cap + kk], n1, n2);
+    for (; kk < count; kk += nwaves) {
         const size_t k = (size_t)v * a.cap + kk;
-        const sift3d_keypoint kp = a.kp[k];
-        if (kp.octave < 0 || kp.octave >= vol.n_units || kp.scale < 1 || kp.scale > a.S) {
+        const bool ok = nok;
+        float b1[kBriefRegs], b2[kBriefRegs];
+#pragma unroll
+        for (int j = 0; j < kBriefRegs; ++j) {
+            b1[j] = n1[j];
+            b2[j] = n2[j];
+        }
+        if (kk + nwaves < count) nok = gather(vol, a.kp[k + nwaves], n1, n2);
+        if (!ok) {
             // not a keypoint of this plan
 #pragma unroll
             for (int j = 0; j < kBriefRegs; ++j) {
@@ -382,26 +418,13 @@ __device__ __forceinline__ void brief_body(const DescLaunch &a, int blk, int nbl
             if (a.brief != nullptr && lane < nw) a.brief[k * nw + lane] = 0;
             continue;
         }
-        const DUnit &oc = (INL ? a.inl[vol.unit0 + kp.octave] : a.units[vol.unit0 + kp.octave]);
-        const int nx = oc.nx, ny = oc.ny, nz = oc.nz;
-        const float *B = reinterpret_cast<const float *>(a.ws + oc.b1) + oc.lstride * (kp.scale - 1);
         double key[kBriefRegs];
         int idx[kBriefRegs];
 #pragma unroll
         for (int j = 0; j < kBriefRegs; ++j) {
             const int i = 64 * j + lane;
             idx[j] = i;
-            key[j] = __builtin_inf();
-            if (i < n) {
-                const int32_t *o = a.pairs + ((size_t)(kp.scale - 1) * n + i) * 6;
-                const int x1 = clampi(kp.x + o[0], 0, nx - 1), y1 = clampi(kp.y + o[1], 0, ny - 1);
-                const int z1 = clampi(kp.z + o[2], 0, nz - 1);
-                const int x2 = clampi(kp.x + o[3], 0, nx - 1), y2 = clampi(kp.y + o[4], 0, ny - 1);
-                const int z2 = clampi(kp.z + o[5], 0, nz - 1);
-                const float b1 = B[((size_t)z1 * ny + y1) * nx + x1];
-                const float b2 = B[((size_t)z2 * ny + y2) * nx + x2];
-                key[j] = (double)b1 - (double)b2;
-            }
+            key[j] = i < n ? (double)b1[j] - (double)b2[j] : __builtin_inf();
         }
         if (a.brief != nullptr) {
 #pragma unroll
