@@ -405,6 +405,84 @@ def pair_alignment(stream, reps=10):
     return out
 
 
+SIGMA_B_SWEEP = (0.0, 0.65, 0.95, 1.25, 1.55, 1.85, 2.15, 2.45, 2.75, 3.05)
+
+
+def descriptor_power(stream):
+    """The paper's descriptor-accuracy experiment (Section 3.3 and the BRIEF
+    and RRIEF accuracy results) on a synthetic pair with known
+    correspondences: for each point-pair method (1..5) and pre-blur sigma_b
+    of the sweep, BRIEF (Hamming) and RRIEF (rank distance) nearest-neighbour
+    matches from volume A to volume B, counted as inliers of the 7-DoF Hough
+    vote. SIFT-Rank (upright, and oriented) is counted the same way. The pair
+    is the 145x174x145 brain-like phantom against a copy rotated 8 degrees,
+    scaled 1.08, warped by a smooth random displacement of up to 2.5 voxels
+    (a stand-in for the differences between two subjects) and given fresh
+    N(0, 0.03^2) noise."""
+    import torch
+
+    import paper_2112_10258_amd as S
+    from gen import phantoms as P
+    A = P.config2()
+    B, s_true, R_true, t_true = P.similarity_copy(A, scale=1.08, angle_deg=8.0, noise=0.03, seed=8, warp=2.5)
+    nz, ny, nx = A.shape
+    hp = S.hough_default_params((nx, ny, nz))
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    cap = 1 << 14
+    draws = P.pair_draws()
+
+    def extract(params, vol):
+        ctx = S.Context(params, draws)
+        plan = S.Plan(ctx, (nx, ny, nz), cap)
+        buf = S.Buffers(plan)
+        S.run_extract(plan, vol, buf, stream)
+        return ctx, plan, buf
+
+    def inliers(ga, gb, da, db, kind):
+        idx = S.match(da, db, kind, stream)[0]
+        res, inl = S.hough(ga, gb, idx, hp, stream=stream)
+        G_A, G_B, I = ga.cpu().numpy().astype(np.float64), gb.cpu().numpy().astype(np.float64), idx.cpu().numpy()
+        true = np.linalg.norm(s_true * G_A[:, :3] @ R_true.T + t_true - G_B[I, :3], axis=1) <= 2.0 * G_B[I, 3] + 2.5 * s_true
+        flags = inl.cpu().numpy().astype(bool)
+        return {"inliers": int(res["n_inliers"]), "true_inliers": int((flags & true).sum()),
+                "true_matches": int(true.sum())}
+
+    out = {"pair": "145x174x145 brain-like phantom vs its copy rotated 8 degrees, scaled 1.08, smoothly warped "
+                   "by up to 2.5 voxels, fresh noise sd 0.03",
+           "sigma_b": list(SIGMA_B_SWEEP), "brief": {}, "rrief": {}}
+    t0 = time.time()
+    for method in (1, 2, 3, 4, 5):
+        out["brief"][method], out["rrief"][method] = [], []
+        for sb in SIGMA_B_SWEEP:
+            params = S.default_params(brief_method=method, brief_blur=sb)
+            (_, pa, ba), (_, pb, bb) = extract(params, dA), extract(params, dB)
+            ua = S.units(ba.kp, ba.count, cap, desc=ba.brief, stream=stream)
+            ub = S.units(bb.kp, bb.count, cap, desc=bb.brief, stream=stream)
+            ra = S.units(ba.kp, ba.count, cap, desc=ba.rrief, stream=stream)
+            rb = S.units(bb.kp, bb.count, cap, desc=bb.rrief, stream=stream)
+            out["brief"][method].append(inliers(ua[1], ub[1], ua[2], ub[2], S.MATCH_BRIEF)["inliers"])
+            out["rrief"][method].append(inliers(ra[1], rb[1], ra[2], rb[2], S.MATCH_RANKS)["inliers"])
+            del pa, ba, pb, bb, ua, ub, ra, rb
+    # SIFT-Rank, upright and oriented (independent of the pair method)
+    (_, pa, ba), (_, pb, bb) = extract(S.default_params(), dA), extract(S.default_params(), dB)
+    ua = S.units(ba.kp, ba.count, cap, desc=ba.siftrank, stream=stream)
+    ub = S.units(bb.kp, bb.count, cap, desc=bb.siftrank, stream=stream)
+    out["siftrank_upright"] = inliers(ua[1], ub[1], ua[2], ub[2], S.MATCH_RANKS)
+    oriented = []
+    for plan, buf in ((pa, ba), (pb, bb)):
+        nf = torch.zeros(cap, dtype=torch.int32, device="cuda")
+        fr = torch.zeros(cap, 4, 9, dtype=torch.float32, device="cuda")
+        sr = torch.zeros(cap, 4, 64, dtype=torch.uint8, device="cuda")
+        plan.orient(buf.ws, buf.kp, buf.count, nf, fr, sr, stream=stream)
+        u = S.units(buf.kp, buf.count, cap, nf, fr, sr, stream=stream)
+        oriented.append((u[1], u[2].reshape(len(u[2]), 64)))
+    out["siftrank_oriented"] = inliers(oriented[0][0], oriented[1][0], oriented[0][1], oriented[1][1], S.MATCH_RANKS)
+    out["keypoints"] = [int(ba.count.item()), int(bb.count.item())]
+    out["seconds"] = round(time.time() - t0, 1)
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_vs_plain(steps, stream, extra):
     """32 mixed-size volumes (each axis U{96..192}): one batch-plan call per step
     against 32 one-volume calls per step. Inputs resident in HBM."""
@@ -735,12 +813,14 @@ def main():
         del keep
         torch.cuda.empty_cache()
 
-    match = align = None
+    match = align = power = None
     if not args.no_extra:
         match = match_throughput(stream)
         log(f"[bench] match: {match}")
         align = pair_alignment(stream)
         log(f"[bench] alignment: {align}")
+        power = descriptor_power(stream)
+        log(f"[bench] descriptor power: {power}")
 
     batch = None
     if not args.no_batch:
@@ -795,6 +875,7 @@ def main():
         "serve": serve,
         "match": match,
         "alignment": align,
+        "descriptor_power": power,
         "box": box,
         "cpu_baseline": cpu,
         "paper_context": "paper: 1.4 s CPU, 0.2 s GPU per 145x174x145 volume (~3000 keypoints, hardware unnamed)",

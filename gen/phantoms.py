@@ -31,7 +31,9 @@ Recipes (all draws from numpy Generator(PCG64(seed))):
 * ``similarity_copy``: a volume resampled under a known similarity
   transform T(x) = s R x + t (input voxel coordinates, x = (x, y, z)),
   B(y) = A(T^-1(y)) by scipy's cubic-spline affine_transform (outside A:
-  0), optionally with fresh N(0, noise^2) noise. R comes from scipy's
+  0), optionally with fresh N(0, noise^2) noise and a smooth random
+  displacement field (white noise smoothed with scipy's Gaussian filter,
+  scaled to a given largest displacement). R comes from scipy's
   Rotation.from_rotvec(axis * angle); t keeps A's centre at B's centre.
   The stand-in for the paper's pairs of brain volumes: the true
   correspondences are known.
@@ -217,9 +219,13 @@ def _rotation(axis, angle):
 
 
 def similarity_copy(vol: np.ndarray, scale: float = 1.0, axis=(0.3, -0.5, 0.8), angle_deg: float = 20.0,
-                    noise: float = 0.0, seed: int = 7):
+                    noise: float = 0.0, seed: int = 7, warp: float = 0.0, warp_sigma: float = 12.0):
     """(vol_b, s, R, t): vol resampled under T(x) = s R x + t (recipe in the
-    module doc). Shape unchanged; t = c - s R c with c the volume centre."""
+    module doc). Shape unchanged; t = c - s R c with c the volume centre.
+    warp > 0 adds a smooth random displacement u (white noise smoothed with
+    sigma warp_sigma voxels, each component scaled to a largest magnitude of
+    warp voxels): B(y) = A(T^-1(y) + u(y)), a stand-in for the anatomical
+    differences between two subjects on top of the global similarity."""
     nz, ny, nx = vol.shape
     R = _rotation(axis, np.deg2rad(angle_deg))
     s = float(scale)
@@ -229,7 +235,17 @@ def similarity_copy(vol: np.ndarray, scale: float = 1.0, axis=(0.3, -0.5, 0.8), 
     P = np.array([[0, 0, 1], [0, 1, 0], [1, 0, 0]], dtype=np.float64)
     M = P @ (R.T / s) @ P
     off = P @ (-(R.T @ t) / s)
-    out = ndi.affine_transform(vol.astype(np.float64), M, offset=off, order=3, mode="constant", cval=0.0)
+    if warp > 0.0:
+        rng = _rng(seed + 1)
+        z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        coords = np.stack([z, y, x]).reshape(3, -1).astype(np.float64)
+        src = M @ coords + off[:, None]
+        for k in range(3):
+            u = ndi.gaussian_filter(rng.standard_normal((nz, ny, nx)), warp_sigma, mode="wrap")
+            src[k] += warp * u.reshape(-1) / max(np.abs(u).max(), 1e-30)
+        out = ndi.map_coordinates(vol.astype(np.float64), src, order=3, mode="constant", cval=0.0).reshape(nz, ny, nx)
+    else:
+        out = ndi.affine_transform(vol.astype(np.float64), M, offset=off, order=3, mode="constant", cval=0.0)
     if noise > 0.0:
         out = out + _rng(seed).normal(0.0, noise, out.shape)
     return np.ascontiguousarray(out.astype(np.float32)), s, R, t

@@ -299,3 +299,21 @@ def test_hough_ignores_rows_without_a_positive_scale():
     r = O.hough(ga2, gb, np.concatenate([m, m[:3]]), hp)
     assert not r["voted"][30:].any() and not r["inlier"][30:].any()
     assert (r["bin"], r["votes"], r["n_inliers"]) == (ref["bin"], ref["votes"], ref["n_inliers"])
+
+
+def test_similarity_copy_warp_stays_within_its_amplitude():
+    # generator check: with a smooth warp of up to w voxels a blob moves at
+    # most about w from where the similarity alone puts it
+    n = 48
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    c = np.array([24.0, 22.0, 25.0])
+    A = np.exp(-((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) / (2 * 3.0 ** 2)).astype(np.float32)
+    B0, s, R, t = P.similarity_copy(A, scale=1.1, angle_deg=10.0)
+    Bw, _, _, _ = P.similarity_copy(A, scale=1.1, angle_deg=10.0, warp=2.0, warp_sigma=6.0)
+    def centroid(V):
+        w = V.astype(np.float64)
+        m = w > 0.5 * w.max()
+        return np.array([(x * w)[m].sum(), (y * w)[m].sum(), (z * w)[m].sum()]) / w[m].sum()
+    assert np.linalg.norm(centroid(B0) - (s * R @ c + t)) < 0.2
+    d = np.linalg.norm(centroid(Bw) - centroid(B0))
+    assert 0.05 < d < 2.0 * 1.1 * np.sqrt(3)
