@@ -23,6 +23,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle.hough import _inliers as oracle_inliers
 from gen import phantoms as P
 from tests.helpers import gpu_extract
 
@@ -184,6 +185,42 @@ def test_hough_large_scene_matches_oracle_and_repeats():
     again = _gpu_hough(ga, gb, m, hp)
     assert again[0]["bin"] == res["bin"] and again[0]["scale"] == res["scale"]
     assert np.array_equal(again[0]["R"], res["R"]) and np.array_equal(again[1], inl)
+
+
+
+def test_hough_maximum_size_on_sampled_matches():
+    """n_a = 2^21, the largest the entry point accepts: the planted
+    similarity is recovered, and on 4000 sampled valid matches each inlier
+    flag equals the oracle's inlier rule applied to the GPU's transform (a
+    full oracle vote at this size would take minutes)."""
+    import paper_2112_10258_amd as S
+    from scipy.spatial.transform import Rotation
+    n = 1 << 21
+    n_true = 1 << 15
+    ga, gb, m, truth = P.hough_scene(n_true, n - n_true, seed=37)
+    hp = S.hough_default_params((145, 174, 145))
+    _say(f"maximum size: {n} matches, workspace {S.hough_workspace_bytes(n) / 2**30:.2f} GiB")
+    res, inl = _gpu_hough(ga, gb, m, hp)
+    _say(f"maximum size: votes {res['votes']}, fit {res['n_fit']}, inliers {res['n_inliers']}, "
+         f"scale {res['scale']:.5f}")
+    assert res["status"] == 1
+    assert abs(res["scale"] / truth["s"] - 1.0) < 0.01
+    err = Rotation.from_matrix(res["R"] @ truth["R"].T).magnitude()
+    assert np.degrees(err) < 0.5, np.degrees(err)
+    assert int(inl.sum()) == res["n_inliers"]
+    # the true pairs are the first n_true rows of A
+    assert inl[:n_true].mean() >= 0.99
+    # a random pair passes both inlier tests with probability about 1e-3
+    assert res["n_inliers"] <= n_true + (n - n_true) // 200
+    rng = np.random.default_rng(38)
+    pick = np.sort(rng.choice(n, 4000, replace=False))
+    pick = np.concatenate([np.arange(200), pick[pick >= 200]])
+    valid = np.ones(len(pick), dtype=bool)
+    ref, mg = oracle_inliers(ga[pick], gb, m[pick], valid, res["scale"], np.asarray(res["R"]), np.asarray(res["t"]),
+                         _oracle_hp(hp))
+    keep = mg >= DECISION_MARGIN
+    assert keep.sum() >= 0.99 * len(pick)
+    assert np.array_equal(inl[pick][keep], ref[keep])
 
 
 # ------------------------------------------------------------ units
