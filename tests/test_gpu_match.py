@@ -90,3 +90,29 @@ def test_match_rank_rows_with_many_ties_and_extreme_bytes(m):
     B = pool[rng.integers(0, 40, n_b)]
     _same(A, B, S.MATCH_RANKS, ("pool", m))
     print(f"[match] ranks {m}: pool rows with ties ok", flush=True)
+
+
+def test_match_at_benchmark_size_on_sampled_rows():
+    """16384 x 16384, the size the benchmark times (64-element rank vectors
+    as random permutations, 4-word BRIEF rows): every A row is matched on
+    the GPU; sampled rows (the first, the last, and random ones) equal the
+    oracle's brute force exactly."""
+    import paper_2112_10258_amd as S
+    n = 16384
+    rng = np.random.default_rng(2112)
+    cases = (
+        (S.MATCH_RANKS, np.argsort(rng.random((n, 64)), axis=1).astype(np.uint8),
+         np.argsort(rng.random((n, 64)), axis=1).astype(np.uint8), 300),
+        (S.MATCH_BRIEF, rng.integers(-2 ** 63, 2 ** 63 - 1, size=(n, 4), dtype=np.int64),
+         rng.integers(-2 ** 63, 2 ** 63 - 1, size=(n, 4), dtype=np.int64), 60),
+    )
+    for kind, A, B, n_pick in cases:
+        got = _gpu_match(A, B, kind)
+        pick = np.unique(np.concatenate([[0, n - 1], rng.choice(n, n_pick, replace=False)]))
+        sub = A[pick]
+        want = O.match_nn(sub.view(np.uint64) if kind == S.MATCH_BRIEF else sub,
+                          B.view(np.uint64) if kind == S.MATCH_BRIEF else B, kind)
+        for g, w, name in zip(got, want, ("idx", "d1", "d2")):
+            assert np.array_equal(g[pick].astype(np.int64), w), (kind, name)
+        assert got[0].min() >= 0 and got[0].max() < n
+        assert np.all(got[1] <= got[2])
