@@ -11,7 +11,9 @@ times.
   - every pre-blurred level B_s equals the oracle's blur of the GPU's G_s;
   - the oracle's detection on the GPU's D levels gives the same keypoints;
   - the descriptors of every keypoint match the oracle's on the GPU's G
-    levels under the near-tie margins.
+    levels under the near-tie margins;
+  - dominant orientations and oriented SIFT-Rank of 3000 sampled keypoints
+    match the oracle's on the GPU's G levels.
 Config 3 (32 volumes, each axis U{96..192}, one batch plan): four of the
 volumes against the oracle (end-to-end levels, stage-wise detection and
 descriptors), and every volume equal to the plain path bit for bit.
@@ -99,6 +101,39 @@ def test_config4_whole_level_parity():
     sr_rows = int(np.sum(np.any(res["siftrank"] != d["siftrank"], axis=1)))
     _say(f"descriptors of all {len(got)} keypoints match (siftrank rows differing {sr_rows}, "
          f"brief bits differing {int((gb != ob).sum())})")
+    # dominant orientations and oriented SIFT-Rank (sift3d_orient, beside the
+    # step) at the same size: sampled keypoints against the oracle on the
+    # GPU's G levels, under the orientation contract (frames within 1e-6,
+    # ranks up to near-ties, decisions within 1e-9 counted and rare)
+    n_kp = len(got)
+    K = S.MAX_ORIENTATIONS
+    nf = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+    fr = torch.full((cap, K, 9), 7.0, dtype=torch.float32, device="cuda")
+    osr = torch.full((cap, K, 64), 255, dtype=torch.uint8, device="cuda")
+    plan.orient(buf.ws, buf.kp, buf.count, nf, fr, osr, 0.8)
+    torch.cuda.synchronize()
+    nf = nf[:n_kp].cpu().numpy()
+    fr = fr[:n_kp].cpu().numpy().reshape(n_kp, K, 3, 3)
+    osr = osr[:n_kp].cpu().numpy()
+    rng = np.random.default_rng(4)
+    pick = np.unique(np.concatenate([[0, n_kp - 1], rng.choice(n_kp, min(3000, n_kp), replace=False)]))
+    ref = O.orientations(G64, got[pick], p, tau=0.8, kmax=K)
+    excused = 0
+    for j, i in enumerate(pick):
+        if ref["margin"][j] < 1e-9:
+            excused += 1
+            continue
+        assert nf[i] == ref["nframes"][j], (i, nf[i], ref["nframes"][j])
+        for f in range(nf[i]):
+            np.testing.assert_allclose(fr[i, f], ref["frames"][j, f], atol=1e-6, err_msg=f"kp {i} frame {f}")
+            h = ref["hist"][j, f]
+            assert rank_mismatch_excused(h, osr[i, f], ref["rank"][j, f], MARGIN * max(h.max(), 1e-300)), (i, f)
+        for f in range(nf[i], K):
+            assert not fr[i, f].any() and not osr[i, f].any(), (i, f)
+    assert np.all((nf >= 0) & (nf <= K))
+    assert excused <= max(2, len(pick) // 50), excused
+    _say(f"orientations of {len(pick)} sampled keypoints match ({excused} under the decision margin), "
+         f"frames per keypoint over all {n_kp}: {np.bincount(nf, minlength=K + 1).tolist()}")
 
 
 def _batch_volume(plan, buf, v, draws):
