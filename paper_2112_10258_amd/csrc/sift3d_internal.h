@@ -74,8 +74,10 @@ constexpr int kScanThreads = 1024;
 // Strict-extremum path (votes == 80): one wavefront per (62 output x plus
 // a halo lane on each side, kDTWY consecutive y rows, kDTZ planes); 4
 // wavefronts (kDTY = 4 kDTWY consecutive rows) per block. Mask word t of a
-// row covers x = 62 t + bit.
-constexpr int kDTXOut = 62, kDTWY = 2, kDTY = 4 * kDTWY, kDTZ = 16;
+// row covers x = 62 t + bit. kDTZ + 2 planes per wavefront is a multiple of
+// the plane loop's unroll (6); 28 re-reads fewer halo planes than 16 and
+// still leaves thousands of blocks on the large octaves.
+constexpr int kDTXOut = 62, kDTWY = 2, kDTY = 4 * kDTWY, kDTZ = 28;
 constexpr int kRowBlock = 256;              // rows per count / emit block; volumes start on a block
 
 // ---------------------------------------------------------------- device tables
